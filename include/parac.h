@@ -1,0 +1,210 @@
+/*
+ * parac.h -- C ABI of the MI355X (gfx950) ParAC library: randomized
+ * approximate-Cholesky preconditioning of graph-Laplacian and SDDM systems,
+ * scheduled by dynamic dependency tracking, and the PCG solve that applies it.
+ *
+ * The method (arXiv 2505.02977):
+ *   - the system is L x = b with L a graph Laplacian (eq. (1), Definition of
+ *     §II-A) or an SDDM matrix, which is factored through the augmented
+ *     Laplacian with a ground vertex (§V methodology);
+ *   - the factor is L ~= F D F^T with F unit lower triangular and D diagonal
+ *     (§IV), built by the rchol elimination (Alg. 1) whose clique update is
+ *     replaced by the sampled spanning tree of Alg. 2;
+ *   - pivots are scheduled by the dependency counters d(i) of §III: a vertex
+ *     is ready when it has no lower-labelled active neighbour;
+ *   - the factor preconditions conjugate gradients to a relative residual
+ *     (§V methodology).
+ *
+ * Conventions for every call:
+ *   - all calls return a parac_status (0 = success, negative = error) and
+ *     never abort or throw across the ABI; parac_last_error() returns a
+ *     thread-local message describing the last failure;
+ *   - "device pointer" means memory on the current HIP device; "host
+ *     pointer" means ordinary host memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls are stream-ordered and return after the work they describe has
+ *     completed unless stated otherwise;
+ *   - vertex labels: perm[v] is the elimination label of original vertex v;
+ *     the factor lives in label space.  In SDDM mode the ground vertex takes
+ *     the last label n.
+ */
+#ifndef PARAC_H
+#define PARAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int parac_status;
+
+#define PARAC_OK 0
+#define PARAC_EINVAL (-1)        /* malformed CSR, permutation or options   */
+#define PARAC_ENOTLAP (-2)       /* positive off-diagonal / negative excess */
+#define PARAC_EPOOL (-3)         /* fill pool exhausted (retried inside)    */
+#define PARAC_ENOMEM (-4)        /* device allocation failed                */
+#define PARAC_ETIMEOUT (-5)      /* elimination watchdog expired            */
+#define PARAC_EDEVICE (-6)       /* HIP runtime error                       */
+#define PARAC_EINCONSISTENT (-7) /* b has a component along a null vector  */
+#define PARAC_ENOCONV (-8)       /* PCG reached maxit                       */
+#define PARAC_EINTERNAL (-9)     /* a scheduler invariant failed            */
+
+#define PARAC_MODE_AUTO 0
+#define PARAC_MODE_LAPLACIAN 1
+#define PARAC_MODE_SDDM 2
+
+#define PARAC_PREC_FP64 0  /* preconditioner apply in FP64               */
+#define PARAC_PREC_MIXED 1 /* apply in FP32 from an FP32 copy of F, D^+;
+                              SpMV, residuals, dots, alpha/beta in FP64 */
+
+/* A symmetric matrix in CSR form, full (both triangles and the diagonal),
+ * columns strictly increasing within each row.  Sign convention of §V:
+ * positive diagonal, non-positive off-diagonals; a positive row excess
+ * a_ii - sum_{j!=i} |a_ij| makes the matrix SDDM. */
+typedef struct {
+  int64_t n;              /* order                                          */
+  int64_t nnz;            /* stored entries                                 */
+  const int64_t *rowptr;  /* [n+1]                                          */
+  const int32_t *col;     /* [nnz]                                          */
+  const double *val;      /* [nnz]                                          */
+  int32_t on_device;      /* 1: the three arrays are device pointers;
+                             0: host pointers (copied in by the call)       */
+} parac_csr;
+
+typedef struct {
+  uint64_t seed;          /* key of the counter-based sampler (Alg. 2 draws) */
+  const int32_t *perm;    /* [n] perm[v] = label; NULL = identity.  Device
+                             pointer iff the matrix is on the device.      */
+  int32_t mode;           /* PARAC_MODE_*                                  */
+  double pool_factor;     /* fill-pool capacity in records per stored entry
+                             of L (default 4.0, as in §IV-A); doubled and
+                             retried automatically on exhaustion            */
+  int32_t workers;        /* persistent waves (0 = all that fit)            */
+  int32_t keep_fp32;      /* also build the FP32 copy used by MIXED apply   */
+  double timeout_s;       /* elimination watchdog (0 = 30 s)                */
+} parac_factor_opts;
+
+typedef struct {
+  int64_t n, ntot;        /* order; order incl. ground vertex               */
+  int32_t mode;           /* resolved mode                                  */
+  int64_t nnz_off;        /* strictly-lower entries of F                    */
+  int64_t n_input_edges;  /* undirected edges of the (augmented) graph      */
+  int64_t n_fill;         /* sampled fill records                           */
+  int64_t max_gather;     /* largest gathered neighbourhood                 */
+  int64_t max_deg;        /* largest merged neighbourhood d_k               */
+  int64_t depth;          /* levels of the elimination dependency DAG       */
+  int64_t n_zero_pivots;  /* D_k = 0 (one per connected component)          */
+  int32_t workers;        /* persistent waves used                          */
+  int32_t retries;        /* pool-exhaustion retries                        */
+  double pool_factor;     /* pool factor of the successful attempt          */
+  double ms_setup;        /* relabel, upper adjacency, counters, queue      */
+  double ms_eliminate;    /* the persistent elimination kernel              */
+  double ms_finalize;     /* canonical CSC, CSR, levels, D^+, FP32 copy     */
+  double ms_total;        /* whole call on the stream                       */
+} parac_factor_stats;
+
+typedef struct parac_factor_s *parac_factor_t;
+
+/* Build L ~= F D F^T (Alg. 1/2 scheduled by §III; scaled form of §IV).
+ *   A     matrix, borrowed for the duration of the call
+ *   o     options (NULL = defaults)
+ *   out   receives a handle that owns all device memory of the factor
+ * Errors: EINVAL (bad CSR, asymmetry, bad permutation), ENOTLAP, ENOMEM,
+ * ETIMEOUT, EDEVICE, EINTERNAL.  EPOOL is handled by retrying with a larger
+ * pool; the factor is identical bit for bit whatever the pool size. */
+parac_status parac_factor(const parac_csr *A, const parac_factor_opts *o,
+                          void *stream, parac_factor_t *out);
+
+/* Sizes and statistics of a factor (host struct, caller-owned). */
+parac_status parac_factor_info(parac_factor_t f, parac_factor_stats *s);
+
+/* Copy the factor to caller-allocated host arrays: canonical CSC of F in
+ * label space (colptr[ntot+1], rowind[nnz_off] rows ascending,
+ * val[nnz_off]), D[ntot], and level[ntot] (longest dependency chain ending
+ * at each label).  Any pointer may be NULL to skip it. */
+parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
+                                 int32_t *rowind, double *val, double *D,
+                                 int32_t *level);
+
+/* z = M^+ r with M = P^T F D F^T P (SDDM: ground row/column dropped, §V).
+ *   r, z       device pointers, original vertex order, n x nrhs row-major
+ *   precision  PARAC_PREC_FP64, or PARAC_PREC_MIXED (needs keep_fp32)
+ * The forward solve F y = P r and the backward solve F^T x = D^+ y run as
+ * level-ordered sync-free triangular solves.  Errors: EINVAL. */
+parac_status parac_apply(parac_factor_t f, const double *r, double *z,
+                         int64_t nrhs, int32_t precision, void *stream);
+
+typedef struct {
+  double rtol;            /* stop when ||r_k|| <= rtol ||b|| (default 1e-6) */
+  int32_t maxit;          /* SpMV cap (default 10000)                       */
+  int32_t precision;      /* PARAC_PREC_*                                   */
+  int32_t check_every;    /* iterations between host convergence checks
+                             (0 = 8)                                        */
+} parac_pcg_opts;
+
+typedef struct {
+  int32_t status;         /* per right-hand side                            */
+  int32_t iterations;     /* SpMVs performed                                */
+  double relres;          /* recursive ||r||/||b|| at exit                  */
+  double true_relres;     /* ||b - A x||/||b|| recomputed in FP64           */
+} parac_pcg_stats;
+
+/* Preconditioned conjugate gradients with x0 = 0 (§V methodology; the
+ * textbook recurrence).  With nrhs > 1 the columns run as independent
+ * recurrences in one block launch sequence (matrix and factor read once per
+ * iteration for all columns).
+ *   A      the matrix the factor was built from (device arrays)
+ *   b, x   device pointers, n x nrhs row-major; x is output only
+ *   st     host array of nrhs stats (may be NULL)
+ * Errors: EINCONSISTENT (Laplacian component with nonzero sum of b),
+ * ENOCONV (x holds the last iterate), EINVAL. */
+parac_status parac_pcg(const parac_csr *A, parac_factor_t f, const double *b,
+                       double *x, int64_t nrhs, const parac_pcg_opts *o,
+                       parac_pcg_stats *st, void *stream);
+
+/* One system of a serving stream. */
+typedef struct {
+  parac_csr A;            /* host arrays                                    */
+  const int32_t *perm;    /* host, [n]                                      */
+  const double *b;        /* host, [n]                                      */
+  double *x;              /* host, [n] output (caller-owned)                */
+  uint64_t seed;
+  double rtol;
+  double arrival_s;       /* arrival time relative to the call's start      */
+} parac_request;
+
+typedef struct {
+  int32_t status;
+  int32_t iterations;
+  double true_relres;
+  double t_arrive, t_admit, t_done;  /* seconds from the call's start       */
+  int64_t bytes_resident;            /* device footprint while admitted     */
+} parac_result;
+
+typedef struct {
+  size_t hbm_budget;      /* bytes the stream may hold resident (0 = 80% of
+                             free device memory)                            */
+  int32_t max_slots;      /* concurrently admitted systems (0 = 32)         */
+  int32_t precision;      /* PARAC_PREC_* for the batched PCG               */
+  int32_t maxit;          /* per system (0 = 10000)                         */
+} parac_serve_opts;
+
+/* Continuous-batching serving loop: requests are admitted in arrival order
+ * as slots and device memory allow, factored on arrival, and their PCG
+ * iterations advance together in batched launches across all admitted
+ * systems; results are copied to the caller's x as each system converges.
+ * Errors: EINVAL for bad options; per-request failures (e.g. ENOMEM for a
+ * system larger than the budget) are reported in out[i].status. */
+parac_status parac_serve(const parac_request *reqs, int64_t n,
+                         const parac_serve_opts *o, parac_result *out);
+
+void parac_factor_free(parac_factor_t f);
+const char *parac_status_str(parac_status s);
+const char *parac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARAC_H */

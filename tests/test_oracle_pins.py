@@ -1,0 +1,511 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each checks the oracle
+against an independent source -- a value the paper prints (Fig. 1 trace), a
+closed form (exact Schur complement on degree-2 pivots; unbiasedness
+E[F D F^T] = L by exact enumeration), a library routine (numpy's Philox,
+numpy's dense pseudo-inverse), brute force, or an invariant the paper states.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2505_02977_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lap(n, i, j, w, excess=None):
+    return inputs.laplacian_from_edges(n, i, j, w, excess)
+
+
+def permuted_dense(A, perm, ntot=None, excess=None):
+    """P L P^T (label space); with ``excess`` the augmented Laplacian with the
+    ground vertex at label n."""
+    n = A.n
+    L = A.to_dense()
+    if excess is not None:
+        La = np.zeros((n + 1, n + 1))
+        La[:n, :n] = L
+        La[:n, n] = -excess
+        La[n, :n] = -excess
+        La[n, n] = excess.sum()
+        L = La
+        n = n + 1
+        perm = np.concatenate([perm, [n - 1]])
+    out = np.zeros_like(L)
+    out[np.ix_(perm, perm)] = L
+    return out
+
+
+def fdft(f):
+    F = f.dense_F()
+    return F @ np.diag(f.D) @ F.T
+
+
+# ----------------------------------------------------------------------------
+# T8: Philox4x64-10 against numpy's independent implementation
+# ----------------------------------------------------------------------------
+def test_philox_matches_numpy(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        ctr = [int(x) for x in rng.integers(1, 2**63, 4, dtype=np.uint64)]
+        key = [int(x) for x in rng.integers(0, 2**63, 2, dtype=np.uint64)]
+        ctr[1] = int(rng.integers(0, 2**40))
+        # numpy's bit generator increments its 256-bit counter before each
+        # block, so it is seeded one below the counter under test
+        g = np.random.Philox(counter=np.array([ctr[0] - 1, ctr[1], ctr[2], ctr[3]], np.uint64),
+                             key=np.array(key, np.uint64))
+        ref = [int(g.random_raw()) for _ in range(4)]
+        got = [int(x) for x in orc.philox4x64_10(ctr, key)]
+        assert got == ref
+
+
+# ----------------------------------------------------------------------------
+# R1: input classification
+# ----------------------------------------------------------------------------
+def test_classify_modes_and_errors(orc):
+    i, j = inputs.path_edges(5)
+    A = lap(5, i, j, np.array([1.0, 2.0, 3.0, 4.0]))
+    st, mode, ex = orc.classify(A)
+    assert st == orc.OK and mode == orc.MODE_LAPLACIAN and np.all(ex == 0)
+    S = lap(5, i, j, np.array([1.0, 2.0, 3.0, 4.0]), excess=np.array([0.5, 0, 0, 0, 0.25]))
+    st, mode, ex = orc.classify(S)
+    assert st == orc.OK and mode == orc.MODE_SDDM
+    assert ex[0] == pytest.approx(0.5, rel=1e-15) and ex[4] == pytest.approx(0.25, rel=1e-15)
+    assert orc.classify(S, orc.MODE_LAPLACIAN)[0] == orc.ENOTLAP
+    # positive off-diagonal
+    B = lap(5, i, j, np.ones(4))
+    B.val = B.val.copy()
+    B.val[1] = 0.5
+    assert orc.classify(B)[0] == orc.ENOTLAP
+    # asymmetric
+    C = lap(5, i, j, np.ones(4))
+    C.val = C.val.copy()
+    C.val[1] = -0.75   # a_01; a_10 stays -1
+    C.val[0] = 0.75    # keep row 0's sum so only symmetry breaks
+    assert orc.classify(C)[0] == orc.EINVAL
+    # negative excess
+    Dm = lap(5, i, j, np.ones(4))
+    Dm.val = Dm.val.copy()
+    Dm.val[0] = 0.5
+    assert orc.classify(Dm)[0] == orc.ENOTLAP
+    # unsorted columns
+    E = lap(5, i, j, np.ones(4))
+    E.col = E.col.copy()
+    E.col[[0, 1]] = E.col[[1, 0]]
+    assert orc.classify(E)[0] == orc.EINVAL
+    # bad permutation
+    f = orc.factor(A, perm=np.array([0, 1, 2, 3, 3]))
+    assert f.status == orc.EINVAL
+
+
+# ----------------------------------------------------------------------------
+# T1: the worked dependency trace of Fig. 1
+# ----------------------------------------------------------------------------
+def test_fig1_trace(orc):
+    g = json.load(open(os.path.join(GOLDEN, "fig1_trace.json")))
+    e = np.array(g["edges"])
+    # ascending weights 0-1 < 0-3 < 0-4 < 0-5 put 5 last in vertex 0's
+    # sampling order; forcing the last candidate at every slot realises the
+    # sampled tree of the figure
+    wmap = {(0, 1): 1.0, (0, 3): 2.0, (0, 4): 3.0, (0, 5): 4.0, (2, 5): 1.5}
+    w = np.array([wmap[(min(a, b), max(a, b))] for a, b in e])
+    A = lap(g["n"], e[:, 0], e[:, 1], w)
+    f = orc.factor(A, forced=[2, 1, 0], trace=True)
+    assert f.status == orc.OK
+    tr = f.trace
+    init_d = [int(r[2]) for r in tr if r[0] == orc.EV_INIT_DP]
+    assert init_d == g["initial_d"]
+    q0 = [int(r[1]) for r in tr if r[0] == orc.EV_ENQ][: len(g["initial_queue"])]
+    assert sorted(q0) == g["initial_queue"]
+    # events of the first elimination
+    claims = np.where(tr[:, 0] == orc.EV_CLAIM)[0]
+    assert tr[claims[0], 1] == g["pivot"]
+    ev = tr[claims[0] + 1: claims[1]]
+    ins = [r for r in ev if r[0] == orc.EV_INSERT]
+    tree = sorted(sorted((int(r[1]), int(r[2]))) for r in ins)
+    assert tree == sorted(sorted(t) for t in g["sampled_tree"])
+    assert int(ins[-1][3]) == g["d5_after_insertions"]
+    # insertions strictly precede deletions
+    kinds = [int(r[0]) for r in ev if r[0] in (orc.EV_INSERT, orc.EV_DEC)]
+    assert kinds == sorted(kinds)
+    dec = {int(r[1]): int(r[3]) for r in ev if r[0] == orc.EV_DEC}
+    for v, dv in enumerate(g["d_after_deletions"]):
+        if dv is not None and v in dec:
+            assert dec[v] == dv
+    enq = sorted(int(r[1]) for r in ev if r[0] == orc.EV_ENQ)
+    assert enq == g["enqueued"]
+    assert all(v not in enq for v in g["not_enqueued"])
+
+
+# ----------------------------------------------------------------------------
+# T2: degree-2 pivots are exact (the sampled edge is the Schur complement)
+# ----------------------------------------------------------------------------
+def exact_check(orc, A, perm, seed, excess=None):
+    f = orc.factor(A, perm=perm, seed=seed)
+    assert f.status == orc.OK
+    ref = permuted_dense(A, perm, excess=excess)
+    got = fdft(f)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    return f
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 40])
+def test_paths_and_cycles_exact(orc, n):
+    rng = np.random.default_rng(n)
+    for kind in ("path", "cycle"):
+        if kind == "cycle" and n < 3:
+            continue
+        i, j = inputs.path_edges(n) if kind == "path" else inputs.cycle_edges(n)
+        w = rng.uniform(0.1, 10.0, len(i))
+        A = lap(n, i, j, w)
+        for trial in range(3):
+            perm = rng.permutation(n).astype(np.int32)
+            f = exact_check(orc, A, perm, seed=trial)
+            assert f.stats["max_deg"] <= 2
+            b = inputs.rhs(n, rng)
+            x, st = orc.pcg(A, f, b, rtol=1e-10)
+            assert st["status"] == 0 and st["iterations"] == 1
+            assert st["true_relres"] < 1e-12
+
+
+def test_tree_leaf_first_exact(orc):
+    rng = np.random.default_rng(7)
+    n = 60
+    i, j = inputs.random_tree_edges(n, rng)
+    A = lap(n, i, j, rng.uniform(0.5, 2.0, len(i)))
+    # child v > parent(v) in a recursive tree: eliminating in reverse vertex
+    # order removes leaves first, so every pivot has exactly one neighbour
+    perm = (n - 1 - np.arange(n)).astype(np.int32)
+    f = exact_check(orc, A, perm, seed=3)
+    assert f.stats["max_deg"] == 1 and f.stats["n_fill"] == 0
+    x, st = orc.pcg(A, f, inputs.rhs(n, rng), rtol=1e-10)
+    assert st["iterations"] == 1
+
+
+def test_sddm_path_exact(orc):
+    rng = np.random.default_rng(11)
+    n = 30
+    i, j = inputs.path_edges(n)
+    ex = np.zeros(n)
+    ex[0], ex[-1] = 0.7, 1.3         # augmented graph is a cycle through ground
+    A = lap(n, i, j, rng.uniform(0.5, 2.0, n - 1), excess=ex)
+    perm = rng.permutation(n).astype(np.int32)
+    f = exact_check(orc, A, perm, seed=5, excess=ex)
+    assert f.mode == orc.MODE_SDDM and f.ntot == n + 1
+    assert f.D[n] == 0.0 and f.stats["n_zero_pivots"] == 1
+    b = rng.standard_normal(n)
+    x, st = orc.pcg(A, f, b, rtol=1e-10)
+    assert st["iterations"] == 1 and st["true_relres"] < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# T3: unbiasedness E[F D F^T] = L by exact enumeration of sampling outcomes
+# ----------------------------------------------------------------------------
+def enumerate_expectation(orc, A, perm, limit=200000):
+    """Sum P(path) F D F^T over every sequence of sampling choices.  Each run
+    of the oracle with a forced prefix completes it with first candidates and
+    logs every slot's option count and the probability of the pick taken."""
+    total, ptot, paths = None, 0.0, 0
+    stack = [[]]
+    while stack:
+        prefix = stack.pop()
+        f = orc.factor(A, perm=perm, forced=prefix)
+        assert f.status == orc.OK
+        picks = list(f.choice_pick)
+        for pos in range(len(prefix), len(picks)):
+            for alt in range(1, int(f.choice_nopt[pos])):
+                stack.append(picks[:pos] + [alt])
+        p = float(np.prod(f.choice_prob)) if len(picks) else 1.0
+        M = p * fdft(f)
+        total = M if total is None else total + M
+        ptot += p
+        paths += 1
+        assert paths <= limit
+    return total, ptot, paths
+
+
+@pytest.mark.parametrize("case", ["fig1", "k4", "grid3x3", "cycle6_chord", "k5_sddm"])
+def test_unbiased_exact_enumeration(orc, case):
+    rng = np.random.default_rng(["fig1", "k4", "grid3x3", "cycle6_chord", "k5_sddm"].index(case))
+    excess = None
+    if case == "fig1":
+        e = np.array([[0, 4], [0, 3], [0, 1], [0, 5], [5, 2]])
+        n, i, j = 6, e[:, 0], e[:, 1]
+    elif case == "k4":
+        n = 4
+        i, j = inputs.complete_edges(4)
+    elif case == "grid3x3":
+        n = 9
+        i, j = inputs.grid2d_edges(3, 3)
+    elif case == "cycle6_chord":
+        n = 6
+        i, j = inputs.cycle_edges(6)
+        i, j = np.concatenate([i, [0]]), np.concatenate([j, [3]])
+    else:
+        n = 5
+        i, j = inputs.complete_edges(5)
+        excess = np.array([0.3, 0.0, 0.9, 0.0, 0.2])
+    w = rng.uniform(0.2, 3.0, len(i))
+    A = lap(n, i, j, w, excess)
+    # random order, except that a vertex of largest degree goes first so the
+    # first pivot really samples (Fig. 1 keeps its own labels)
+    perm = (np.arange(n) if case == "fig1" else rng.permutation(n)).astype(np.int32)
+    hub = int(np.argmax(np.diff(A.rowptr)))
+    first = int(np.where(perm == 0)[0][0])
+    perm[[hub, first]] = perm[[first, hub]]
+    E, ptot, paths = enumerate_expectation(orc, A, perm)
+    ref = permuted_dense(A, perm, excess=excess)
+    assert paths > 1
+    assert abs(ptot - 1.0) < 1e-12
+    assert np.max(np.abs(E - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_biased_mistake_is_caught(orc):
+    """A planted mistake (a uniform partner instead of the weighted one) is
+    visible to the enumeration: its expectation misses L."""
+    n = 4
+    i, j = inputs.complete_edges(4)
+    w = np.array([0.3, 1.0, 2.5, 0.7, 1.9, 0.4])
+    A = lap(n, i, j, w)
+    perm = np.arange(n, dtype=np.int32)
+    total = None
+    stack = [[]]
+    while stack:
+        prefix = stack.pop()
+        f = orc.factor(A, perm=perm, forced=prefix)
+        picks = list(f.choice_pick)
+        for pos in range(len(prefix), len(picks)):
+            for alt in range(1, int(f.choice_nopt[pos])):
+                stack.append(picks[:pos] + [alt])
+        p = float(np.prod(1.0 / f.choice_nopt.astype(float)))  # wrong law
+        M = p * fdft(f)
+        total = M if total is None else total + M
+    assert np.max(np.abs(total - A.to_dense())) > 1e-3
+
+
+def test_unbiased_monte_carlo(orc):
+    """Mean of F D F^T over Philox seeds approaches L at rate ~ M^-1/2."""
+    n = 6
+    i, j = inputs.complete_edges(n)
+    rng = np.random.default_rng(3)
+    A = lap(n, i, j, rng.uniform(0.5, 2.0, len(i)))
+    ref = A.to_dense()
+    errs = []
+    acc = np.zeros((n, n))
+    M = 0
+    for target in (250, 1000, 4000):
+        while M < target:
+            acc += fdft(orc.factor(A, seed=1000 + M))
+            M += 1
+        errs.append(np.max(np.abs(acc / M - ref)) / np.max(np.abs(ref)))
+    assert errs[-1] < 0.03
+    assert errs[-1] < errs[0]
+
+
+# ----------------------------------------------------------------------------
+# T4: per-slot sampling law (chi-square on a weighted star)
+# ----------------------------------------------------------------------------
+def test_sampling_law_chi2(orc):
+    from scipy.stats import chi2
+    w = np.array([0.5, 1.0, 1.7, 2.2, 3.1, 4.0])       # leaves 1..6
+    A = lap(7, np.zeros(6, int), np.arange(1, 7), w)
+    # slot 0 is the lightest leaf (vertex 1); its partner is drawn from the
+    # other five with probability w_v / S_2
+    counts = np.zeros(7)
+    T = 20000
+    for s in range(T):
+        f = orc.factor(A, seed=s, trace=True)
+        tr = f.trace
+        ins = tr[tr[:, 0] == orc.EV_INSERT]
+        first = ins[0]
+        a, b = int(first[1]), int(first[2])
+        partner = b if a == 1 else a
+        counts[partner] += 1
+    p = w[1:] / w[1:].sum()
+    exp = T * p
+    obs = counts[2:7]
+    stat = float(np.sum((obs - exp) ** 2 / exp))
+    assert stat < chi2.ppf(0.999, df=4)
+
+
+# ----------------------------------------------------------------------------
+# T5: structural invariants of the factor
+# ----------------------------------------------------------------------------
+def random_graph(rng, n, extra, sddm=False):
+    i, j = inputs.connected_random_edges(n, extra, rng)
+    w = rng.uniform(0.01, 10.0, len(i))
+    ex = None
+    if sddm:
+        ex = np.zeros(n)
+        hot = rng.choice(n, size=max(1, n // 10), replace=False)
+        ex[hot] = rng.random(len(hot))
+    return lap(n, i, j, w, ex), ex
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_invariants(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(20, 400))
+    A, ex = random_graph(rng, n, int(rng.integers(n, 5 * n)), sddm=seed % 2 == 1)
+    perm = rng.permutation(n).astype(np.int32)
+    f = orc.factor(A, perm=perm, seed=seed)
+    assert f.status == orc.OK
+    ntot = f.ntot
+    d = np.diff(f.colptr)
+    cols = np.repeat(np.arange(ntot), d)
+    assert np.all(f.rowind > cols)                       # strictly lower
+    assert np.all(f.val < 0) and np.all(f.D >= 0)
+    for k in range(ntot):                               # rows ascending
+        seg = f.rowind[f.colptr[k]:f.colptr[k + 1]]
+        assert np.all(np.diff(seg) > 0)
+    # D_k = 0 exactly at the last label of the (single) component
+    assert f.stats["n_zero_pivots"] == 1 and f.D[ntot - 1] == 0.0
+    # column sums of F vanish (Laplacian Schur complements keep zero row sums)
+    cs = np.bincount(cols, weights=f.val, minlength=ntot) + 1.0
+    cs[ntot - 1] -= 1.0
+    assert np.max(np.abs(cs)) <= 64 * np.finfo(float).eps * max(1, d.max())
+    # sizes: nnz(F) = sum d_k; fill = nnz - (n - components) ... one sampled
+    # record per slot p = 1..d_k-1
+    assert f.nnz_off == d.sum()
+    assert f.stats["n_fill"] == int(np.sum(np.maximum(d - 1, 0)))
+    # levels form a valid schedule
+    assert np.all(f.level[f.rowind] >= f.level[cols] + 1)
+    assert f.stats["depth"] == f.level.max() + 1
+
+
+def test_components(orc):
+    """Two components: two zero pivots; consistent b converges; a b with a
+    nonzero component sum is rejected."""
+    rng = np.random.default_rng(4)
+    i1, j1 = inputs.connected_random_edges(30, 40, rng)
+    i2, j2 = inputs.connected_random_edges(20, 25, rng)
+    i = np.concatenate([i1, i2 + 30])
+    j = np.concatenate([j1, j2 + 30])
+    A = lap(50, i, j, rng.uniform(0.5, 2, len(i)))
+    perm = rng.permutation(50).astype(np.int32)
+    f = orc.factor(A, perm=perm, seed=9)
+    assert f.stats["n_zero_pivots"] == 2
+    b = rng.standard_normal(50)
+    b[:30] -= b[:30].mean()
+    b[30:] -= b[30:].mean()
+    x, st = orc.pcg(A, f, b, rtol=1e-10)
+    assert st["status"] == 0 and st["true_relres"] < 1e-9
+    b2 = b.copy()
+    b2[0] += 1.0
+    b2[30] -= 1.0                      # total sum still zero, components not
+    x, st = orc.pcg(A, f, b2)
+    assert st["status"] == orc.EINCONSISTENT
+
+
+# ----------------------------------------------------------------------------
+# T6: schedule invariance (§III distribution preservation, made bitwise by
+# the canonical merge/sort/scan/draw rules)
+# ----------------------------------------------------------------------------
+def same_factor(a, b):
+    return (np.array_equal(a.colptr, b.colptr) and np.array_equal(a.rowind, b.rowind)
+            and np.array_equal(a.val.view(np.uint64), b.val.view(np.uint64))
+            and np.array_equal(a.D.view(np.uint64), b.D.view(np.uint64)))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_schedule_invariance(orc, seed):
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(50, 300))
+    A, ex = random_graph(rng, n, 3 * n, sddm=seed == 3)
+    perm = rng.permutation(n).astype(np.int32)
+    ref = orc.factor(A, perm=perm, seed=seed)
+    for W in (1, 2, 3, 7, 64):
+        for ss in range(3):
+            f = orc.factor(A, perm=perm, seed=seed, schedule=orc.SCHED_ASYNC,
+                           sched_seed=1000 * W + ss, nworkers=W)
+            assert f.status == orc.OK
+            assert same_factor(f, ref)
+
+
+def test_delete_first_mistake_is_caught(orc):
+    """Applying the pivot-edge decrements before the sampled insertions lets a
+    vertex be claimed before its fill has arrived (§III): under concurrency
+    this shows as a broken counter or a different factor."""
+    caught = 0
+    for seed in range(6):
+        rng = np.random.default_rng(300 + seed)
+        n = 120
+        A, _ = random_graph(rng, n, 3 * n)
+        perm = rng.permutation(n).astype(np.int32)
+        ref = orc.factor(A, perm=perm, seed=seed)
+        f = orc.factor(A, perm=perm, seed=seed, schedule=orc.SCHED_ASYNC, sched_seed=seed,
+                       nworkers=16, debug_flags=orc.DBG_DELETE_FIRST)
+        if f.status != orc.OK or not same_factor(f, ref):
+            caught += 1
+    assert caught >= 4
+
+
+# ----------------------------------------------------------------------------
+# T7: PCG against a dense pseudo-inverse solve
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(5))
+def test_pcg_matches_pinv(orc, seed):
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(10, 200))
+    sddm = seed % 2 == 1
+    A, ex = random_graph(rng, n, 2 * n, sddm=sddm)
+    perm = rng.permutation(n).astype(np.int32)
+    f = orc.factor(A, perm=perm, seed=seed)
+    b = rng.standard_normal(n)
+    if not sddm:
+        b -= b.mean()
+    x, st = orc.pcg(A, f, b, rtol=1e-12)
+    assert st["status"] == 0 and st["true_relres"] <= 1e-11
+    xr = np.linalg.pinv(A.to_dense()) @ b
+    if not sddm:
+        x = x - x.mean()
+        xr = xr - xr.mean()
+    assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+def test_apply_is_exact_inverse_on_exact_factor(orc):
+    """On a cycle every pivot has degree <= 2, so M = L exactly and M^+ b
+    solves L z = b for centred b (R9: D^+ at the zero pivot)."""
+    rng = np.random.default_rng(8)
+    n = 25
+    i, j = inputs.cycle_edges(n)
+    A = lap(n, i, j, rng.uniform(0.5, 2.0, n))
+    perm = rng.permutation(n).astype(np.int32)
+    f = orc.factor(A, perm=perm, seed=1)
+    b = inputs.rhs(n, rng)
+    z = orc.apply(f, b)
+    r = b - A.to_dense() @ z
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
+    z32 = orc.apply(f, b, precision=1)
+    assert np.linalg.norm(z32 - z) <= 1e-5 * np.linalg.norm(z)
+
+
+# ----------------------------------------------------------------------------
+# R4: suffix sums
+# ----------------------------------------------------------------------------
+def test_suffix_sums_exact_on_integers(orc):
+    """With unit weights on a star every partial sum is an exact integer, so
+    D_k must equal the degree whatever the association, and the factor
+    entries are exactly -1/d."""
+    for d in (1, 5, 63, 64, 65, 130, 200):
+        A = lap(d + 1, np.zeros(d, int), np.arange(1, d + 1), np.ones(d))
+        f = orc.factor(A, seed=1)
+        assert f.D[0] == float(d)
+        assert np.all(f.val[: d] == -1.0 / d)
+
+
+def test_large_degree_sum_within_bound(orc):
+    """A hub with many distinct weights: D_k = S_1 agrees with the correctly
+    rounded sum to within the error bound of any summation order."""
+    rng = np.random.default_rng(12)
+    for d in (64, 65, 200, 1000):
+        w = rng.uniform(1e-3, 1.0, d)
+        A = lap(d + 1, np.zeros(d, int), np.arange(1, d + 1), w)
+        f = orc.factor(A, seed=2)
+        exact = math.fsum(w)
+        assert abs(f.D[0] - exact) <= d * np.finfo(float).eps * exact
