@@ -142,6 +142,8 @@ typedef struct {
   int32_t precision;      /* PARAC_PREC_*                                   */
   int32_t check_every;    /* iterations between host convergence checks
                              (0 = 8)                                        */
+  int32_t timing;         /* 1: time the phases with HIP events on the
+                             stream (fills the ms_* fields of the stats)    */
 } parac_pcg_opts;
 
 typedef struct {
@@ -149,6 +151,10 @@ typedef struct {
   int32_t iterations;     /* SpMVs performed                                */
   double relres;          /* recursive ||r||/||b|| at exit                  */
   double true_relres;     /* ||b - A x||/||b|| recomputed in FP64           */
+  double ms_total;        /* the whole call on the stream                   */
+  double ms_apply;        /* preconditioner applies (both triangular solves)
+                             when timing = 1, else 0                        */
+  int32_t applies;        /* preconditioner applies performed               */
 } parac_pcg_stats;
 
 /* Preconditioned conjugate gradients with x0 = 0 (§V methodology; the

@@ -1,0 +1,170 @@
+// device.hpp -- wave64 building blocks for the gfx950 kernels: lane utilities,
+// agent-scope atomics and fences, the counter-based sampler, bitonic networks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace parac {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// lanes
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// index of the j-th set bit of m (0-based); m must have more than j bits set
+__device__ __forceinline__ int select_bit(uint64_t m, int j) {
+  int base = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    uint64_t low = m & ((w == 64) ? ~0ull : ((1ull << w) - 1));
+    int c = __popcll(low);
+    if (j >= c) {
+      j -= c;
+      m >>= w;
+      base += w;
+    } else {
+      m = low;
+    }
+  }
+  return base;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, kWave); }
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  return (uint64_t)__shfl((unsigned long long)v, src, kWave);
+}
+
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+  return __shfl(v, src, kWave);
+}
+
+__device__ __forceinline__ int first_lane_i32(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// ---------------------------------------------------------------------------
+// atomics and fences (agent scope: the whole device, across XCDs)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld_acq_relaxed(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T fetch_add(T *p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T fetch_max(T *p, T v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_acquire() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+__device__ __forceinline__ void fence_release() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+__device__ __forceinline__ void fence_acq_rel() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+}
+// orders this wave's own global/LDS accesses (same CU)
+__device__ __forceinline__ void fence_wave_local() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// first error wins
+__device__ __forceinline__ void set_error(int *err, int code) {
+  int expected = 0;
+  __hip_atomic_compare_exchange_strong(err, &expected, code, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t now_ticks() { return wall_clock64(); }
+
+// exponential back-off for spin loops: 64 .. 64*2^6 cycles between polls, so
+// thousands of waiting waves do not flood the memory system with requests
+struct Backoff {
+  int step = 0;
+  __device__ __forceinline__ void pause() {
+    switch (step) {
+      case 0: __builtin_amdgcn_s_sleep(1); break;
+      case 1: __builtin_amdgcn_s_sleep(2); break;
+      case 2: __builtin_amdgcn_s_sleep(4); break;
+      case 3: __builtin_amdgcn_s_sleep(8); break;
+      case 4: __builtin_amdgcn_s_sleep(16); break;
+      case 5: __builtin_amdgcn_s_sleep(32); break;
+      default: __builtin_amdgcn_s_sleep(64); break;
+    }
+    if (step < 6) ++step;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): 2 x (64x64 -> 128) multiplies per
+// round, Weyl key schedule.  Only the first output word is needed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t philox_first_word(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                      uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  const uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t h0 = __umul64hi(kM0, c0), l0 = kM0 * c0;
+    uint64_t h1 = __umul64hi(kM1, c2), l1 = kM1 * c2;
+    uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = l1;
+    c2 = n2;
+    c3 = l0;
+    k0 += kW0;
+    k1 += kW1;
+  }
+  return c0;
+}
+
+// uniform double in [0,1) with 53 random bits: (x >> 11) * 2^-53 (exact)
+__device__ __forceinline__ double draw_unit(uint64_t seed, uint32_t k, uint32_t s) {
+  uint64_t x = philox_first_word((uint64_t)k, (uint64_t)s, 0, 0, seed, 0);
+  return (double)(x >> 11) * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Sort keys
+// ---------------------------------------------------------------------------
+// merge key: (u, src) with src = -1 for an input edge -> unique 64-bit key
+__device__ __forceinline__ uint64_t merge_key(int32_t u, int32_t src) {
+  return ((uint64_t)(uint32_t)u << 32) | (uint64_t)(uint32_t)(src + 1);
+}
+
+// positive doubles order like their bit patterns
+__device__ __forceinline__ uint64_t dbits(double w) { return (uint64_t)__double_as_longlong(w); }
+__device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
+
+// (wbits, u) lexicographic
+__device__ __forceinline__ bool less_wu(uint64_t wa, int32_t ua, uint64_t wb, int32_t ub) {
+  return wa < wb || (wa == wb && ua < ub);
+}
+
+// One compare-exchange step of the bitonic network across lanes, in its
+// direction-free form: stage `p` (block size), step `j`; the first step of
+// each stage compares with the mirrored lane, later ones with lane ^ j.
+// Lanes beyond the data hold +inf keys, so the network needs no padding.
+__device__ __forceinline__ int bitonic_partner(int l, int p, int j, bool first) {
+  return first ? (l ^ (p - 1)) : (l ^ j);
+}
+
+}  // namespace parac

@@ -1,0 +1,603 @@
+// eliminate.hip -- the persistent elimination kernel.
+//
+// One wave64 eliminates one pivot at a time.  Workers poll their slots of the
+// ready queue round-robin (§IV-A, work scheduling), so the whole factorisation
+// is one launch (§IV-C, persistent kernel).  For a pivot k the wave
+//   1. gathers the input upper edges of k and every fill record addressed to k
+//      (all present once k is ready: insertions precede deletions, §III);
+//   2. merges parallel edges (sort by (u, src), left fold per run -- the
+//      multiplicity is the run length);
+//   3. sorts the merged neighbours by (w, u) ascending (Alg. 2) and forms the
+//      suffix sums S with the 64-wide tiled association; D_k = S_1;
+//   4. draws one partner per slot p = 1..d-1 with probability w_q / S_{p+1}
+//      (Alg. 2) from a counter-based generator keyed by (k, slot) and appends
+//      the sampled edge, of weight S_{p+1} w_p / D_k, to the inbox of its
+//      smaller endpoint, incrementing the counter of the larger (§III);
+//   5. writes column k of F, F(u,k) = -w_u / D_k, and D_k (§IV scaled form);
+//   6. publishes everything with one agent-scope release, then decrements the
+//      counters of its neighbours by their multiplicities and enqueues those
+//      that reach zero (Alg. 3/4).
+// The arithmetic follows fixed orders that do not depend on the schedule, so
+// the factor is the same bit for bit for any grid size or timing.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace parac {
+
+struct Worker {
+  int64_t f_base, f_left;    // reserved factor entries
+  int64_t pg_base, pg_left;  // reserved fill-record pages
+  int64_t sc_base, sc_size;  // scratch region of the large-neighbourhood path
+};
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// record r of an inbox: page j holds kInline << j records starting at
+// record kInline (2^j - 1)
+__device__ __forceinline__ void page_of(int r, int &j, int &off) {
+  int q = r / kInline + 1;
+  j = 31 - __clz(q);
+  off = r - kInline * ((1 << j) - 1);
+}
+
+__device__ __forceinline__ Rec load_rec(const ElimArgs &a, int32_t k, int r) {
+  int j, off;
+  page_of(r, j, off);
+  const Rec *p;
+  if (j == 0) {
+    p = a.inl + (int64_t)k * kInline + off;
+  } else {
+    int32_t base = a.ptab[(int64_t)k * (kPages - 1) + j - 1];
+    p = a.pool + (int64_t)base + off;
+  }
+  return *p;
+}
+
+__device__ __forceinline__ bool timed_out(const ElimArgs &a, uint64_t deadline) {
+  if (now_ticks() > deadline) {
+    set_error(a.err, PARAC_ETIMEOUT);
+    return true;
+  }
+  return ld_acq_relaxed(a.err) != 0;
+}
+
+// Append one sampled edge per active lane to the inbox of `tgt` and count it
+// on `oth` (insertion step of §III).  Returns false after setting an error.
+__device__ bool insert_records(const ElimArgs &a, Worker &wk, bool ins, int32_t tgt, int32_t oth,
+                               int32_t k, double c, uint64_t deadline) {
+  const int l = lane();
+  int r = ins ? fetch_add(&a.fill_cnt[tgt], 1) : 0;
+  int j = 0, off = 0;
+  if (ins) page_of(r, j, off);
+  if (__any(ins && j >= kPages)) {
+    set_error(a.err, PARAC_EPOOL);
+    return false;
+  }
+  const bool alloc = ins && j > 0 && off == 0;
+  int32_t *pslot = (ins && j > 0) ? &a.ptab[(int64_t)tgt * (kPages - 1) + j - 1] : nullptr;
+  int need = alloc ? (kInline << j) : 0;
+  int incl = need;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(incl, o, kWave);
+    if (l >= o) incl += y;
+  }
+  const int total = shfl(incl, kWave - 1);
+  int64_t mybase = -1;
+  if (total > 0) {
+    if ((int64_t)total > wk.pg_left) {
+      int64_t grab = total > a.pg_chunk ? total : a.pg_chunk;
+      long long b = 0;
+      if (l == 0) b = (long long)atomicAdd(a.pool_top, (unsigned long long)grab);
+      b = __shfl(b, 0, kWave);
+      if (b + grab > a.pool_cap) {
+        if (alloc) st_relaxed(pslot, (int32_t)-2);  // release waiters
+        set_error(a.err, PARAC_EPOOL);
+        return false;
+      }
+      wk.pg_base = b;
+      wk.pg_left = grab;
+    }
+    mybase = wk.pg_base + (incl - need);
+    wk.pg_base += total;
+    wk.pg_left -= total;
+    if (alloc) st_relaxed(pslot, (int32_t)mybase);
+  }
+  int64_t pbase = alloc ? mybase : -1;
+  bool wait = ins && j > 0 && !alloc;
+  Backoff bo;
+  for (int it = 0; __any(wait); ++it) {
+    if (wait) {
+      int32_t v = ld_acq_relaxed(pslot);
+      if (v != -1) {
+        pbase = v;
+        wait = false;
+      }
+    }
+    if (__any(wait)) {
+      bo.pause();
+      if ((it & 63) == 63 && timed_out(a, deadline)) return false;
+    }
+  }
+  if (__any(ins && j > 0 && pbase < 0)) {
+    set_error(a.err, PARAC_EPOOL);
+    return false;
+  }
+  if (ins) {
+    Rec *dst = (j == 0) ? a.inl + (int64_t)tgt * kInline + off : a.pool + pbase + off;
+    Rec rec;
+    rec.other = oth;
+    rec.src = k;
+    rec.w = c;
+    *dst = rec;
+    fetch_add(&a.dp[oth], 1);
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool alloc_column(const ElimArgs &a, Worker &wk, int d, int64_t &base) {
+  if ((int64_t)d > wk.f_left) {
+    int64_t grab = d > a.f_chunk ? d : a.f_chunk;
+    long long b = 0;
+    if (lane() == 0) b = (long long)atomicAdd(a.f_top, (unsigned long long)grab);
+    b = __shfl(b, 0, kWave);
+    if (b + grab > a.f_cap) {
+      set_error(a.err, PARAC_EPOOL);
+      return false;
+    }
+    wk.f_base = b;
+    wk.f_left = grab;
+  }
+  base = wk.f_base;
+  wk.f_base += d;
+  wk.f_left -= d;
+  return true;
+}
+
+// pivot-edge deletion of §III: d(u) -= m(u,k); enqueue on reaching zero
+__device__ __forceinline__ bool decrement(const ElimArgs &a, bool valid, int32_t u, int m) {
+  bool enq = false, bad = false;
+  if (valid) {
+    int prior = fetch_add(&a.dp[u], -m);
+    enq = prior == m;
+    bad = prior < m;
+  }
+  if (__any(bad)) {
+    set_error(a.err, PARAC_EINTERNAL);
+    return false;
+  }
+  if (__any(enq)) {
+    fence_acq_rel();
+    if (enq) {
+      int x = u & (kSubQueues - 1);
+      int pos = fetch_add(&a.qtail[x * kTailStride], 1);
+      if (pos < a.cap_q) st_relaxed(&a.q[(int64_t)x * a.cap_q + pos], u);
+      else bad = true;
+    }
+    if (__any(bad)) {
+      set_error(a.err, PARAC_EINTERNAL);
+      return false;
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// neighbourhoods of at most 64 gathered entries: one entry per lane
+// ---------------------------------------------------------------------------
+__device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
+                            int levk, uint64_t deadline) {
+  const int l = lane();
+  // 1. gather
+  uint64_t key = ~0ull;
+  double w = 0.0;
+  if (l < nU) {
+    key = merge_key(a.uidx[u0 + l], -1);
+    w = a.uw[u0 + l];
+  } else if (l < g) {
+    Rec rc = load_rec(a, k, l - nU);
+    key = merge_key(rc.other, rc.src);
+    w = rc.w;
+  }
+  // 2. sort by (u, src): bitonic network across the 64 lanes
+#pragma unroll
+  for (int p = 2; p <= kWave; p <<= 1) {
+#pragma unroll
+    for (int jj = p >> 1; jj >= 1; jj >>= 1) {
+      int pl = (jj == (p >> 1)) ? (l ^ (p - 1)) : (l ^ jj);
+      uint64_t ok = shfl_u64(key, pl);
+      double ow = shfl_f64(w, pl);
+      bool take = (pl > l) ? (ok < key) : (ok > key);
+      if (take) {
+        key = ok;
+        w = ow;
+      }
+    }
+  }
+  // merge runs of equal u: left fold in key order, multiplicity = run length
+  const bool valid = l < g;
+  const int32_t u = (int32_t)(key >> 32);
+  const int32_t up = shfl(u, l > 0 ? l - 1 : 0);
+  const bool head = valid && (l == 0 || up != u);
+  double acc = w;
+  int m = 1;
+  bool active = head;
+  for (int step = 1; step < kWave; ++step) {
+    int sl = l + step < kWave ? l + step : kWave - 1;
+    double ws = shfl_f64(w, sl);
+    int32_t us = shfl(u, sl);
+    bool cont = active && (l + step < g) && (us == u);
+    if (cont) {
+      acc = acc + ws;
+      ++m;
+    }
+    active = cont;
+    if (!__any(active)) break;
+  }
+  if (__any(valid && (u < 0 || u >= a.ntot || u <= k))) {  // labels above k only
+    set_error(a.err, PARAC_EINTERNAL);
+    return false;
+  }
+  const uint64_t hm = __ballot(head);
+  const int d = __popcll(hm);
+  const int src = l < d ? select_bit(hm, l) : 0;
+  int32_t mu = shfl(u, src);
+  double mw = shfl_f64(acc, src);
+  int mm = shfl(m, src);
+  if (l >= d) {
+    mu = 0x7fffffff;
+    mw = 0.0;
+    mm = 0;
+  }
+  // 3. sampling order (w asc, u asc) and suffix sums
+  uint64_t wb = l < d ? dbits(mw) : ~0ull;
+  int32_t su = l < d ? mu : 0x7fffffff;
+#pragma unroll
+  for (int p = 2; p <= kWave; p <<= 1) {
+#pragma unroll
+    for (int jj = p >> 1; jj >= 1; jj >>= 1) {
+      int pl = (jj == (p >> 1)) ? (l ^ (p - 1)) : (l ^ jj);
+      uint64_t ow = shfl_u64(wb, pl);
+      int32_t ou = shfl(su, pl);
+      bool take = (pl > l) ? less_wu(ow, ou, wb, su) : less_wu(wb, su, ow, ou);
+      if (take) {
+        wb = ow;
+        su = ou;
+      }
+    }
+  }
+  const double sw = l < d ? bitsd(wb) : 0.0;
+  double S = sw;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    double y = shfl_f64(S, l + o < kWave ? l + o : kWave - 1);
+    if (l + o < d) S = S + y;
+  }
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    double y = shfl_f64(S, l + o < kWave ? l + o : kWave - 1);
+    if (l + o < d && y > S) S = y;
+  }
+  const double Dk = shfl_f64(S, 0);
+  // 4. one sampled edge per slot s = 0..d-2 (position p = s+1)
+  const bool ins = l < d - 1;
+  const double Sp1 = shfl_f64(S, l + 1 < kWave ? l + 1 : kWave - 1);
+  const double t = draw_unit(a.seed, (uint32_t)k, (uint32_t)l) * Sp1;
+  int lo = l + 1, hi = d - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    int mid = (lo + hi) >> 1;
+    int idx = mid + 1 < kWave ? mid + 1 : kWave - 1;
+    double sn = shfl_f64(S, idx);
+    if (mid + 1 >= d) sn = 0.0;
+    if (lo < hi) {
+      if (sn <= t) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  const int32_t ub = shfl(su, lo < kWave ? lo : kWave - 1);
+  const double c = (Sp1 * sw) / Dk;
+  const int32_t tgt = su < ub ? su : ub, oth = su < ub ? ub : su;
+  if (!insert_records(a, wk, ins, tgt, oth, k, c, deadline)) return false;
+  // 5. column k of F (rows ascending) and D_k
+  int64_t base;
+  if (!alloc_column(a, wk, d, base)) return false;
+  if (l < d) {
+    a.frow[base + l] = mu;
+    a.fval[base + l] = -(mw / Dk);
+    fetch_max(&a.lev[mu], levk + 1);
+  }
+  if (l == 0) {
+    a.D[k] = Dk;
+    a.colstart[k] = base;
+    a.colcnt[k] = d;
+  }
+  // 6. publish, then delete the pivot's edges
+  fence_release();
+  return decrement(a, l < d, mu, mm);
+}
+
+// ---------------------------------------------------------------------------
+// larger neighbourhoods: the same steps over wave-private scratch in HBM;
+// sorting by rank (keys are unique), suffix sums tile by tile
+// ---------------------------------------------------------------------------
+__device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
+                            int levk, uint64_t deadline) {
+  const int l = lane();
+  const int64_t bytes = (((int64_t)g * 68) + 255) & ~(int64_t)255;
+  if (bytes > wk.sc_size) {
+    // the worker's region is reused across pivots; grow it geometrically
+    int64_t want = bytes > 2 * wk.sc_size ? bytes : 2 * wk.sc_size;
+    long long off = 0;
+    if (l == 0) off = (long long)atomicAdd(a.arena_top, (unsigned long long)want);
+    off = __shfl(off, 0, kWave);
+    if (off + want > a.arena_cap) {
+      set_error(a.err, PARAC_EPOOL);
+      return false;
+    }
+    wk.sc_base = off;
+    wk.sc_size = want;
+  }
+  char *base = a.arena + wk.sc_base;
+  uint64_t *keyA = (uint64_t *)base;
+  double *wA = (double *)(keyA + g);
+  uint64_t *keyB = (uint64_t *)(wA + g);
+  double *wB = (double *)(keyB + g);
+  double *mw = wB + g;
+  double *sw = mw + g;
+  double *S = sw + g;
+  int32_t *mu = (int32_t *)(S + g);
+  int32_t *mm = mu + g;
+  int32_t *su = mm + g;
+  // 1. gather
+  for (int i = l; i < g; i += kWave) {
+    int32_t u, src;
+    double w;
+    if (i < nU) {
+      u = a.uidx[u0 + i];
+      src = -1;
+      w = a.uw[u0 + i];
+    } else {
+      Rec rc = load_rec(a, k, i - nU);
+      u = rc.other;
+      src = rc.src;
+      w = rc.w;
+    }
+    keyA[i] = merge_key(u, src);
+    wA[i] = w;
+  }
+  fence_wave_local();
+  // 2. sort by (u, src): rank = number of smaller keys
+  for (int ib = 0; ib < g; ib += kWave) {
+    const int i = ib + l;
+    const uint64_t ki = i < g ? keyA[i] : ~0ull;
+    int rank = 0;
+    for (int jb = 0; jb < g; jb += kWave) {
+      const uint64_t kj = (jb + l < g) ? keyA[jb + l] : ~0ull;
+      const int lim = g - jb < kWave ? g - jb : kWave;
+      for (int jj = 0; jj < lim; ++jj) rank += readlane_u64(kj, jj) < ki ? 1 : 0;
+    }
+    if (i < g) {
+      keyB[rank] = ki;
+      wB[rank] = wA[i];
+    }
+  }
+  fence_wave_local();
+  // every gathered label must lie above k (and exist)
+  {
+    bool bad = false;
+    for (int i = l; i < g; i += kWave) {
+      int32_t u = (int32_t)(keyB[i] >> 32);
+      bad |= u <= k || u >= a.ntot;
+    }
+    if (__any(bad)) {
+      set_error(a.err, PARAC_EINTERNAL);
+      return false;
+    }
+  }
+  // merge runs of equal u (left fold in key order)
+  int d = 0;
+  for (int ib = 0; ib < g; ib += kWave) {
+    const int i = ib + l;
+    const bool valid = i < g;
+    const int32_t u = valid ? (int32_t)(keyB[i] >> 32) : -1;
+    const int32_t up = (valid && i > 0) ? (int32_t)(keyB[i - 1] >> 32) : -1;
+    const bool head = valid && (i == 0 || up != u);
+    double acc = 0.0;
+    int m = 0;
+    if (head) {
+      acc = wB[i];
+      m = 1;
+      for (int jx = i + 1; jx < g && (int32_t)(keyB[jx] >> 32) == u; ++jx) {
+        acc = acc + wB[jx];
+        ++m;
+      }
+    }
+    const uint64_t hm = __ballot(head);
+    const int pos = d + __popcll(hm & lanemask_lt());
+    if (head) {
+      mu[pos] = u;
+      mw[pos] = acc;
+      mm[pos] = m;
+    }
+    d += __popcll(hm);
+  }
+  fence_wave_local();
+  // 3. sampling order by rank on (w, u)
+  for (int ib = 0; ib < d; ib += kWave) {
+    const int i = ib + l;
+    const uint64_t wi = i < d ? dbits(mw[i]) : ~0ull;
+    const int32_t ui = i < d ? mu[i] : 0x7fffffff;
+    int rank = 0;
+    for (int jb = 0; jb < d; jb += kWave) {
+      const uint64_t wj = (jb + l < d) ? dbits(mw[jb + l]) : ~0ull;
+      const int32_t uj = (jb + l < d) ? mu[jb + l] : 0x7fffffff;
+      const int lim = d - jb < kWave ? d - jb : kWave;
+      for (int jj = 0; jj < lim; ++jj) {
+        uint64_t ww = readlane_u64(wj, jj);
+        int32_t uu = __builtin_amdgcn_readlane(uj, jj);
+        rank += less_wu(ww, uu, wi, ui) ? 1 : 0;
+      }
+    }
+    if (i < d) {
+      su[rank] = ui;
+      sw[rank] = mw[i];
+    }
+  }
+  fence_wave_local();
+  // suffix sums: 64-wide tiles, Hillis-Steele inside, carries right to left
+  const int ntile = (d + kWave - 1) / kWave;
+  double carry = 0.0;
+  for (int tt = ntile - 1; tt >= 0; --tt) {
+    const int t0 = tt * kWave;
+    const int len = d - t0 < kWave ? d - t0 : kWave;
+    double v = l < len ? sw[t0 + l] : 0.0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
+      if (l + o < len) v = v + y;
+    }
+    const double total = shfl_f64(v, 0);
+    if (tt != ntile - 1) v = v + carry;
+    carry = (tt == ntile - 1) ? total : total + carry;
+    if (l < len) S[t0 + l] = v;
+  }
+  fence_wave_local();
+  // suffix maximum (exact): S non-increasing
+  double runmax = 0.0;
+  for (int tt = ntile - 1; tt >= 0; --tt) {
+    const int t0 = tt * kWave;
+    const int len = d - t0 < kWave ? d - t0 : kWave;
+    double v = l < len ? S[t0 + l] : 0.0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
+      if (l + o < len && y > v) v = y;
+    }
+    if (runmax > v) v = runmax;
+    runmax = shfl_f64(v, 0);
+    if (l < len) S[t0 + l] = v;
+  }
+  fence_wave_local();
+  const double Dk = S[0];
+  // 4. sampled edges
+  for (int ib = 0; ib < d - 1; ib += kWave) {
+    const int s = ib + l;
+    const bool ins = s < d - 1;
+    int32_t tgt = 0, oth = 0;
+    double c = 0.0;
+    if (ins) {
+      const double Sp1 = S[s + 1];
+      const double t = draw_unit(a.seed, (uint32_t)k, (uint32_t)s) * Sp1;
+      int lo = s + 1, hi = d - 1;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        double sn = (mid + 1 < d) ? S[mid + 1] : 0.0;
+        if (sn <= t) hi = mid;
+        else lo = mid + 1;
+      }
+      const int32_t ua = su[s], ub = su[lo];
+      c = (Sp1 * sw[s]) / Dk;
+      tgt = ua < ub ? ua : ub;
+      oth = ua < ub ? ub : ua;
+    }
+    if (!insert_records(a, wk, ins, tgt, oth, k, c, deadline)) return false;
+  }
+  // 5. column k of F
+  int64_t fbase;
+  if (!alloc_column(a, wk, d, fbase)) return false;
+  for (int i = l; i < d; i += kWave) {
+    const int32_t uu = mu[i];
+    a.frow[fbase + i] = uu;
+    a.fval[fbase + i] = -(mw[i] / Dk);
+    fetch_max(&a.lev[uu], levk + 1);
+  }
+  if (l == 0) {
+    a.D[k] = Dk;
+    a.colstart[k] = fbase;
+    a.colcnt[k] = d;
+  }
+  // 6. publish, then delete the pivot's edges
+  fence_release();
+  for (int ib = 0; ib < d; ib += kWave) {
+    const int i = ib + l;
+    const bool valid = i < d;
+    if (!decrement(a, valid, valid ? mu[i] : 0, valid ? mm[i] : 0)) return false;
+  }
+  return true;
+}
+
+__device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline) {
+  const int64_t u0 = a.uptr[k];
+  const int nU = (int)(a.uptr[k + 1] - u0);
+  const int nF = ld_acq_relaxed(&a.fill_cnt[k]);
+  const int g = nU + nF;
+  if (g == 0) {  // empty neighbourhood: D_k = 0 (Alg. 3/4)
+    if (lane() == 0) {
+      a.D[k] = 0.0;
+      a.colstart[k] = 0;
+      a.colcnt[k] = 0;
+    }
+    return true;
+  }
+  const int levk = ld_acq_relaxed(&a.lev[k]);
+  if (g <= kWave) return small_pivot(a, wk, k, u0, nU, g, levk, deadline);
+  return large_pivot(a, wk, k, u0, nU, g, levk, deadline);
+}
+
+__global__ __launch_bounds__(256) void k_eliminate(ElimArgs a) {
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wid >= a.nworkers) return;
+  const uint64_t deadline = now_ticks() + a.timeout_ticks;
+  // Shard x holds exactly the labels v = x (mod kSubQueues), so its slot
+  // count is known.  Workers claim its slots in increasing order (the next
+  // claim is taken before the current pivot is eliminated): the lowest ready
+  // slot is always held by a running worker, whatever the residency.
+  const int x = wid & (kSubQueues - 1);
+  const int cnt = x < a.ntot ? (a.ntot - 1 - x) / kSubQueues + 1 : 0;
+  const int32_t *qx = a.q + (int64_t)x * a.cap_q;
+  int *head = a.qhead + x * kTailStride;
+  Worker wk{0, 0, 0, 0, 0, 0};
+  int next = 0;
+  if (lane() == 0) next = atomicAdd(head, 1);
+  next = __shfl(next, 0, kWave);
+  while (next < cnt) {
+    const int slot = next;
+    int32_t k;
+    Backoff bo;
+    for (int it = 0;; ++it) {
+      int32_t v = 0;
+      if (lane() == 0) v = ld_acq_relaxed(&qx[slot]);
+      k = first_lane_i32(v);
+      if (k >= 0) break;
+      // the shared error word and the clock are consulted rarely
+      if ((it & 63) == 63 && timed_out(a, deadline)) return;
+      bo.pause();
+    }
+    fence_acquire();
+    if (lane() == 0) next = atomicAdd(head, 1);
+    next = __shfl(next, 0, kWave);
+    if (!eliminate_pivot(a, wk, k, deadline)) return;
+  }
+}
+
+hipError_t launch_eliminate(const ElimArgs &a, int wgs, hipStream_t s) {
+  hipLaunchKernelGGL(k_eliminate, dim3((unsigned)wgs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int eliminate_max_workgroups() {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eliminate, 256, 0) != hipSuccess)
+    return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
+}  // namespace parac

@@ -1,0 +1,297 @@
+// finalize.hip -- from the elimination's column chunks to the solve layout:
+// canonical CSC of F (label order, rows ascending), its CSR transpose (rows
+// ordered by column, so every row sum has a fixed order), rows grouped by
+// elimination level for the triangular solves, D^+, FP32 copies, statistics.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace parac {
+
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+__global__ void k_compact_csc(int64_t ntot, const int64_t *__restrict__ colstart,
+                              const int32_t *__restrict__ colcnt, const int32_t *__restrict__ frow,
+                              const double *__restrict__ fval, const int64_t *__restrict__ colptr,
+                              int32_t *rowind, double *val) {
+  // one wave per 64 columns; each lane copies one column
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ntot) return;
+  int64_t s = colstart[k], o = colptr[k];
+  int c = colcnt[k];
+  for (int e = 0; e < c; ++e) {
+    rowind[o + e] = frow[s + e];
+    val[o + e] = fval[s + e];
+  }
+}
+
+hipError_t launch_compact_csc(int64_t ntot, const int64_t *colstart, const int32_t *colcnt,
+                              const int32_t *frow, const double *fval, const int64_t *colptr,
+                              int32_t *rowind, double *val, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_csc, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, colstart, colcnt,
+                     frow, fval, colptr, rowind, val);
+  return hipGetLastError();
+}
+
+__global__ void k_row_count(int64_t nnz, const int32_t *__restrict__ rowind, int32_t *rowcnt) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&rowcnt[rowind[e]], 1);
+}
+
+hipError_t launch_row_count(int64_t nnz, const int32_t *rowind, int32_t *rowcnt, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_count, dim3(nblk(nnz, 256)), dim3(256), 0, s, nnz, rowind, rowcnt);
+  return hipGetLastError();
+}
+
+__global__ void k_transpose(int64_t ntot, const int64_t *__restrict__ colptr,
+                            const int32_t *__restrict__ rowind, const double *__restrict__ val,
+                            const int64_t *__restrict__ rowptr_f, int32_t *cursor,
+                            int32_t *colind_f, double *val_f) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ntot) return;
+  for (int64_t e = colptr[k]; e < colptr[k + 1]; ++e) {
+    int32_t i = rowind[e];
+    int64_t pos = rowptr_f[i] + atomicAdd(&cursor[i], 1);
+    colind_f[pos] = (int32_t)k;
+    val_f[pos] = val[e];
+  }
+}
+
+hipError_t launch_transpose(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
+                            const double *val, const int64_t *rowptr_f, int32_t *cursor,
+                            int32_t *colind_f, double *val_f, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, colptr, rowind, val,
+                     rowptr_f, cursor, colind_f, val_f);
+  return hipGetLastError();
+}
+
+// rows of up to 64 entries: insertion sort by column, one lane per row; the
+// longer ones are listed for the wave-per-row pass
+__global__ void k_sort_rows(int64_t ntot, const int64_t *__restrict__ rowptr_f, int32_t *colind_f,
+                            double *val_f, int32_t *long_rows, int32_t *n_long) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  int64_t b = rowptr_f[i], e = rowptr_f[i + 1];
+  if (e - b > 64) {
+    long_rows[atomicAdd(n_long, 1)] = (int32_t)i;
+    return;
+  }
+  for (int64_t p = b + 1; p < e; ++p) {
+    int32_t c = colind_f[p];
+    double v = val_f[p];
+    int64_t q = p - 1;
+    while (q >= b && colind_f[q] > c) {
+      colind_f[q + 1] = colind_f[q];
+      val_f[q + 1] = val_f[q];
+      --q;
+    }
+    colind_f[q + 1] = c;
+    val_f[q + 1] = v;
+  }
+}
+
+// long rows: one wave per row, rank sort (columns are distinct) through the
+// scratch arrays tmp_c / tmp_v at the row's own offsets
+__global__ void k_sort_long_rows(const int64_t *__restrict__ rowptr_f, int32_t *colind_f,
+                                 double *val_f, const int32_t *__restrict__ long_rows,
+                                 const int32_t *__restrict__ n_long, int32_t *tmp_c,
+                                 double *tmp_v) {
+  const int l = lane();
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
+  const int cnt = *n_long;
+  for (int r = wid; r < cnt; r += nw) {
+    const int32_t row = long_rows[r];
+    const int64_t b = rowptr_f[row];
+    const int len = (int)(rowptr_f[row + 1] - b);
+    for (int ib = 0; ib < len; ib += kWave) {
+      const int i = ib + l;
+      const int32_t ci = i < len ? colind_f[b + i] : 0x7fffffff;
+      int rank = 0;
+      for (int jb = 0; jb < len; jb += kWave) {
+        const int32_t cj = jb + l < len ? colind_f[b + jb + l] : 0x7fffffff;
+        const int lim = len - jb < kWave ? len - jb : kWave;
+        for (int jj = 0; jj < lim; ++jj) rank += __builtin_amdgcn_readlane(cj, jj) < ci ? 1 : 0;
+      }
+      if (i < len) {
+        tmp_c[b + rank] = ci;
+        tmp_v[b + rank] = val_f[b + i];
+      }
+    }
+    fence_wave_local();
+    for (int i = l; i < len; i += kWave) {
+      colind_f[b + i] = tmp_c[b + i];
+      val_f[b + i] = tmp_v[b + i];
+    }
+    fence_wave_local();
+  }
+}
+
+hipError_t launch_sort_rows(int64_t ntot, const int64_t *rowptr_f, int32_t *colind_f,
+                            double *val_f, int32_t *long_rows, int32_t *n_long, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_rows, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, rowptr_f, colind_f,
+                     val_f, long_rows, n_long);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_long_rows(const int64_t *rowptr_f, int32_t *colind_f, double *val_f,
+                                 const int32_t *long_rows, const int32_t *n_long, int32_t *tmp_c,
+                                 double *tmp_v, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_long_rows, dim3(1024), dim3(256), 0, s, rowptr_f, colind_f, val_f,
+                     long_rows, n_long, tmp_c, tmp_v);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// rows grouped by level; one atomic per wave and distinct level
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int wave_aggregate_add(bool valid, int key, int32_t *ctr, int &mine) {
+  uint64_t act = __ballot(valid);
+  mine = 0;
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int kl = shfl(key, leader);
+    const uint64_t peers = __ballot(valid && key == kl) & act;
+    int base = 0;
+    if (lane() == leader) base = atomicAdd(&ctr[kl], __popcll(peers));
+    base = shfl(base, leader);
+    if ((peers >> lane()) & 1ull) mine = base + __popcll(peers & lanemask_lt());
+    act &= ~peers;
+  }
+  return 0;
+}
+
+__global__ void k_level_count(int64_t nrows, const int32_t *__restrict__ lev, int32_t *lcount) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = i < nrows;
+  int L = valid ? lev[i] : 0;
+  int mine;
+  wave_aggregate_add(valid, L, lcount, mine);
+}
+
+hipError_t launch_level_count(int64_t nrows, const int32_t *lev, int32_t *lcount, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_count, dim3(nblk(nrows, 256)), dim3(256), 0, s, nrows, lev, lcount);
+  return hipGetLastError();
+}
+
+__global__ void k_level_place(int64_t nrows, const int32_t *__restrict__ lev,
+                              const int64_t *__restrict__ lptr, int32_t *lcursor, int32_t *order) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = i < nrows;
+  int L = valid ? lev[i] : 0;
+  int mine;
+  wave_aggregate_add(valid, L, lcursor, mine);
+  if (valid) order[lptr[L] + mine] = (int32_t)i;
+}
+
+hipError_t launch_level_place(int64_t nrows, const int32_t *lev, const int64_t *lptr,
+                              int32_t *lcursor, int32_t *order, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_place, dim3(nblk(nrows, 256)), dim3(256), 0, s, nrows, lev, lptr,
+                     lcursor, order);
+  return hipGetLastError();
+}
+
+// batches per level: rows of one level are independent; a batch is the set
+// of rows one wave solves together
+__global__ void k_batches(int64_t depth, const int64_t *__restrict__ lptr, int32_t *bcnt, int rpb) {
+  int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= depth) return;
+  int64_t c = lptr[L + 1] - lptr[L];
+  bcnt[L] = (int32_t)((c + rpb - 1) / rpb);
+}
+
+hipError_t launch_batches(int64_t depth, const int64_t *lptr, int32_t *bcnt, int rpb,
+                          hipStream_t s) {
+  if (depth == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batches, dim3(nblk(depth, 256)), dim3(256), 0, s, depth, lptr, bcnt, rpb);
+  return hipGetLastError();
+}
+
+__global__ void k_dinv(int64_t ntot, const double *__restrict__ D, double *Dinv, float *Dinv32) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ntot) return;
+  double d = D[k];
+  double v = d > 0.0 ? 1.0 / d : 0.0;  // D^+ (zero pivots: one per component)
+  Dinv[k] = v;
+  if (Dinv32) Dinv32[k] = (float)v;
+}
+
+hipError_t launch_dinv(int64_t ntot, const double *D, double *Dinv, float *Dinv32,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_dinv, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, D, Dinv, Dinv32);
+  return hipGetLastError();
+}
+
+__global__ void k_cast32(int64_t n, const double *__restrict__ a, float *b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+hipError_t launch_cast32(int64_t n, const double *a, float *b, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast32, dim3(nblk(n, 256)), dim3(256), 0, s, n, a, b);
+  return hipGetLastError();
+}
+
+// out: [0] max gather, [1] max d_k, [2] sum max(d_k - 1, 0), [3] max level,
+//      [4] zero pivots
+__global__ void k_max_stats(int64_t ntot, const int64_t *__restrict__ uptr,
+                            const int32_t *__restrict__ fill_cnt,
+                            const int32_t *__restrict__ colcnt, const int32_t *__restrict__ lev,
+                            unsigned long long *out) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long g = 0, d = 0, f = 0, L = 0, z = 0;
+  if (k < ntot) {
+    g = (unsigned long long)(uptr[k + 1] - uptr[k] + fill_cnt[k]);
+    d = (unsigned long long)colcnt[k];
+    f = d > 0 ? d - 1 : 0;
+    L = (unsigned long long)lev[k];
+    z = colcnt[k] == 0 ? 1 : 0;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    unsigned long long g2 = __shfl_xor(g, o, kWave), d2 = __shfl_xor(d, o, kWave);
+    unsigned long long L2 = __shfl_xor(L, o, kWave);
+    g = g2 > g ? g2 : g;
+    d = d2 > d ? d2 : d;
+    L = L2 > L ? L2 : L;
+    f += __shfl_xor(f, o, kWave);
+    z += __shfl_xor(z, o, kWave);
+  }
+  if (lane() == 0) {
+    atomicMax(&out[0], g);
+    atomicMax(&out[1], d);
+    atomicAdd(&out[2], f);
+    atomicMax(&out[3], L);
+    atomicAdd(&out[4], z);
+  }
+}
+
+hipError_t launch_max_stats(int64_t ntot, const int64_t *uptr, const int32_t *fill_cnt,
+                            const int32_t *colcnt, const int32_t *lev, unsigned long long *out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_max_stats, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, uptr, fill_cnt,
+                     colcnt, lev, out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace parac

@@ -1,0 +1,194 @@
+// internal.hpp -- host-side types shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "parac.h"
+
+namespace parac {
+
+// fill record: an edge (target = the smaller label, other) of weight w,
+// produced by pivot src.  Stored at its target's inbox.
+struct __attribute__((aligned(16))) Rec {
+  int32_t other;
+  int32_t src;
+  double w;
+};
+
+// inbox geometry: page 0 (kInline records) is preallocated per vertex; page
+// j >= 1 holds kInline << j records and is allocated on first use, its base
+// published in the vertex's page table (kPages - 1 entries).
+constexpr int kInline = 8;
+constexpr int kPages = 17;             // capacity 8 (2^17 - 1) ~ 1M records
+constexpr int kSubQueues = 64;         // ready-queue shards (power of two)
+constexpr int kTailStride = 32;        // ints between shard tails (128 B)
+constexpr int kFChunk = 2048;          // largest factor-entry reservation
+constexpr int kPageChunk = 4096;       // largest fill-record reservation
+
+// sentinel bit patterns of the sync-free triangular solves ("not yet
+// computed"); a computed NaN is stored as the canonical quiet NaN instead
+constexpr uint64_t kSent64 = 0x7FF4DEADBEEF0001ull;
+constexpr uint32_t kSent32 = 0x7FA0BEEFu;
+
+struct ElimArgs {
+  int32_t ntot;
+  const int64_t *uptr;
+  const int32_t *uidx;
+  const double *uw;
+  int32_t *dp;
+  int32_t *q;          // kSubQueues shards of cap_q slots
+  int32_t *qtail;      // shard tails, kTailStride apart
+  int32_t *qhead;      // shard claim counters, kTailStride apart
+  int32_t cap_q;
+  int32_t *fill_cnt;
+  Rec *inl;            // ntot * kInline
+  int32_t *ptab;       // ntot * (kPages - 1)
+  Rec *pool;
+  int64_t pool_cap;
+  unsigned long long *pool_top;
+  int32_t *frow;
+  double *fval;
+  int64_t f_cap;
+  unsigned long long *f_top;
+  int64_t *colstart;
+  int32_t *colcnt;
+  double *D;
+  int32_t *lev;
+  char *arena;         // scratch of the large-neighbourhood path
+  int64_t arena_cap;
+  unsigned long long *arena_top;
+  uint64_t seed;
+  int *err;
+  uint64_t timeout_ticks;
+  int32_t nworkers;
+  int32_t pg_chunk;    // fill records a worker reserves at a time
+  int32_t f_chunk;     // factor entries a worker reserves at a time
+};
+
+// --- launchers (setup.hip) ---
+// input errors are min-reduced into *errkey (all ones = no error); the low
+// byte holds -status
+hipError_t launch_check_csr(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                            const double *val, double *excess, unsigned long long *errkey,
+                            int *any_excess, hipStream_t s);
+hipError_t launch_check_perm(int64_t n, const int32_t *perm, int32_t *seen, int32_t *iperm,
+                             unsigned long long *errkey, hipStream_t s);
+hipError_t launch_upper_count(int64_t n, const int64_t *rowptr, const int32_t *col,
+                              const double *val, const int32_t *perm, const double *excess,
+                              int sddm, int32_t *ucnt, int32_t *dp, hipStream_t s);
+hipError_t launch_upper_fill(int64_t n, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const int32_t *perm, const double *excess,
+                             int sddm, const int64_t *uptr, int32_t *uidx, double *uw,
+                             hipStream_t s);
+hipError_t launch_queue_init(int64_t ntot, const int32_t *dp, int32_t *q, int32_t *qtail,
+                             int32_t cap_q, hipStream_t s);
+// exclusive scan of int32 counts into int64 offsets (out[n] = total)
+hipError_t scan_counts(const int32_t *cnt, int64_t *out, int64_t n, void *tmp, size_t tmp_bytes,
+                       hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+
+// --- eliminate.hip ---
+hipError_t launch_eliminate(const ElimArgs &a, int wgs, hipStream_t s);
+int eliminate_max_workgroups();
+
+// --- finalize.hip ---
+hipError_t launch_compact_csc(int64_t ntot, const int64_t *colstart, const int32_t *colcnt,
+                              const int32_t *frow, const double *fval, const int64_t *colptr,
+                              int32_t *rowind, double *val, hipStream_t s);
+hipError_t launch_row_count(int64_t nnz, const int32_t *rowind, int32_t *rowcnt, hipStream_t s);
+hipError_t launch_transpose(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
+                            const double *val, const int64_t *rowptr_f, int32_t *cursor,
+                            int32_t *colind_f, double *val_f, hipStream_t s);
+hipError_t launch_sort_rows(int64_t ntot, const int64_t *rowptr_f, int32_t *colind_f,
+                            double *val_f, int32_t *long_rows, int32_t *n_long, hipStream_t s);
+hipError_t launch_level_count(int64_t nrows, const int32_t *lev, int32_t *lcount, hipStream_t s);
+hipError_t launch_level_place(int64_t nrows, const int32_t *lev, const int64_t *lptr,
+                              int32_t *lcursor, int32_t *order, hipStream_t s);
+hipError_t launch_batches(int64_t depth, const int64_t *lptr, int32_t *bcnt, int rpb,
+                          hipStream_t s);
+hipError_t launch_sort_long_rows(const int64_t *rowptr_f, int32_t *colind_f, double *val_f,
+                                 const int32_t *long_rows, const int32_t *n_long, int32_t *tmp_c,
+                                 double *tmp_v, hipStream_t s);
+hipError_t launch_dinv(int64_t ntot, const double *D, double *Dinv, float *Dinv32,
+                       hipStream_t s);
+hipError_t launch_cast32(int64_t n, const double *a, float *b, hipStream_t s);
+hipError_t launch_max_stats(int64_t ntot, const int64_t *uptr, const int32_t *fill_cnt,
+                            const int32_t *colcnt, const int32_t *lev, unsigned long long *out,
+                            hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// --- solve.hip ---
+struct SolveArgs {
+  int64_t n;             // solved rows (labels 0..n-1)
+  int32_t nrhs;
+  const int64_t *rowptr_f; const int32_t *colind_f;  // CSR of F
+  const int64_t *colptr; const int32_t *rowind;      // CSC of F
+  const double *val_f, *val, *Dinv;                  // FP64 values
+  const float *val_f32, *val32, *Dinv32;             // FP32 copies
+  const int32_t *order;  // rows by ascending level
+  const int64_t *bptr;   // batch prefix over levels [depth+1]
+  const int64_t *lptr;   // row prefix over levels [depth+1]
+  int64_t depth, nbatch;
+  const int32_t *perm;   // vertex -> label
+  const int32_t *iperm;  // label -> vertex
+  const int *skip;       // device flag: nonzero => return immediately
+  int *err;              // watchdog flag (set when a wait exceeds the deadline)
+  int *claim;            // batch counters: forward [0], backward [kTailStride]
+  uint64_t timeout_ticks;
+};
+hipError_t launch_trsv_fwd(const SolveArgs &a, const double *r, void *y, void *x, int prec,
+                           int waves, hipStream_t s);
+hipError_t launch_trsv_bwd(const SolveArgs &a, void *y, void *x, double *z, int prec, int waves,
+                           hipStream_t s);
+int trsv_max_waves();
+constexpr int kRowsPerBatch = 16;  // rows one wave solves together (4 lanes each)
+int pcg_partials();
+hipError_t pcg_launch_init(int64_t n, const double *b, double *x, double *r, double *partial,
+                           double *st, int *ist, hipStream_t s);
+hipError_t pcg_launch_rz(int64_t n, const double *r, const double *z, double *p, double *partial,
+                         double *st, int *ist, int first, hipStream_t s);
+hipError_t pcg_launch_step(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                           double *x, double *r, double *p, double *q, double *partial, double *st,
+                           int *ist, hipStream_t s);
+hipError_t pcg_launch_true_res(int64_t n, const int64_t *rowptr, const int32_t *col,
+                               const double *val, const double *x, const double *b, double *tmp,
+                               double *partial, double *st, int *ist, hipStream_t s);
+hipError_t launch_comp_init(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
+                            int32_t *parent, hipStream_t s);
+hipError_t launch_comp_jump(int64_t ntot, const int32_t *src, int32_t *dst, int *changed,
+                            hipStream_t s);
+hipError_t launch_comp_check(int64_t n, int64_t ground, const int32_t *perm, const int32_t *root,
+                             const double *b, double *sum, double *sabs, int *bad, hipStream_t s);
+
+}  // namespace parac
+
+// the opaque handle
+struct parac_factor_s {
+  int64_t n = 0, ntot = 0;
+  int32_t mode = 0;
+  int64_t nnz_off = 0, depth = 0, nbatch = 0;
+  parac_factor_stats stats{};
+  // device arrays
+  int32_t *perm = nullptr, *iperm = nullptr;
+  int64_t *colptr = nullptr;
+  int32_t *rowind = nullptr;
+  double *val = nullptr;
+  int64_t *rowptr_f = nullptr;
+  int32_t *colind_f = nullptr;
+  double *val_f = nullptr;
+  double *D = nullptr, *Dinv = nullptr;
+  float *val32 = nullptr, *val_f32 = nullptr, *Dinv32 = nullptr;
+  int32_t *lev = nullptr, *order = nullptr, *root = nullptr;
+  int64_t *lptr = nullptr, *bptr = nullptr;
+  // solve work vectors (label space, sentinel-filled between solves)
+  void *wy64 = nullptr, *wx64 = nullptr, *wy32 = nullptr, *wx32 = nullptr;
+  int trsv_waves = 0;
+  int *err = nullptr;    // watchdog flag of the triangular solves
+  int *claim = nullptr;  // batch counters of the triangular solves
+  std::vector<void *> owned;
+};

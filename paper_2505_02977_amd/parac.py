@@ -1,0 +1,201 @@
+"""Thin Python binding of the C ABI declared in ``include/parac.h``.
+
+Argument marshalling only: every step of the factorisation and the solves
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+stream.  The library must be built (``paper_2505_02977_amd/build.py``); if it
+is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libparac.so")
+
+OK, EINVAL, ENOTLAP, EPOOL, ENOMEM, ETIMEOUT, EDEVICE, EINCONSISTENT, ENOCONV, EINTERNAL = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+MODE_AUTO, MODE_LAPLACIAN, MODE_SDDM = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class ParacError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class parac_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class parac_factor_opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("perm", C.c_void_p), ("mode", C.c_int32),
+                ("pool_factor", C.c_double), ("workers", C.c_int32), ("keep_fp32", C.c_int32),
+                ("timeout_s", C.c_double)]
+
+
+class parac_factor_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ntot", C.c_int64), ("mode", C.c_int32),
+                ("nnz_off", C.c_int64), ("n_input_edges", C.c_int64), ("n_fill", C.c_int64),
+                ("max_gather", C.c_int64), ("max_deg", C.c_int64), ("depth", C.c_int64),
+                ("n_zero_pivots", C.c_int64), ("workers", C.c_int32), ("retries", C.c_int32),
+                ("pool_factor", C.c_double), ("ms_setup", C.c_double),
+                ("ms_eliminate", C.c_double), ("ms_finalize", C.c_double),
+                ("ms_total", C.c_double)]
+
+
+class parac_pcg_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32),
+                ("check_every", C.c_int32), ("timing", C.c_int32)]
+
+
+class parac_pcg_stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("relres", C.c_double),
+                ("true_relres", C.c_double), ("ms_total", C.c_double), ("ms_apply", C.c_double),
+                ("applies", C.c_int32)]
+
+
+class parac_request(C.Structure):
+    _fields_ = [("A", parac_csr), ("perm", C.c_void_p), ("b", C.c_void_p), ("x", C.c_void_p),
+                ("seed", C.c_uint64), ("rtol", C.c_double), ("arrival_s", C.c_double)]
+
+
+class parac_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("true_relres", C.c_double),
+                ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("bytes_resident", C.c_int64)]
+
+
+class parac_serve_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("precision", C.c_int32),
+                ("maxit", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libparac.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libparac.so is not built: run paper_2505_02977_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.parac_factor.argtypes = [C.POINTER(parac_csr), C.POINTER(parac_factor_opts), P,
+                                   C.POINTER(P)]
+        L.parac_factor_info.argtypes = [P, C.POINTER(parac_factor_stats)]
+        L.parac_factor_export.argtypes = [P, P, P, P, P, P]
+        L.parac_apply.argtypes = [P, P, P, C.c_int64, C.c_int32, P]
+        L.parac_pcg.argtypes = [C.POINTER(parac_csr), P, P, P, C.c_int64,
+                                C.POINTER(parac_pcg_opts), C.POINTER(parac_pcg_stats), P]
+        L.parac_serve.argtypes = [C.POINTER(parac_request), C.c_int64,
+                                  C.POINTER(parac_serve_opts), C.POINTER(parac_result)]
+        L.parac_factor_free.argtypes = [P]
+        L.parac_status_str.restype = C.c_char_p
+        L.parac_status_str.argtypes = [C.c_int]
+        L.parac_last_error.restype = C.c_char_p
+        for name in ("parac_factor", "parac_factor_info", "parac_factor_export", "parac_apply",
+                     "parac_pcg", "parac_serve"):
+            getattr(L, name).restype = C.c_int
+        L.parac_factor_free.restype = None
+        _lib = L
+    return _lib
+
+
+def _raise(st):
+    if st != OK:
+        raise ParacError(st, lib().parac_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceCSR:
+    """A CSR matrix resident on the device (torch tensors) and its ABI view."""
+
+    def __init__(self, A, device="cuda"):
+        import torch
+        self.n = int(A.n)
+        self.rowptr = torch.as_tensor(np.ascontiguousarray(A.rowptr, np.int64), device=device)
+        self.col = torch.as_tensor(np.ascontiguousarray(A.col, np.int32), device=device)
+        self.val = torch.as_tensor(np.ascontiguousarray(A.val, np.float64), device=device)
+        self.c = parac_csr(self.n, int(self.col.numel()), self.rowptr.data_ptr(),
+                           self.col.data_ptr(), self.val.data_ptr(), 1)
+
+
+class Factor:
+    """Owns a parac_factor_t."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.parac_factor_free(self.h)
+            self.h = None
+
+    def info(self) -> dict:
+        s = parac_factor_stats()
+        _raise(lib().parac_factor_info(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in parac_factor_stats._fields_}
+
+    def export(self):
+        """(colptr, rowind, val, D, level) as numpy arrays (label space)."""
+        s = self.info()
+        ntot, nnz = s["ntot"], s["nnz_off"]
+        colptr = np.zeros(ntot + 1, np.int64)
+        rowind = np.zeros(max(nnz, 1), np.int32)
+        val = np.zeros(max(nnz, 1), np.float64)
+        D = np.zeros(max(ntot, 1), np.float64)
+        lev = np.zeros(max(ntot, 1), np.int32)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        _raise(lib().parac_factor_export(self.h, p(colptr), p(rowind), p(val), p(D), p(lev)))
+        return colptr, rowind[:nnz], val[:nnz], D[:ntot], lev[:ntot]
+
+
+def parac_factor(A: DeviceCSR, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, workers=0,
+                 keep_fp32=False, timeout_s=30.0, stream=None) -> Factor:
+    import torch
+    pt = None
+    if perm is not None:
+        pt = torch.as_tensor(np.ascontiguousarray(perm, np.int32), device=A.rowptr.device)
+    o = parac_factor_opts(int(seed) & (2**64 - 1), pt.data_ptr() if pt is not None else None,
+                          mode, pool_factor, workers, 1 if keep_fp32 else 0, timeout_s)
+    h = C.c_void_p()
+    _raise(lib().parac_factor(C.byref(A.c), C.byref(o), _stream(stream), C.byref(h)))
+    return Factor(h)
+
+
+def parac_apply(f: Factor, r, z, precision=PREC_FP64, stream=None):
+    """z = M^+ r for device tensors r, z (float64, length n)."""
+    _raise(lib().parac_apply(f.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), 1,
+                             precision, _stream(stream)))
+    return z
+
+
+def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=1, rtol=1e-6, maxit=10000,
+              precision=PREC_FP64, check_every=8, timing=False, stream=None):
+    """PCG (x0 = 0) on device tensors b, x (n x nrhs row-major).  Returns a
+    list of per-column stat dicts; raises on EINVAL/EINCONSISTENT."""
+    o = parac_pcg_opts(rtol, maxit, precision, check_every, 1 if timing else 0)
+    st = (parac_pcg_stats * nrhs)()
+    rc = lib().parac_pcg(C.byref(A.c), f.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                         nrhs, C.byref(o), st, _stream(stream))
+    if rc not in (OK, ENOCONV):
+        _raise(rc)
+    return [dict(status=s.status, iterations=s.iterations, relres=s.relres,
+                 true_relres=s.true_relres, ms_total=s.ms_total, ms_apply=s.ms_apply,
+                 applies=s.applies) for s in st]
+
+
+def status_str(st):
+    return lib().parac_status_str(st).decode()

@@ -1,0 +1,136 @@
+"""GPU parity of the factor: the FP64 F and D built by the persistent HIP
+elimination are identical, bit for bit, to the CPU oracle's, on the same
+seeded inputs -- whatever the grid size, the pool size or the timing."""
+import numpy as np
+import pytest
+
+from paper_2505_02977_amd import inputs
+from tests.gpu_util import compare_factor, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def lap(n, i, j, w, excess=None):
+    return inputs.laplacian_from_edges(n, i, j, w, excess)
+
+
+def gpu_factor(A, perm, seed, **kw):
+    from paper_2505_02977_amd import parac
+    dA = parac.DeviceCSR(A)
+    return parac.parac_factor(dA, perm=perm, seed=seed, **kw)
+
+
+def case_graphs():
+    rng = np.random.default_rng(77)
+    out = []
+    # tiny and ragged sizes
+    for n in (1, 2, 3, 5, 17, 63, 64, 65, 130):
+        if n == 1:
+            A = lap(1, np.zeros(0, int), np.zeros(0, int), np.zeros(0))
+        else:
+            i, j = inputs.connected_random_edges(n, 2 * n, rng)
+            A = lap(n, i, j, rng.uniform(0.01, 10.0, len(i)))
+        out.append(("rand%d" % n, A, None))
+    # unit weights: ties in the sampling order
+    i, j = inputs.grid2d_edges(20, 13)
+    out.append(("grid_unit", lap(260, i, j, np.ones(len(i))), None))
+    # a hub: gathered neighbourhoods beyond one wave (multi-tile suffix sums)
+    n = 400
+    i = np.concatenate([np.zeros(299, int), np.arange(1, 399)])
+    j = np.concatenate([np.arange(1, 300), np.arange(2, 400)])
+    i, j = inputs.dedupe_edges(i, j)
+    out.append(("hub", lap(n, i, j, rng.uniform(0.1, 1.0, len(i))), None))
+    # SDDM with a ground vertex
+    n = 300
+    i, j = inputs.connected_random_edges(n, 3 * n, rng)
+    ex = np.zeros(n)
+    hot = rng.choice(n, 30, replace=False)
+    ex[hot] = rng.random(30)
+    out.append(("sddm", lap(n, i, j, rng.uniform(0.1, 2.0, len(i)), ex), ex))
+    # two components
+    i1, j1 = inputs.connected_random_edges(100, 200, rng)
+    i2, j2 = inputs.connected_random_edges(80, 150, rng)
+    i = np.concatenate([i1, i2 + 100])
+    j = np.concatenate([j1, j2 + 100])
+    out.append(("two_comp", lap(180, i, j, rng.uniform(0.5, 2, len(i))), None))
+    return out
+
+
+@pytest.mark.parametrize("name,A,ex", case_graphs(), ids=lambda v: v if isinstance(v, str) else "")
+def test_factor_bit_identical(orc, name, A, ex):
+    need_gpu()
+    rng = np.random.default_rng(sum(map(ord, name)) * 131 + A.n)
+    perm = rng.permutation(A.n).astype(np.int32)
+    seed = 12345 + A.n
+    ref = orc.factor(A, perm=perm, seed=seed)
+    assert ref.status == 0
+    f = gpu_factor(A, perm, seed)
+    info = f.info()
+    assert info["nnz_off"] == ref.nnz_off
+    assert info["n_fill"] == ref.stats["n_fill"]
+    assert info["max_deg"] == ref.stats["max_deg"]
+    assert info["depth"] == ref.stats["depth"]
+    compare_factor(f, ref)
+
+
+def test_grid2d_workload_bit_identical(orc):
+    need_gpu()
+    W = inputs.grid2d_workload()
+    ref = orc.factor(W.A, perm=W.perm, seed=W.seed)
+    f = gpu_factor(W.A, W.perm, W.seed)
+    compare_factor(f, ref)
+
+
+@pytest.mark.parametrize("workers", [64, 128, 1024, 0])
+def test_grid_size_invariance(orc, workers):
+    """Different persistent grids interleave pivots differently; the factor
+    must not change (a race detector by differential testing)."""
+    need_gpu()
+    rng = np.random.default_rng(5)
+    i, j = inputs.grid3d_edges(14, 13, 12)
+    n = 14 * 13 * 12
+    A = lap(n, i, j, 10.0 ** rng.uniform(-2, 2, len(i)))
+    perm = rng.permutation(n).astype(np.int32)
+    ref = orc.factor(A, perm=perm, seed=99)
+    f = gpu_factor(A, perm, 99, workers=workers)
+    compare_factor(f, ref)
+
+
+def test_pool_exhaustion_retry_is_exact(orc):
+    """A pool far too small forces EPOOL and internal retries with larger
+    pools; the result is unchanged because storage does not enter the
+    arithmetic."""
+    need_gpu()
+    rng = np.random.default_rng(6)
+    n = 3000
+    i, j = inputs.connected_random_edges(n, 6 * n, rng)
+    A = lap(n, i, j, rng.uniform(0.1, 1, len(i)))
+    perm = rng.permutation(n).astype(np.int32)
+    ref = orc.factor(A, perm=perm, seed=3)
+    f = gpu_factor(A, perm, 3, pool_factor=0.02, workers=64)
+    assert f.info()["retries"] >= 1
+    compare_factor(f, ref)
+
+
+def test_errors_match_oracle(orc):
+    need_gpu()
+    from paper_2505_02977_amd import parac
+    i, j = inputs.path_edges(6)
+    good = lap(6, i, j, np.ones(5))
+    bad_sign = lap(6, i, j, np.ones(5))
+    bad_sign.val = bad_sign.val.copy()
+    bad_sign.val[1] = 0.5
+    asym = lap(6, i, j, np.ones(5))
+    asym.val = asym.val.copy()
+    asym.val[1] = -0.75
+    asym.val[0] = 0.75
+    for A, perm in ((bad_sign, None), (asym, None), (good, np.array([0, 1, 2, 3, 4, 4]))):
+        st_ref = orc.factor(A, perm=perm).status
+        with pytest.raises(parac.ParacError) as e:
+            gpu_factor(A, perm, 1)
+        assert e.value.status == st_ref
+    # Laplacian mode forced on an SDDM matrix
+    S = lap(6, i, j, np.ones(5), excess=np.array([0.5, 0, 0, 0, 0, 0]))
+    with pytest.raises(parac.ParacError) as e:
+        gpu_factor(S, None, 1, mode=parac.MODE_LAPLACIAN)
+    assert e.value.status == parac.ENOTLAP
