@@ -235,8 +235,11 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   // per-attempt state
   const int32_t cap_q = (int32_t)((ntot + kSubQueues - 1) / kSubQueues);
   int32_t *q = tmp.alloc<int32_t>((int64_t)cap_q * kSubQueues, "queue");
-  int32_t *qtail = tmp.alloc<int32_t>(2 * kSubQueues * kTailStride, "qtail");
+  int32_t *qtail = tmp.alloc<int32_t>(3 * kSubQueues * kTailStride + 3 * kTailStride, "qtail");
   int32_t *qhead = qtail + kSubQueues * kTailStride;
+  int32_t *qdone = qhead + kSubQueues * kTailStride;
+  int32_t *tqc = qdone + kSubQueues * kTailStride;  // tail head, tail, count
+  int32_t *tq = tmp.alloc<int32_t>(ntot, "tail queue");
   int32_t *fill_cnt = tmp.alloc<int32_t>(ntot, "fill_cnt");
   Rec *inl = tmp.alloc<Rec>(ntot * kInline, "inline inbox");
   int32_t *ptab = tmp.alloc<int32_t>(ntot * (kPages - 1), "page table");
@@ -276,12 +279,14 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     chk(hipMemsetAsync(dp, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
     chk(launch_upper_count(n, rowptr, col, val, F->perm, excess, sddm, ucnt, dp, s), "upper_count");
     chk(hipMemsetAsync(q, 0xff, (size_t)cap_q * kSubQueues * sizeof(int32_t), s), "memset");
-    chk(hipMemsetAsync(qtail, 0, 2 * kSubQueues * kTailStride * sizeof(int32_t), s), "memset");
+    chk(hipMemsetAsync(qtail, 0, (3 * kSubQueues * kTailStride + 3 * kTailStride) * sizeof(int32_t), s),
+        "memset");
+    chk(hipMemsetAsync(tq, 0xff, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
     chk(hipMemsetAsync(fill_cnt, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
     chk(hipMemsetAsync(ptab, 0xff, std::max<int64_t>(ntot * (kPages - 1), 1) * sizeof(int32_t), s),
         "memset");
     chk(hipMemsetAsync(F->lev, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
-    chk(hipMemsetAsync(colcnt, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
+    chk(hipMemsetAsync(colcnt, 0xff, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
     chk(hipMemsetAsync(tops, 0, 8 * sizeof(unsigned long long), s), "memset");
     chk(hipMemsetAsync(err, 0, sizeof(int), s), "memset");
     chk(launch_queue_init(ntot, dp, q, qtail, cap_q, s), "queue_init");
@@ -321,6 +326,24 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     ea.nworkers = workers;
     ea.pg_chunk = pg_chunk;
     ea.f_chunk = f_chunk;
+    ea.done = qdone;
+    {
+      // the wide kernel leaves the last `tail_fraction` of the pivots (the
+      // thin end of the dependency DAG) to the single-workgroup kernel
+      const double tf = opt.tail_fraction == 0.0 ? 0.04 : opt.tail_fraction;
+      if (tf >= 1.0) {
+        ea.stop_at = 0;
+      } else if (tf < 0.0) {
+        ea.stop_at = ntot + 1;
+      } else {
+        const int64_t left = (int64_t)(tf * (double)ntot);
+        ea.stop_at = left < 256 ? ntot + 1 : ntot - left;
+      }
+    }
+    ea.tq = tq;
+    ea.tq_head = tqc;
+    ea.tq_tail = tqc + kTailStride;
+    ea.tq_count = tqc + 2 * kTailStride;
     if (ntot > 0) chk(launch_eliminate(ea, wgs, s), "eliminate");
     chk(hipEventRecord(ev.e[2], s), "event");
     int herr = 0;
@@ -365,19 +388,19 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   int32_t *rowcnt = tmp.alloc<int32_t>(ntot, "rowcnt");
   chk(hipMemsetAsync(rowcnt, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
   chk(launch_row_count(nnz_off, F->rowind, rowcnt, s), "row_count");
-  F->rowptr_f = tmp.alloc<int64_t>(ntot + 1, "rowptr_f");
-  chk(scan_counts(rowcnt, F->rowptr_f, ntot, scan_tmp, scan_bytes, s), "scan");
+  int64_t *rowptr_f = tmp.alloc<int64_t>(ntot + 1, "rowptr_f");
+  chk(scan_counts(rowcnt, rowptr_f, ntot, scan_tmp, scan_bytes, s), "scan");
   chk(hipMemsetAsync(rowcnt, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
-  F->colind_f = tmp.alloc<int32_t>(nnz_off, "colind_f");
-  F->val_f = tmp.alloc<double>(nnz_off, "val_f");
+  int32_t *colind_f = tmp.alloc<int32_t>(nnz_off, "colind_f");
+  double *val_f = tmp.alloc<double>(nnz_off, "val_f");
   int32_t *long_rows = tmp.alloc<int32_t>(ntot, "long rows");
   if (ntot > 0) {
-    chk(launch_transpose(ntot, F->colptr, F->rowind, F->val, F->rowptr_f, rowcnt, F->colind_f,
-                         F->val_f, s),
+    chk(launch_transpose(ntot, F->colptr, F->rowind, F->val, rowptr_f, rowcnt, colind_f,
+                         val_f, s),
         "transpose");
-    chk(launch_sort_rows(ntot, F->rowptr_f, F->colind_f, F->val_f, long_rows, flags + 2, s),
+    chk(launch_sort_rows(ntot, rowptr_f, colind_f, val_f, long_rows, flags + 2, s),
         "sort_rows");
-    chk(launch_sort_long_rows(F->rowptr_f, F->colind_f, F->val_f, long_rows, flags + 2, frow, fval,
+    chk(launch_sort_long_rows(rowptr_f, colind_f, val_f, long_rows, flags + 2, frow, fval,
                               s),
         "sort_long_rows");
   }
@@ -394,27 +417,50 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   int32_t *lcount = tmp.alloc<int32_t>(depth + 1, "lcount");
   F->lptr = tmp.alloc<int64_t>(depth + 2, "lptr");
   F->order = tmp.alloc<int32_t>(n, "order");
-  int32_t *bcnt = tmp.alloc<int32_t>(depth + 1, "bcnt");
-  F->bptr = tmp.alloc<int64_t>(depth + 2, "bptr");
   chk(hipMemsetAsync(lcount, 0, (depth + 1) * sizeof(int32_t), s), "memset");
   if (n > 0) {
     chk(launch_level_count(n, F->lev, lcount, s), "level_count");
     chk(scan_counts(lcount, F->lptr, depth, scan_tmp, scan_bytes, s), "scan");
     chk(hipMemsetAsync(lcount, 0, (depth + 1) * sizeof(int32_t), s), "memset");
     chk(launch_level_place(n, F->lev, F->lptr, lcount, F->order, s), "level_place");
-    chk(launch_batches(depth, F->lptr, bcnt, kRowsPerBatch, s), "batches");
-    chk(scan_counts(bcnt, F->bptr, depth, scan_tmp, scan_bytes, s), "scan");
-    F->nbatch = read1(F->bptr + depth, s);
+    F->hlptr.resize(depth + 1);
+    chk(hipMemcpyAsync(F->hlptr.data(), F->lptr, (depth + 1) * sizeof(int64_t),
+                       hipMemcpyDeviceToHost, s),
+        "read");
+    chk(hipStreamSynchronize(s), "sync");
+    // the thin tail: the smallest level from which every level has at most
+    // kTailWidth rows
+    int64_t L0 = depth;
+    while (L0 > 0 && F->hlptr[L0] - F->hlptr[L0 - 1] <= kTailWidth) --L0;
+    F->L0 = L0;
+    // level-ordered copies of the rows (forward) and columns (backward) of F
+    int32_t *flen = tmp.alloc<int32_t>(n, "flen");
+    int32_t *blen = tmp.alloc<int32_t>(n, "blen");
+    chk(launch_level_layout(n, F->order, rowptr_f, F->colptr, F->rowind, flen, blen, s),
+        "level_layout");
+    F->lf_ptr = tmp.alloc<int64_t>(n + 1, "lf_ptr");
+    F->lb_ptr = tmp.alloc<int64_t>(n + 1, "lb_ptr");
+    chk(scan_counts(flen, F->lf_ptr, n, scan_tmp, scan_bytes, s), "scan");
+    chk(scan_counts(blen, F->lb_ptr, n, scan_tmp, scan_bytes, s), "scan");
+    const int64_t nf = read1(F->lf_ptr + n, s), nbk = read1(F->lb_ptr + n, s);
+    F->lf_idx = tmp.alloc<int32_t>(nf, "lf_idx");
+    F->lf_val = tmp.alloc<double>(nf, "lf_val");
+    F->lb_idx = tmp.alloc<int32_t>(nbk, "lb_idx");
+    F->lb_val = tmp.alloc<double>(nbk, "lb_val");
+    chk(launch_level_copy(n, F->order, rowptr_f, colind_f, val_f, F->colptr, F->rowind,
+                          F->val, F->lf_ptr, F->lb_ptr, F->lf_idx, F->lf_val, F->lb_idx,
+                          F->lb_val, s),
+        "level_copy");
+    if (opt.keep_fp32) {
+      F->lf_val32 = tmp.alloc<float>(nf, "lf_val32");
+      F->lb_val32 = tmp.alloc<float>(nbk, "lb_val32");
+      chk(launch_cast32(nf, F->lf_val, F->lf_val32, s), "cast");
+      chk(launch_cast32(nbk, F->lb_val, F->lb_val32, s), "cast");
+    }
   }
   F->Dinv = tmp.alloc<double>(ntot, "Dinv");
   float *Dinv32 = nullptr;
-  if (opt.keep_fp32) {
-    Dinv32 = tmp.alloc<float>(ntot, "Dinv32");
-    F->val32 = tmp.alloc<float>(nnz_off, "val32");
-    F->val_f32 = tmp.alloc<float>(nnz_off, "val_f32");
-    chk(launch_cast32(nnz_off, F->val, F->val32, s), "cast");
-    chk(launch_cast32(nnz_off, F->val_f, F->val_f32, s), "cast");
-  }
+  if (opt.keep_fp32) Dinv32 = tmp.alloc<float>(ntot, "Dinv32");
   F->Dinv32 = Dinv32;
   if (ntot > 0) chk(launch_dinv(ntot, F->D, F->Dinv, Dinv32, s), "dinv");
   // component roots (last label of each component) by pointer jumping
@@ -458,10 +504,10 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
 
   // keep the handle's arrays; everything else is freed with `tmp`
   for (void *p : {(void *)F->perm, (void *)F->iperm, (void *)F->colptr, (void *)F->rowind,
-                  (void *)F->val, (void *)F->rowptr_f, (void *)F->colind_f, (void *)F->val_f,
-                  (void *)F->D, (void *)F->Dinv, (void *)F->val32, (void *)F->val_f32,
-                  (void *)F->Dinv32, (void *)F->lev, (void *)F->order, (void *)F->root,
-                  (void *)F->lptr, (void *)F->bptr})
+                  (void *)F->val, (void *)F->D, (void *)F->Dinv, (void *)F->Dinv32,
+                  (void *)F->lev, (void *)F->order, (void *)F->root, (void *)F->lptr,
+                  (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
+                  (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
     if (p) tmp.keep(p, F->owned);
   guard.ok = true;
   return F;
@@ -473,52 +519,27 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
 static SolveArgs solve_args(parac_factor_t f, const int *skip) {
   SolveArgs a{};
   a.n = f->n;
-  a.nrhs = 1;
-  a.rowptr_f = f->rowptr_f;
-  a.colind_f = f->colind_f;
-  a.colptr = f->colptr;
-  a.rowind = f->rowind;
-  a.val_f = f->val_f;
-  a.val = f->val;
-  a.Dinv = f->Dinv;
-  a.val_f32 = f->val_f32;
-  a.val32 = f->val32;
-  a.Dinv32 = f->Dinv32;
   a.order = f->order;
-  a.bptr = f->bptr;
   a.lptr = f->lptr;
   a.depth = f->depth;
-  a.nbatch = f->nbatch;
-  a.perm = f->perm;
+  a.L0 = f->L0;
+  a.lf_ptr = f->lf_ptr;
+  a.lf_idx = f->lf_idx;
+  a.lf_val = f->lf_val;
+  a.lf_val32 = f->lf_val32;
+  a.lb_ptr = f->lb_ptr;
+  a.lb_idx = f->lb_idx;
+  a.lb_val = f->lb_val;
+  a.lb_val32 = f->lb_val32;
+  a.Dinv = f->Dinv;
+  a.Dinv32 = f->Dinv32;
   a.iperm = f->iperm;
   a.skip = skip;
-  a.err = f->err;
-  a.claim = f->claim;
-  a.timeout_ticks = (uint64_t)(10.0 * 1000.0 * (double)wall_khz());
   return a;
 }
 
-// label-space work vectors: y all-sentinel, x sentinel on rows < n and 0 at
-// the ground label (its entries of F are dropped but the row exists)
-static void ensure_work(parac_factor_t f, int prec, hipStream_t s) {
-  if (!f->err) {
-    chk(hipMalloc((void **)&f->err, sizeof(int)), "flag");
-    f->owned.push_back(f->err);
-    chk(hipMemsetAsync(f->err, 0, sizeof(int), s), "memset");
-    chk(hipMalloc((void **)&f->claim, 2 * kTailStride * sizeof(int)), "counters");
-    f->owned.push_back(f->claim);
-    chk(hipMemsetAsync(f->claim, 0, 2 * kTailStride * sizeof(int), s), "memset");
-  }
-  if (!f->trsv_waves) {
-    int w = trsv_max_waves();
-    if (w <= 0) throw Err{PARAC_EDEVICE, "occupancy query failed"};
-    // tuning override of the triangular solves' grid (waves)
-    if (const char *e = getenv("PARAC_TRSV_WAVES")) {
-      int v = atoi(e);
-      if (v >= 4) w = std::min(w, v);
-    }
-    f->trsv_waves = w;
-  }
+// label-space work vectors of the two triangular solves
+static void ensure_work(parac_factor_t f, int prec) {
   void **py = prec == PARAC_PREC_MIXED ? &f->wy32 : &f->wy64;
   void **px = prec == PARAC_PREC_MIXED ? &f->wx32 : &f->wx64;
   if (*py) return;
@@ -528,26 +549,16 @@ static void ensure_work(parac_factor_t f, int prec, hipStream_t s) {
   f->owned.push_back(*py);
   chk(hipMalloc(px, m * el), "work vector");
   f->owned.push_back(*px);
-  if (prec == PARAC_PREC_MIXED) {
-    chk(launch_fill_u32((uint32_t *)*py, kSent32, m, s), "fill");
-    chk(launch_fill_u32((uint32_t *)*px, kSent32, m, s), "fill");
-    if (f->ntot > f->n) chk(hipMemsetAsync((float *)*px + f->n, 0, 4, s), "memset");
-  } else {
-    chk(launch_fill_u64((uint64_t *)*py, kSent64, m, s), "fill");
-    chk(launch_fill_u64((uint64_t *)*px, kSent64, m, s), "fill");
-    if (f->ntot > f->n) chk(hipMemsetAsync((double *)*px + f->n, 0, 8, s), "memset");
-  }
 }
 
 static void apply_one(parac_factor_t f, const double *r, double *z, int prec, const int *skip,
                       hipStream_t s) {
   if (f->n == 0) return;
-  ensure_work(f, prec, s);
+  ensure_work(f, prec);
   SolveArgs a = solve_args(f, skip);
   void *y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
   void *x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
-  chk(launch_trsv_fwd(a, r, y, x, prec, f->trsv_waves, s), "trsv_fwd");
-  chk(launch_trsv_bwd(a, y, x, z, prec, f->trsv_waves, s), "trsv_bwd");
+  chk(launch_apply(a, f->hlptr.data(), r, y, x, z, prec, s), "apply");
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +624,6 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
   apply_one(f, r, z, o.precision, ist + 2, s);
   mark();
   ++applies;
-  if (read1(f->err, s)) throw Err{PARAC_ETIMEOUT, "triangular-solve watchdog expired"};
   chk(pcg_launch_rz(n, r, z, p, partial, dst, ist, 1, s), "pcg_rz");
   const int K = o.check_every > 0 ? o.check_every : 8;
   int launched = 0;
@@ -632,7 +642,6 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
     launched += chunk;
     chk(hipMemcpyAsync(hist, ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read");
     chk(hipStreamSynchronize(s), "sync");
-    if (read1(f->err, s)) throw Err{PARAC_ETIMEOUT, "triangular-solve watchdog expired"};
     if (hist[1]) break;
   }
   chk(pcg_launch_true_res(n, A->rowptr, A->col, A->val, x, b, q, partial, dst, ist, s), "true_res");
@@ -641,7 +650,6 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
   chk(hipMemcpyAsync(hst, dst, sizeof(hst), hipMemcpyDeviceToHost, s), "read");
   chk(hipMemcpyAsync(hist, ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read");
   chk(hipStreamSynchronize(s), "sync");
-  if (read1(f->err, s)) throw Err{PARAC_ETIMEOUT, "triangular-solve watchdog expired"};
   const int done = hist[1];
   const double bn = sqrt(hst[0]);
   if (st) {
@@ -725,7 +733,7 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z, int64_t n
     g_last_error = "bad apply arguments";
     return PARAC_EINVAL;
   }
-  if (precision == PARAC_PREC_MIXED && !f->val32) {
+  if (precision == PARAC_PREC_MIXED && !f->Dinv32) {
     g_last_error = "mixed precision needs a factor built with keep_fp32";
     return PARAC_EINVAL;
   }
@@ -740,7 +748,7 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z, int64_t n
   try {
     hipStream_t s = (hipStream_t)stream;
     apply_one(f, r, z, precision, nullptr, s);
-    if (f->n && read1(f->err, s)) throw Err{PARAC_ETIMEOUT, "triangular-solve watchdog expired"};
+    chk(hipStreamSynchronize(s), "sync");
     return PARAC_OK;
   } catch (Err &e) {
     return status_from(e);
@@ -761,7 +769,7 @@ parac_status parac_pcg(const parac_csr *A, parac_factor_t f, const double *b, do
     if (!(opt.rtol >= 0)) opt.rtol = 1e-6;
     if (opt.maxit <= 0) opt.maxit = 10000;
   }
-  if (opt.precision == PARAC_PREC_MIXED && !f->val32) {
+  if (opt.precision == PARAC_PREC_MIXED && !f->Dinv32) {
     g_last_error = "mixed precision needs a factor built with keep_fp32";
     return PARAC_EINVAL;
   }

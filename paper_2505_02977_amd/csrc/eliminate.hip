@@ -158,7 +158,39 @@ __device__ __forceinline__ bool alloc_column(const ElimArgs &a, Worker &wk, int 
   return true;
 }
 
+// Synchronisation policies.  The wide kernel runs on every XCD: a pivot
+// publishes its fill and factor column with an agent-scope release fence and
+// enqueues into the sharded queue.  The tail kernel is one workgroup on one
+// CU: workgroup-scope fences suffice, and it has its own queue.
+struct WideSync {
+  static __device__ __forceinline__ void release() { fence_release(); }
+  static __device__ __forceinline__ void acquire() { fence_acquire(); }
+  static __device__ __forceinline__ bool enqueue(const ElimArgs &a, int32_t u) {
+    const int x = u & (kSubQueues - 1);
+    const int pos = fetch_add(&a.qtail[x * kTailStride], 1);
+    if (pos >= a.cap_q) return false;
+    __hip_atomic_exchange(&a.q[(int64_t)x * a.cap_q + pos], u, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+};
+struct TailSync {
+  static __device__ __forceinline__ void release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  }
+  static __device__ __forceinline__ void acquire() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  static __device__ __forceinline__ bool enqueue(const ElimArgs &a, int32_t u) {
+    const int pos = __hip_atomic_fetch_add(a.tq_tail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (pos >= a.ntot) return false;
+    __hip_atomic_store(&a.tq[pos], u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return true;
+  }
+};
+
 // pivot-edge deletion of §III: d(u) -= m(u,k); enqueue on reaching zero
+template <class Sync>
 __device__ __forceinline__ bool decrement(const ElimArgs &a, bool valid, int32_t u, int m) {
   bool enq = false, bad = false;
   if (valid) {
@@ -171,13 +203,9 @@ __device__ __forceinline__ bool decrement(const ElimArgs &a, bool valid, int32_t
     return false;
   }
   if (__any(enq)) {
-    fence_acq_rel();
-    if (enq) {
-      int x = u & (kSubQueues - 1);
-      int pos = fetch_add(&a.qtail[x * kTailStride], 1);
-      if (pos < a.cap_q) st_relaxed(&a.q[(int64_t)x * a.cap_q + pos], u);
-      else bad = true;
-    }
+    // no fence here: the consumer synchronises with every producer of u
+    // through u's counter (see claim_pivot); the slot only carries the label
+    if (enq && !Sync::enqueue(a, u)) bad = true;
     if (__any(bad)) {
       set_error(a.err, PARAC_EINTERNAL);
       return false;
@@ -189,6 +217,7 @@ __device__ __forceinline__ bool decrement(const ElimArgs &a, bool valid, int32_t
 // ---------------------------------------------------------------------------
 // neighbourhoods of at most 64 gathered entries: one entry per lane
 // ---------------------------------------------------------------------------
+template <class Sync>
 __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
                             int levk, uint64_t deadline) {
   const int l = lane();
@@ -317,16 +346,86 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     a.colcnt[k] = d;
   }
   // 6. publish, then delete the pivot's edges
-  fence_release();
-  return decrement(a, l < d, mu, mm);
+  Sync::release();
+  return decrement<Sync>(a, l < d, mu, mm);
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (key, payload) pairs by one wave, ping-ponging
+// between two scratch buffers: 8-bit digits, a 256-bucket histogram in the
+// wave's LDS slice, in-wave ranks by matching digits with ballots.  Returns
+// true when the sorted data ends in the first buffer.
+// ---------------------------------------------------------------------------
+constexpr int kRankMax = 2048;  // above this the radix sort replaces ranking
+
+__device__ __forceinline__ void lds_sync() { fence_wave_local(); }
+
+__device__ bool wave_radix_sort(uint64_t *ka, uint64_t *va, uint64_t *kb, uint64_t *vb, int n,
+                                const int *shifts, int npass, int *h) {
+  const int l = lane();
+  bool in_a = true;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int sh = shifts[pass];
+    uint64_t *ks = in_a ? ka : kb, *vs = in_a ? va : vb;
+    uint64_t *kd = in_a ? kb : ka, *vd = in_a ? vb : va;
+    for (int t = l; t < 256; t += kWave) h[t] = 0;
+    lds_sync();
+    for (int base = 0; base < n; base += kWave) {
+      const int i = base + l;
+      if (i < n) atomicAdd(&h[(int)((ks[i] >> sh) & 255)], 1);
+    }
+    lds_sync();
+    // exclusive scan of the 256 buckets, four per lane
+    int c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
+    int tot = c0 + c1 + c2 + c3, incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      int y = __shfl_up(incl, o, kWave);
+      if (l >= o) incl += y;
+    }
+    const int ex = incl - tot;
+    lds_sync();
+    h[4 * l] = ex;
+    h[4 * l + 1] = ex + c0;
+    h[4 * l + 2] = ex + c0 + c1;
+    h[4 * l + 3] = ex + c0 + c1 + c2;
+    lds_sync();
+    // stable scatter, 64 elements at a time in index order
+    for (int base = 0; base < n; base += kWave) {
+      const int i = base + l;
+      const bool valid = i < n;
+      const uint64_t k = valid ? ks[i] : 0;
+      const uint64_t v = valid ? vs[i] : 0;
+      const int d = (int)((k >> sh) & 255);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bm = __ballot(valid && ((d >> b) & 1));
+        peers &= ((d >> b) & 1) ? bm : ~bm;
+      }
+      const int off = valid ? h[d] : 0;
+      lds_sync();
+      if (valid) {
+        const int rank = __popcll(peers & lanemask_lt());
+        kd[off + rank] = k;
+        vd[off + rank] = v;
+        if (rank == 0) h[d] = off + __popcll(peers);
+      }
+      lds_sync();
+    }
+    fence_wave_local();
+    in_a = !in_a;
+  }
+  return in_a;
 }
 
 // ---------------------------------------------------------------------------
 // larger neighbourhoods: the same steps over wave-private scratch in HBM;
 // sorting by rank (keys are unique), suffix sums tile by tile
 // ---------------------------------------------------------------------------
+template <class Sync>
 __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
-                            int levk, uint64_t deadline) {
+                            int levk, uint64_t deadline, int *h) {
   const int l = lane();
   const int64_t bytes = (((int64_t)g * 68) + 255) & ~(int64_t)255;
   if (bytes > wk.sc_size) {
@@ -371,19 +470,36 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     wA[i] = w;
   }
   fence_wave_local();
-  // 2. sort by (u, src): rank = number of smaller keys
-  for (int ib = 0; ib < g; ib += kWave) {
-    const int i = ib + l;
-    const uint64_t ki = i < g ? keyA[i] : ~0ull;
-    int rank = 0;
-    for (int jb = 0; jb < g; jb += kWave) {
-      const uint64_t kj = (jb + l < g) ? keyA[jb + l] : ~0ull;
-      const int lim = g - jb < kWave ? g - jb : kWave;
-      for (int jj = 0; jj < lim; ++jj) rank += readlane_u64(kj, jj) < ki ? 1 : 0;
+  // 2. sort by (u, src)
+  uint64_t *keyS = keyB;   // sorted keys and weights end up here
+  double *wS = wB;
+  if (g <= kRankMax) {
+    // rank = number of smaller keys (keys are unique)
+    for (int ib = 0; ib < g; ib += kWave) {
+      const int i = ib + l;
+      const uint64_t ki = i < g ? keyA[i] : ~0ull;
+      int rank = 0;
+      for (int jb = 0; jb < g; jb += kWave) {
+        const uint64_t kj = (jb + l < g) ? keyA[jb + l] : ~0ull;
+        const int lim = g - jb < kWave ? g - jb : kWave;
+        for (int jj = 0; jj < lim; ++jj) rank += readlane_u64(kj, jj) < ki ? 1 : 0;
+      }
+      if (i < g) {
+        keyB[rank] = ki;
+        wB[rank] = wA[i];
+      }
     }
-    if (i < g) {
-      keyB[rank] = ki;
-      wB[rank] = wA[i];
+  } else {
+    // radix passes over the bits a key can use: src + 1 in the low word,
+    // u in the high word, both below 2^bits(ntot + 1)
+    const int nb = 32 - __clz(a.ntot + 1);
+    int shifts[8], np = 0;
+    for (int b = 0; b < nb; b += 8) shifts[np++] = b;
+    for (int b = 0; b < nb; b += 8) shifts[np++] = 32 + b;
+    const bool in_a = wave_radix_sort(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g, shifts, np, h);
+    if (in_a) {
+      keyS = keyA;
+      wS = wA;
     }
   }
   fence_wave_local();
@@ -391,7 +507,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   {
     bool bad = false;
     for (int i = l; i < g; i += kWave) {
-      int32_t u = (int32_t)(keyB[i] >> 32);
+      int32_t u = (int32_t)(keyS[i] >> 32);
       bad |= u <= k || u >= a.ntot;
     }
     if (__any(bad)) {
@@ -404,16 +520,16 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   for (int ib = 0; ib < g; ib += kWave) {
     const int i = ib + l;
     const bool valid = i < g;
-    const int32_t u = valid ? (int32_t)(keyB[i] >> 32) : -1;
-    const int32_t up = (valid && i > 0) ? (int32_t)(keyB[i - 1] >> 32) : -1;
+    const int32_t u = valid ? (int32_t)(keyS[i] >> 32) : -1;
+    const int32_t up = (valid && i > 0) ? (int32_t)(keyS[i - 1] >> 32) : -1;
     const bool head = valid && (i == 0 || up != u);
     double acc = 0.0;
     int m = 0;
     if (head) {
-      acc = wB[i];
+      acc = wS[i];
       m = 1;
-      for (int jx = i + 1; jx < g && (int32_t)(keyB[jx] >> 32) == u; ++jx) {
-        acc = acc + wB[jx];
+      for (int jx = i + 1; jx < g && (int32_t)(keyS[jx] >> 32) == u; ++jx) {
+        acc = acc + wS[jx];
         ++m;
       }
     }
@@ -427,25 +543,44 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     d += __popcll(hm);
   }
   fence_wave_local();
-  // 3. sampling order by rank on (w, u)
-  for (int ib = 0; ib < d; ib += kWave) {
-    const int i = ib + l;
-    const uint64_t wi = i < d ? dbits(mw[i]) : ~0ull;
-    const int32_t ui = i < d ? mu[i] : 0x7fffffff;
-    int rank = 0;
-    for (int jb = 0; jb < d; jb += kWave) {
-      const uint64_t wj = (jb + l < d) ? dbits(mw[jb + l]) : ~0ull;
-      const int32_t uj = (jb + l < d) ? mu[jb + l] : 0x7fffffff;
-      const int lim = d - jb < kWave ? d - jb : kWave;
-      for (int jj = 0; jj < lim; ++jj) {
-        uint64_t ww = readlane_u64(wj, jj);
-        int32_t uu = __builtin_amdgcn_readlane(uj, jj);
-        rank += less_wu(ww, uu, wi, ui) ? 1 : 0;
+  // 3. sampling order (w asc, u asc)
+  if (d <= kRankMax) {
+    for (int ib = 0; ib < d; ib += kWave) {
+      const int i = ib + l;
+      const uint64_t wi = i < d ? dbits(mw[i]) : ~0ull;
+      const int32_t ui = i < d ? mu[i] : 0x7fffffff;
+      int rank = 0;
+      for (int jb = 0; jb < d; jb += kWave) {
+        const uint64_t wj = (jb + l < d) ? dbits(mw[jb + l]) : ~0ull;
+        const int32_t uj = (jb + l < d) ? mu[jb + l] : 0x7fffffff;
+        const int lim = d - jb < kWave ? d - jb : kWave;
+        for (int jj = 0; jj < lim; ++jj) {
+          uint64_t ww = readlane_u64(wj, jj);
+          int32_t uu = __builtin_amdgcn_readlane(uj, jj);
+          rank += less_wu(ww, uu, wi, ui) ? 1 : 0;
+        }
+      }
+      if (i < d) {
+        su[rank] = ui;
+        sw[rank] = mw[i];
       }
     }
-    if (i < d) {
-      su[rank] = ui;
-      sw[rank] = mw[i];
+  } else {
+    // the merged list is in ascending u, so a stable sort on the bits of w
+    // alone yields the (w, u) order
+    uint64_t *kx = keyA, *vx = (uint64_t *)wA, *ky = keyB, *vy = (uint64_t *)wB;
+    for (int i = l; i < d; i += kWave) {
+      kx[i] = dbits(mw[i]);
+      vx[i] = (uint64_t)(uint32_t)mu[i];
+    }
+    fence_wave_local();
+    int shifts[8];
+    for (int p2 = 0; p2 < 8; ++p2) shifts[p2] = 8 * p2;
+    const bool in_x = wave_radix_sort(kx, vx, ky, vy, d, shifts, 8, h);
+    const uint64_t *kr = in_x ? kx : ky, *vr = in_x ? vx : vy;
+    for (int i = l; i < d; i += kWave) {
+      sw[i] = bitsd(kr[i]);
+      su[i] = (int32_t)(uint32_t)vr[i];
     }
   }
   fence_wave_local();
@@ -522,16 +657,18 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     a.colcnt[k] = d;
   }
   // 6. publish, then delete the pivot's edges
-  fence_release();
+  Sync::release();
   for (int ib = 0; ib < d; ib += kWave) {
     const int i = ib + l;
     const bool valid = i < d;
-    if (!decrement(a, valid, valid ? mu[i] : 0, valid ? mm[i] : 0)) return false;
+    if (!decrement<Sync>(a, valid, valid ? mu[i] : 0, valid ? mm[i] : 0)) return false;
   }
   return true;
 }
 
-__device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline) {
+template <class Sync>
+__device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
+                                int *h) {
   const int64_t u0 = a.uptr[k];
   const int nU = (int)(a.uptr[k + 1] - u0);
   const int nF = ld_acq_relaxed(&a.fill_cnt[k]);
@@ -545,13 +682,40 @@ __device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64
     return true;
   }
   const int levk = ld_acq_relaxed(&a.lev[k]);
-  if (g <= kWave) return small_pivot(a, wk, k, u0, nU, g, levk, deadline);
-  return large_pivot(a, wk, k, u0, nU, g, levk, deadline);
+  if (g <= kWave) return small_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline);
+  return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h);
+}
+
+// After a slot has delivered label k: read k's counter by a read-modify-write
+// (it returns the last value of the counter's modification order, zero), so
+// the acquire fence that follows synchronises with the release fence of every
+// pivot that touched k.
+template <class Sync>
+__device__ __forceinline__ bool sync_with_producers(const ElimArgs &a, int32_t k) {
+  int v = 0;
+  if (lane() == 0) v = fetch_add(&a.dp[k], 0);
+  v = first_lane_i32(v);
+  if (v != 0) {
+    set_error(a.err, PARAC_EINTERNAL);
+    return false;
+  }
+  Sync::acquire();
+  return true;
+}
+
+// sum of the per-shard counts of eliminated pivots
+__device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
+  int v = ld_acq_relaxed(&a.done[lane() * kTailStride]);
+  int64_t t = v;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, kWave);
+  return t;
 }
 
 __global__ __launch_bounds__(256) void k_eliminate(ElimArgs a) {
+  __shared__ int hist[4][256];  // radix-sort histogram of each wave
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wid >= a.nworkers) return;
+  if (wid >= a.nworkers || a.stop_at <= 0) return;
   const uint64_t deadline = now_ticks() + a.timeout_ticks;
   // Shard x holds exactly the labels v = x (mod kSubQueues), so its slot
   // count is known.  Workers claim its slots in increasing order (the next
@@ -561,6 +725,7 @@ __global__ __launch_bounds__(256) void k_eliminate(ElimArgs a) {
   const int cnt = x < a.ntot ? (a.ntot - 1 - x) / kSubQueues + 1 : 0;
   const int32_t *qx = a.q + (int64_t)x * a.cap_q;
   int *head = a.qhead + x * kTailStride;
+  const int *tailx = a.qtail + x * kTailStride;
   Worker wk{0, 0, 0, 0, 0, 0};
   int next = 0;
   if (lane() == 0) next = atomicAdd(head, 1);
@@ -568,25 +733,86 @@ __global__ __launch_bounds__(256) void k_eliminate(ElimArgs a) {
   while (next < cnt) {
     const int slot = next;
     int32_t k;
+    // Poll the slot.  A worker whose slot lies d places beyond the shard's
+    // tail cannot be served before d more enqueues, so it waits ~d polls'
+    // worth between reads: the front of each queue stays responsive while
+    // the idle workers of a narrow phase stay quiet.  Once all but the thin
+    // tail of the pivots are eliminated, idle workers leave: the tail kernel
+    // finishes the factorisation.
     Backoff bo;
     for (int it = 0;; ++it) {
       int32_t v = 0;
       if (lane() == 0) v = ld_acq_relaxed(&qx[slot]);
       k = first_lane_i32(v);
       if (k >= 0) break;
-      // the shared error word and the clock are consulted rarely
-      if ((it & 63) == 63 && timed_out(a, deadline)) return;
+      if ((it & 15) == 15) {
+        if (timed_out(a, deadline)) return;
+        if (pivots_done(a) >= a.stop_at) return;
+        int t = 0;
+        if (lane() == 0) t = ld_acq_relaxed(tailx);
+        const int dist = first_lane_i32(slot - t);
+        for (int w = 1; w < dist && w < 32; ++w) __builtin_amdgcn_s_sleep(64);
+      }
       bo.pause();
     }
-    fence_acquire();
+    if (!sync_with_producers<WideSync>(a, k)) return;
     if (lane() == 0) next = atomicAdd(head, 1);
     next = __shfl(next, 0, kWave);
-    if (!eliminate_pivot(a, wk, k, deadline)) return;
+    if (!eliminate_pivot<WideSync>(a, wk, k, deadline, hist[threadIdx.x >> 6])) return;
+    if (lane() == 0) atomicAdd(&a.done[x * kTailStride], 1);
+  }
+}
+
+// The tail's starting point: labels not yet eliminated (colcnt < 0) are
+// counted; those already ready (counter zero) seed the tail queue.
+__global__ void k_tail_seed(ElimArgs a) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool left = v < a.ntot && a.colcnt[v] < 0;
+  const bool ready = left && a.dp[v] == 0;
+  const uint64_t ml = __ballot(left), mr = __ballot(ready);
+  int base_r = 0;
+  if (lane() == 0) {
+    if (ml) atomicAdd(a.tq_count, (int)__popcll(ml));
+    if (mr) base_r = atomicAdd(a.tq_tail, (int)__popcll(mr));
+  }
+  base_r = __shfl(base_r, 0, kWave);
+  if (ready) a.tq[base_r + __popcll(mr & lanemask_lt())] = (int32_t)v;
+}
+
+// One workgroup (16 waves, one CU) eliminates the remaining pivots; the same
+// pivot code with workgroup-scope fences and its own in-order queue.
+__global__ __launch_bounds__(1024) void k_eliminate_tail(ElimArgs a) {
+  __shared__ int hist[16][256];  // radix-sort histogram of each wave
+  const int total = *a.tq_count;
+  if (total == 0) return;
+  const uint64_t deadline = now_ticks() + a.timeout_ticks;
+  Worker wk{0, 0, 0, 0, 0, 0};
+  int next = 0;
+  if (lane() == 0) next = __hip_atomic_fetch_add(a.tq_head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  next = __shfl(next, 0, kWave);
+  while (next < total) {
+    const int slot = next;
+    int32_t k;
+    Backoff bo;
+    for (int it = 0;; ++it) {
+      int32_t v = 0;
+      if (lane() == 0) v = __hip_atomic_load(&a.tq[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      k = first_lane_i32(v);
+      if (k >= 0) break;
+      if ((it & 15) == 15 && timed_out(a, deadline)) return;
+      bo.pause();
+    }
+    if (!sync_with_producers<TailSync>(a, k)) return;
+    if (lane() == 0) next = __hip_atomic_fetch_add(a.tq_head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    next = __shfl(next, 0, kWave);
+    if (!eliminate_pivot<TailSync>(a, wk, k, deadline, hist[threadIdx.x >> 6])) return;
   }
 }
 
 hipError_t launch_eliminate(const ElimArgs &a, int wgs, hipStream_t s) {
   hipLaunchKernelGGL(k_eliminate, dim3((unsigned)wgs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_tail_seed, dim3((unsigned)((a.ntot + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_eliminate_tail, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 

@@ -161,49 +161,73 @@ __device__ __forceinline__ int wave_aggregate_add(bool valid, int key, int32_t *
   return 0;
 }
 
-__global__ void k_level_count(int64_t nrows, const int32_t *__restrict__ lev, int32_t *lcount) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = i < nrows;
-  int L = valid ? lev[i] : 0;
-  int mine;
-  wave_aggregate_add(valid, L, lcount, mine);
+// Rows are grouped by level with block-local histograms in LDS (levels below
+// kHist; the heavily populated low levels then cost one global atomic per
+// block instead of one per row); rarer higher levels use wave-aggregated
+// global atomics.  Positions within a level are arbitrary: rows of one level
+// are independent.
+constexpr int kHist = 4096;
+constexpr int kLvT = 1024, kLvItems = 4;
+
+__global__ __launch_bounds__(kLvT) void k_level_count(int64_t nrows, const int32_t *__restrict__ lev,
+                                                      int32_t *lcount) {
+  __shared__ int32_t h[kHist];
+  for (int t = threadIdx.x; t < kHist; t += kLvT) h[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kLvT * kLvItems;
+  for (int k = 0; k < kLvItems; ++k) {
+    const int64_t i = base + threadIdx.x + (int64_t)k * kLvT;
+    const bool valid = i < nrows;
+    const int L = valid ? lev[i] : 0;
+    if (valid && L < kHist) atomicAdd(&h[L], 1);
+    int mine;
+    wave_aggregate_add(valid && L >= kHist, L, lcount, mine);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHist; t += kLvT)
+    if (h[t]) atomicAdd(&lcount[t], h[t]);
 }
 
 hipError_t launch_level_count(int64_t nrows, const int32_t *lev, int32_t *lcount, hipStream_t s) {
-  hipLaunchKernelGGL(k_level_count, dim3(nblk(nrows, 256)), dim3(256), 0, s, nrows, lev, lcount);
+  hipLaunchKernelGGL(k_level_count, dim3(nblk(nrows, kLvT * kLvItems)), dim3(kLvT), 0, s, nrows, lev,
+                     lcount);
   return hipGetLastError();
 }
 
-__global__ void k_level_place(int64_t nrows, const int32_t *__restrict__ lev,
-                              const int64_t *__restrict__ lptr, int32_t *lcursor, int32_t *order) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = i < nrows;
-  int L = valid ? lev[i] : 0;
-  int mine;
-  wave_aggregate_add(valid, L, lcursor, mine);
-  if (valid) order[lptr[L] + mine] = (int32_t)i;
+__global__ __launch_bounds__(kLvT) void k_level_place(int64_t nrows, const int32_t *__restrict__ lev,
+                                                      const int64_t *__restrict__ lptr,
+                                                      int32_t *lcursor, int32_t *order) {
+  __shared__ int32_t h[kHist];
+  __shared__ int32_t bs[kHist];
+  for (int t = threadIdx.x; t < kHist; t += kLvT) h[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kLvT * kLvItems;
+  int rank[kLvItems], Ls[kLvItems];
+  for (int k = 0; k < kLvItems; ++k) {
+    const int64_t i = base + threadIdx.x + (int64_t)k * kLvT;
+    const bool valid = i < nrows;
+    Ls[k] = valid ? lev[i] : -1;
+    rank[k] = (valid && Ls[k] < kHist) ? atomicAdd(&h[Ls[k]], 1) : 0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHist; t += kLvT)
+    if (h[t]) bs[t] = atomicAdd(&lcursor[t], h[t]);
+  __syncthreads();
+  for (int k = 0; k < kLvItems; ++k) {
+    const int64_t i = base + threadIdx.x + (int64_t)k * kLvT;
+    const int L = Ls[k];
+    const bool hi = L >= kHist;
+    int mine;
+    wave_aggregate_add(hi, hi ? L : 0, lcursor, mine);
+    if (L >= 0 && !hi) order[lptr[L] + bs[L] + rank[k]] = (int32_t)i;
+    if (hi) order[lptr[L] + mine] = (int32_t)i;
+  }
 }
 
 hipError_t launch_level_place(int64_t nrows, const int32_t *lev, const int64_t *lptr,
                               int32_t *lcursor, int32_t *order, hipStream_t s) {
-  hipLaunchKernelGGL(k_level_place, dim3(nblk(nrows, 256)), dim3(256), 0, s, nrows, lev, lptr,
-                     lcursor, order);
-  return hipGetLastError();
-}
-
-// batches per level: rows of one level are independent; a batch is the set
-// of rows one wave solves together
-__global__ void k_batches(int64_t depth, const int64_t *__restrict__ lptr, int32_t *bcnt, int rpb) {
-  int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (L >= depth) return;
-  int64_t c = lptr[L + 1] - lptr[L];
-  bcnt[L] = (int32_t)((c + rpb - 1) / rpb);
-}
-
-hipError_t launch_batches(int64_t depth, const int64_t *lptr, int32_t *bcnt, int rpb,
-                          hipStream_t s) {
-  if (depth == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batches, dim3(nblk(depth, 256)), dim3(256), 0, s, depth, lptr, bcnt, rpb);
+  hipLaunchKernelGGL(k_level_place, dim3(nblk(nrows, kLvT * kLvItems)), dim3(kLvT), 0, s, nrows, lev,
+                     lptr, lcursor, order);
   return hipGetLastError();
 }
 
@@ -234,19 +258,24 @@ hipError_t launch_cast32(int64_t n, const double *a, float *b, hipStream_t s) {
 }
 
 // out: [0] max gather, [1] max d_k, [2] sum max(d_k - 1, 0), [3] max level,
-//      [4] zero pivots
-__global__ void k_max_stats(int64_t ntot, const int64_t *__restrict__ uptr,
-                            const int32_t *__restrict__ fill_cnt,
-                            const int32_t *__restrict__ colcnt, const int32_t *__restrict__ lev,
-                            unsigned long long *out) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+//      [4] zero pivots -- reduced per block in LDS, one atomic per block
+__global__ __launch_bounds__(1024) void k_max_stats(int64_t ntot, const int64_t *__restrict__ uptr,
+                                                    const int32_t *__restrict__ fill_cnt,
+                                                    const int32_t *__restrict__ colcnt,
+                                                    const int32_t *__restrict__ lev,
+                                                    unsigned long long *out) {
+  __shared__ unsigned long long sh[5][16];
   unsigned long long g = 0, d = 0, f = 0, L = 0, z = 0;
-  if (k < ntot) {
-    g = (unsigned long long)(uptr[k + 1] - uptr[k] + fill_cnt[k]);
-    d = (unsigned long long)colcnt[k];
-    f = d > 0 ? d - 1 : 0;
-    L = (unsigned long long)lev[k];
-    z = colcnt[k] == 0 ? 1 : 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ntot;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long gk = (unsigned long long)(uptr[k + 1] - uptr[k] + fill_cnt[k]);
+    unsigned long long dk = (unsigned long long)colcnt[k];
+    unsigned long long Lk = (unsigned long long)lev[k];
+    g = gk > g ? gk : g;
+    d = dk > d ? dk : d;
+    L = Lk > L ? Lk : L;
+    f += dk > 0 ? dk - 1 : 0;
+    z += colcnt[k] == 0 ? 1 : 0;
   }
   for (int o = 32; o >= 1; o >>= 1) {
     unsigned long long g2 = __shfl_xor(g, o, kWave), d2 = __shfl_xor(d, o, kWave);
@@ -257,7 +286,24 @@ __global__ void k_max_stats(int64_t ntot, const int64_t *__restrict__ uptr,
     f += __shfl_xor(f, o, kWave);
     z += __shfl_xor(z, o, kWave);
   }
+  const int w = threadIdx.x >> 6;
   if (lane() == 0) {
+    sh[0][w] = g;
+    sh[1][w] = d;
+    sh[2][w] = f;
+    sh[3][w] = L;
+    sh[4][w] = z;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int i = 1; i < nw; ++i) {
+      g = sh[0][i] > g ? sh[0][i] : g;
+      d = sh[1][i] > d ? sh[1][i] : d;
+      f += sh[2][i];
+      L = sh[3][i] > L ? sh[3][i] : L;
+      z += sh[4][i];
+    }
     atomicMax(&out[0], g);
     atomicMax(&out[1], d);
     atomicAdd(&out[2], f);
@@ -269,8 +315,9 @@ __global__ void k_max_stats(int64_t ntot, const int64_t *__restrict__ uptr,
 hipError_t launch_max_stats(int64_t ntot, const int64_t *uptr, const int32_t *fill_cnt,
                             const int32_t *colcnt, const int32_t *lev, unsigned long long *out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_max_stats, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, uptr, fill_cnt,
-                     colcnt, lev, out);
+  const unsigned blocks = nblk(ntot, 1024) < 512 ? nblk(ntot, 1024) : 512;
+  hipLaunchKernelGGL(k_max_stats, dim3(blocks), dim3(1024), 0, s, ntot, uptr, fill_cnt, colcnt, lev,
+                     out);
   return hipGetLastError();
 }
 

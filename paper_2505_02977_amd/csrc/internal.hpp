@@ -29,11 +29,6 @@ constexpr int kTailStride = 32;        // ints between shard tails (128 B)
 constexpr int kFChunk = 2048;          // largest factor-entry reservation
 constexpr int kPageChunk = 4096;       // largest fill-record reservation
 
-// sentinel bit patterns of the sync-free triangular solves ("not yet
-// computed"); a computed NaN is stored as the canonical quiet NaN instead
-constexpr uint64_t kSent64 = 0x7FF4DEADBEEF0001ull;
-constexpr uint32_t kSent32 = 0x7FA0BEEFu;
-
 struct ElimArgs {
   int32_t ntot;
   const int64_t *uptr;
@@ -67,6 +62,10 @@ struct ElimArgs {
   int32_t nworkers;
   int32_t pg_chunk;    // fill records a worker reserves at a time
   int32_t f_chunk;     // factor entries a worker reserves at a time
+  int32_t *done;       // per-shard eliminated-pivot counts, kTailStride apart
+  int64_t stop_at;     // the wide kernel leaves once this many are eliminated
+  int32_t *tq;         // tail queue [ntot] (-1 = empty slot)
+  int32_t *tq_head, *tq_tail, *tq_count;  // tail claim, append, pivots left
 };
 
 // --- launchers (setup.hip) ---
@@ -108,8 +107,6 @@ hipError_t launch_sort_rows(int64_t ntot, const int64_t *rowptr_f, int32_t *coli
 hipError_t launch_level_count(int64_t nrows, const int32_t *lev, int32_t *lcount, hipStream_t s);
 hipError_t launch_level_place(int64_t nrows, const int32_t *lev, const int64_t *lptr,
                               int32_t *lcursor, int32_t *order, hipStream_t s);
-hipError_t launch_batches(int64_t depth, const int64_t *lptr, int32_t *bcnt, int rpb,
-                          hipStream_t s);
 hipError_t launch_sort_long_rows(const int64_t *rowptr_f, int32_t *colind_f, double *val_f,
                                  const int32_t *long_rows, const int32_t *n_long, int32_t *tmp_c,
                                  double *tmp_v, hipStream_t s);
@@ -125,28 +122,29 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // --- solve.hip ---
 struct SolveArgs {
   int64_t n;             // solved rows (labels 0..n-1)
-  int32_t nrhs;
-  const int64_t *rowptr_f; const int32_t *colind_f;  // CSR of F
-  const int64_t *colptr; const int32_t *rowind;      // CSC of F
-  const double *val_f, *val, *Dinv;                  // FP64 values
-  const float *val_f32, *val32, *Dinv32;             // FP32 copies
   const int32_t *order;  // rows by ascending level
-  const int64_t *bptr;   // batch prefix over levels [depth+1]
   const int64_t *lptr;   // row prefix over levels [depth+1]
-  int64_t depth, nbatch;
-  const int32_t *perm;   // vertex -> label
+  int64_t depth;
+  int64_t L0;            // first level of the thin tail (solved by one workgroup)
+  // level-ordered copies of F: forward rows, backward columns (no ground)
+  const int64_t *lf_ptr; const int32_t *lf_idx; const double *lf_val; const float *lf_val32;
+  const int64_t *lb_ptr; const int32_t *lb_idx; const double *lb_val; const float *lb_val32;
+  const double *Dinv; const float *Dinv32;
   const int32_t *iperm;  // label -> vertex
   const int *skip;       // device flag: nonzero => return immediately
-  int *err;              // watchdog flag (set when a wait exceeds the deadline)
-  int *claim;            // batch counters: forward [0], backward [kTailStride]
-  uint64_t timeout_ticks;
 };
-hipError_t launch_trsv_fwd(const SolveArgs &a, const double *r, void *y, void *x, int prec,
-                           int waves, hipStream_t s);
-hipError_t launch_trsv_bwd(const SolveArgs &a, void *y, void *x, double *z, int prec, int waves,
-                           hipStream_t s);
-int trsv_max_waves();
-constexpr int kRowsPerBatch = 16;  // rows one wave solves together (4 lanes each)
+// z = M^+ r; hlptr is the host copy of lptr
+hipError_t launch_apply(const SolveArgs &a, const int64_t *hlptr, const double *r, void *y, void *x,
+                        double *z, int prec, hipStream_t s);
+hipError_t launch_level_layout(int64_t n, const int32_t *order, const int64_t *rowptr_f,
+                               const int64_t *colptr, const int32_t *rowind, int32_t *flen,
+                               int32_t *blen, hipStream_t s);
+hipError_t launch_level_copy(int64_t n, const int32_t *order, const int64_t *rowptr_f,
+                             const int32_t *colind_f, const double *val_f, const int64_t *colptr,
+                             const int32_t *rowind, const double *val, const int64_t *lf_ptr,
+                             const int64_t *lb_ptr, int32_t *lf_idx, double *lf_val,
+                             int32_t *lb_idx, double *lb_val, hipStream_t s);
+constexpr int kTailWidth = 1024;  // levels this narrow (and all above) form the tail
 int pcg_partials();
 hipError_t pcg_launch_init(int64_t n, const double *b, double *x, double *r, double *partial,
                            double *st, int *ist, hipStream_t s);
@@ -171,24 +169,23 @@ hipError_t launch_comp_check(int64_t n, int64_t ground, const int32_t *perm, con
 struct parac_factor_s {
   int64_t n = 0, ntot = 0;
   int32_t mode = 0;
-  int64_t nnz_off = 0, depth = 0, nbatch = 0;
+  int64_t nnz_off = 0, depth = 0, L0 = 0;
   parac_factor_stats stats{};
   // device arrays
   int32_t *perm = nullptr, *iperm = nullptr;
-  int64_t *colptr = nullptr;
+  int64_t *colptr = nullptr;   // canonical CSC of F (label space)
   int32_t *rowind = nullptr;
   double *val = nullptr;
-  int64_t *rowptr_f = nullptr;
-  int32_t *colind_f = nullptr;
-  double *val_f = nullptr;
   double *D = nullptr, *Dinv = nullptr;
-  float *val32 = nullptr, *val_f32 = nullptr, *Dinv32 = nullptr;
+  float *Dinv32 = nullptr;
   int32_t *lev = nullptr, *order = nullptr, *root = nullptr;
-  int64_t *lptr = nullptr, *bptr = nullptr;
-  // solve work vectors (label space, sentinel-filled between solves)
+  int64_t *lptr = nullptr;
+  int64_t *lf_ptr = nullptr, *lb_ptr = nullptr;
+  int32_t *lf_idx = nullptr, *lb_idx = nullptr;
+  double *lf_val = nullptr, *lb_val = nullptr;
+  float *lf_val32 = nullptr, *lb_val32 = nullptr;
+  std::vector<int64_t> hlptr;  // host copy of lptr
+  // solve work vectors (label space)
   void *wy64 = nullptr, *wx64 = nullptr, *wy32 = nullptr, *wx32 = nullptr;
-  int trsv_waves = 0;
-  int *err = nullptr;    // watchdog flag of the triangular solves
-  int *claim = nullptr;  // batch counters of the triangular solves
   std::vector<void *> owned;
 };

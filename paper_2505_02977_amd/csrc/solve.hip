@@ -1,14 +1,9 @@
 // solve.hip -- the preconditioner apply z = P^T F^-T D^+ F^-1 P r and the
 // kernels of preconditioned conjugate gradients.
 //
-// Triangular solves are sync-free: every row waits for the rows it depends
-// on by polling their values, which hold a sentinel bit pattern until they
-// are computed (agent-scope loads and stores, so a value is its own ready
-// flag).  Rows are processed in batches of one elimination level (rows of a
-// level are independent); the forward solve walks the levels upwards, the
-// backward solve downwards, so every dependency lies in an earlier batch and
-// the lowest unfinished batch can always complete.  Each row is folded left
-// in ascending column order, the order of the CPU reference.
+// Both triangular solves follow the elimination levels: the rows of one
+// level depend only on rows of lower levels (forward) or higher levels
+// (backward), so a level is solved in parallel once its predecessors are.
 #include <float.h>
 
 #include "device.hpp"
@@ -16,238 +11,209 @@
 
 namespace parac {
 
-template <typename T> struct Bits;
-template <> struct Bits<double> {
-  using U = unsigned long long;
-  static __device__ __forceinline__ U sent() { return (U)kSent64; }
-  static __device__ __forceinline__ U to(double v) {
-    U b = (U)__double_as_longlong(v);
-    return b == (U)kSent64 ? 0x7FF8000000000000ull : b;
-  }
-  static __device__ __forceinline__ double from(U b) { return __longlong_as_double((long long)b); }
+// ---------------------------------------------------------------------------
+// Preconditioner apply.  The factor is stored twice in level order: the rows
+// of F for the forward solve and its columns (without the ground row) for
+// the backward solve; position p of either copy is the row order[p].  Rows of
+// one level are independent.
+//
+//  * wide levels (below L0): one launch per level, one thread per row;
+//    the level's dependencies were written by earlier launches;
+//  * the thin tail (L0 and above, at most kTailWidth rows per level): one
+//    workgroup walks the levels; per level it gathers all products into LDS
+//    with coalesced reads, then each row folds its own products.
+//
+// Every row is folded left in ascending column order, starting from the
+// right-hand side (forward) or D^+ y (backward): the order of the CPU
+// reference, so the result is the same bit for bit.
+// ---------------------------------------------------------------------------
+template <typename T> struct FactorVals;
+template <> struct FactorVals<double> {
+  static __device__ __forceinline__ const double *fwd(const SolveArgs &a) { return a.lf_val; }
+  static __device__ __forceinline__ const double *bwd(const SolveArgs &a) { return a.lb_val; }
+  static __device__ __forceinline__ const double *dinv(const SolveArgs &a) { return a.Dinv; }
 };
-template <> struct Bits<float> {
-  using U = unsigned int;
-  static __device__ __forceinline__ U sent() { return kSent32; }
-  static __device__ __forceinline__ U to(float v) {
-    U b = (U)__float_as_uint(v);
-    return b == kSent32 ? 0x7FC00000u : b;
-  }
-  static __device__ __forceinline__ float from(U b) { return __uint_as_float(b); }
+template <> struct FactorVals<float> {
+  static __device__ __forceinline__ const float *fwd(const SolveArgs &a) { return a.lf_val32; }
+  static __device__ __forceinline__ const float *bwd(const SolveArgs &a) { return a.lb_val32; }
+  static __device__ __forceinline__ const float *dinv(const SolveArgs &a) { return a.Dinv32; }
 };
 
-template <typename T> __device__ __forceinline__ const T *fvals_csr(const SolveArgs &a);
-template <> __device__ __forceinline__ const double *fvals_csr<double>(const SolveArgs &a) { return a.val_f; }
-template <> __device__ __forceinline__ const float *fvals_csr<float>(const SolveArgs &a) { return a.val_f32; }
-template <typename T> __device__ __forceinline__ const T *fvals_csc(const SolveArgs &a);
-template <> __device__ __forceinline__ const double *fvals_csc<double>(const SolveArgs &a) { return a.val; }
-template <> __device__ __forceinline__ const float *fvals_csc<float>(const SolveArgs &a) { return a.val32; }
-template <typename T> __device__ __forceinline__ const T *dinv_of(const SolveArgs &a);
-template <> __device__ __forceinline__ const double *dinv_of<double>(const SolveArgs &a) { return a.Dinv; }
-template <> __device__ __forceinline__ const float *dinv_of<float>(const SolveArgs &a) { return a.Dinv32; }
-
-constexpr int kG = 4;                 // lanes per row (triangular solves)
-constexpr int kU = 4;                 // entries per lane and round
-constexpr int kRound = kG * kU;       // entries of a row per round
-constexpr int kRPB = kWave / kG;      // rows per batch
-constexpr int kSG = 8;                // lanes per row (SpMV)
-constexpr int kSRPW = kWave / kSG;    // SpMV rows per wave
-
-// level of batch b: the largest L with bptr[L] <= b
-__device__ __forceinline__ int64_t batch_level(const SolveArgs &a, int64_t b) {
-  int64_t lo = 0, hi = a.depth - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (a.bptr[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// Batches are claimed in increasing order from a counter, so the lowest
-// unfinished batch is always held by a running wave: nothing assumes how many
-// waves are resident.  The next claim is issued before the current batch is
-// solved, hiding its latency.
-__device__ __forceinline__ int64_t claim(int *ctr) {
-  int v = 0;
-  if (lane() == 0) v = atomicAdd(ctr, 1);
-  return (int64_t)__shfl(v, 0, kWave);
-}
-
-// One row per kG lanes.  A row's entries are taken kRound at a time: all
-// dependency values of a round are requested at once and polled until each
-// is computed (it holds the sentinel until then); the products are folded
-// left in entry order.
 template <typename T>
-__device__ __forceinline__ T row_fold(T acc, int64_t e0, int64_t e1,
-                                      const int32_t *__restrict__ idx, const T *__restrict__ fv,
-                                      const T *vec, int grp, int sub, uint64_t deadline,
-                                      int *err) {
-  using B = Bits<T>;
-  using U = typename B::U;
-  for (int64_t eb = e0; __any(eb < e1); eb += kRound) {
-    U bits[kU];
-    int32_t jj[kU];
-    T f[kU];
-    bool wait[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t e = eb + sub + (int64_t)u * kG;
-      const bool has = e < e1;
-      jj[u] = has ? idx[e] : 0;
-      f[u] = has ? fv[e] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const bool has = eb + sub + (int64_t)u * kG < e1;
-      bits[u] = has ? ld_acq_relaxed((const U *)(vec + jj[u])) : (U)0;
-      wait[u] = has && bits[u] == B::sent();
-    }
-    bool any = false;
-#pragma unroll
-    for (int u = 0; u < kU; ++u) any |= wait[u];
-    Backoff bo;
-    while (__any(any)) {
-      bo.pause();
-      any = false;
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (wait[u]) {
-          const U v = ld_acq_relaxed((const U *)(vec + jj[u]));
-          if (v != B::sent()) {
-            bits[u] = v;
-            wait[u] = false;
-          } else {
-            any = true;
-          }
-        }
-      }
-      if (__any(any) && now_ticks() > deadline) {
-        set_error(err, PARAC_ETIMEOUT);
-        break;
-      }
-    }
-    T prod[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) prod[u] = f[u] * B::from(bits[u]);
-#pragma unroll
-    for (int t = 0; t < kRound; ++t) {
-      const T pt = shfl(prod[t / kG], grp * kG + (t % kG));
-      if (eb + t < e1) acc = acc - pt;
-    }
+__global__ __launch_bounds__(256) void k_level_fwd(SolveArgs a, int64_t p0, int64_t p1,
+                                                   const double *__restrict__ r, T *y) {
+  if (a.skip && *a.skip) return;
+  const int64_t pos = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= p1) return;
+  const int32_t i = a.order[pos];
+  const T *fv = FactorVals<T>::fwd(a);
+  T acc = (T)r[a.iperm[i]];
+  for (int64_t e = a.lf_ptr[pos]; e < a.lf_ptr[pos + 1]; ++e) acc = acc - fv[e] * y[a.lf_idx[e]];
+  y[i] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_level_bwd(SolveArgs a, int64_t p0, int64_t p1,
+                                                   const T *__restrict__ y, T *x, double *z) {
+  if (a.skip && *a.skip) return;
+  const int64_t pos = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= p1) return;
+  const int32_t i = a.order[pos];
+  const T *fv = FactorVals<T>::bwd(a);
+  T acc = FactorVals<T>::dinv(a)[i] * y[i];
+  for (int64_t e = a.lb_ptr[pos]; e < a.lb_ptr[pos + 1]; ++e) acc = acc - fv[e] * x[a.lb_idx[e]];
+  x[i] = acc;
+  z[a.iperm[i]] = (double)acc;
+}
+
+constexpr int kTThreads = 1024;
+constexpr int kTStage = 8192;  // products staged in LDS per pass
+
+// one tail level: stage the products of the level's entries [q0, q1) in
+// passes of kTStage, each row folding its own entries after every pass
+template <typename T>
+__device__ __forceinline__ T tail_level(T acc, int64_t e0, int64_t e1, int64_t q0, int64_t q1,
+                                        const int32_t *__restrict__ idx,
+                                        const T *__restrict__ fv, const T *vec, T *stage) {
+  for (int64_t qc = q0; qc < q1; qc += kTStage) {
+    const int64_t qe = qc + kTStage < q1 ? qc + kTStage : q1;
+    for (int64_t q = qc + threadIdx.x; q < qe; q += kTThreads) stage[q - qc] = fv[q] * vec[idx[q]];
+    __syncthreads();
+    const int64_t lo = e0 > qc ? e0 : qc, hi = e1 < qe ? e1 : qe;
+    for (int64_t e = lo; e < hi; ++e) acc = acc - stage[e - qc];
+    __syncthreads();
   }
   return acc;
 }
 
 template <typename T>
-__device__ __forceinline__ void publish(T *p, T v) {
-  using B = Bits<T>;
-  st_relaxed((typename B::U *)p, B::to(v));
-}
-
-// forward: y_i = r_{perm^-1(i)} - sum_j F_ij y_j (left fold, j ascending);
-// also re-arms x_i for the backward solve
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd(SolveArgs a, const double *__restrict__ r, T *y,
-                                                  T *x) {
+__global__ __launch_bounds__(kTThreads) void k_tail_fwd(SolveArgs a, const double *__restrict__ r,
+                                                        T *y) {
+  __shared__ T stage[kTStage];
   if (a.skip && *a.skip) return;
-  using B = Bits<T>;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(a.claim + kTailStride, 0);  // backward's
-  const int l = lane(), grp = l / kG, sub = l % kG;
-  const T *fv = fvals_csr<T>(a);
-  const uint64_t deadline = now_ticks() + a.timeout_ticks;
-  int64_t next = claim(a.claim);
-  while (next < a.nbatch) {
-    const int64_t b = next;
-    next = claim(a.claim);
-    const int64_t L = batch_level(a, b);
-    const int64_t pos = a.lptr[L] + (b - a.bptr[L]) * kRPB + grp;
-    const bool valid = pos < a.lptr[L + 1];
+  const T *fv = FactorVals<T>::fwd(a);
+  for (int64_t L = a.L0; L < a.depth; ++L) {
+    const int64_t p0 = a.lptr[L], p1 = a.lptr[L + 1];
+    const int64_t pos = p0 + threadIdx.x;  // at most kTailWidth <= kTThreads rows
+    const bool valid = pos < p1;
     const int32_t i = valid ? a.order[pos] : 0;
-    const int64_t e0 = valid ? a.rowptr_f[i] : 0, e1 = valid ? a.rowptr_f[i + 1] : 0;
     T acc = valid ? (T)r[a.iperm[i]] : (T)0;
-    acc = row_fold<T>(acc, e0, e1, a.colind_f, fv, y, grp, sub, deadline, a.err);
-    if (valid && sub == 0) {
-      publish<T>(y + i, acc);
-      st_relaxed((typename B::U *)(x + i), B::sent());
-    }
+    const int64_t e0 = valid ? a.lf_ptr[pos] : 0, e1 = valid ? a.lf_ptr[pos + 1] : 0;
+    acc = tail_level<T>(acc, e0, e1, a.lf_ptr[p0], a.lf_ptr[p1], a.lf_idx, fv, y, stage);
+    if (valid) y[i] = acc;
+    __syncthreads();
   }
 }
 
-// backward: x_i = Dinv_i y_i - sum_{u>i} F_ui x_u (left fold, u ascending;
-// the ground row of an SDDM factor is dropped); z_{perm^-1(i)} = x_i; also
-// re-arms y_i for the next forward solve
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, T *y, T *x, double *z) {
+__global__ __launch_bounds__(kTThreads) void k_tail_bwd(SolveArgs a, const T *__restrict__ y,
+                                                        T *x, double *z) {
+  __shared__ T stage[kTStage];
   if (a.skip && *a.skip) return;
-  using B = Bits<T>;
-  int *ctr = a.claim + kTailStride;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(a.claim, 0);  // forward's
-  const int l = lane(), grp = l / kG, sub = l % kG;
-  const T *fv = fvals_csc<T>(a);
-  const T *dv = dinv_of<T>(a);
-  const uint64_t deadline = now_ticks() + a.timeout_ticks;
-  int64_t next = claim(ctr);
-  while (next < a.nbatch) {
-    const int64_t b = a.nbatch - 1 - next;
-    next = claim(ctr);
-    const int64_t L = batch_level(a, b);
-    const int64_t pos = a.lptr[L] + (b - a.bptr[L]) * kRPB + grp;
-    const bool valid = pos < a.lptr[L + 1];
+  const T *fv = FactorVals<T>::bwd(a);
+  const T *dv = FactorVals<T>::dinv(a);
+  for (int64_t L = a.depth - 1; L >= a.L0; --L) {
+    const int64_t p0 = a.lptr[L], p1 = a.lptr[L + 1];
+    const int64_t pos = p0 + threadIdx.x;
+    const bool valid = pos < p1;
     const int32_t i = valid ? a.order[pos] : 0;
-    int64_t e0 = valid ? a.colptr[i] : 0, e1 = valid ? a.colptr[i + 1] : 0;
-    if (e1 > e0 && a.rowind[e1 - 1] >= a.n) --e1;  // ground is the last row
-    const T yi = valid ? B::from(ld_acq_relaxed((const typename B::U *)(y + i))) : (T)0;
-    T acc = valid ? dv[i] * yi : (T)0;
-    acc = row_fold<T>(acc, e0, e1, a.rowind, fv, x, grp, sub, deadline, a.err);
-    if (valid && sub == 0) {
-      publish<T>(x + i, acc);
+    T acc = valid ? dv[i] * y[i] : (T)0;
+    const int64_t e0 = valid ? a.lb_ptr[pos] : 0, e1 = valid ? a.lb_ptr[pos + 1] : 0;
+    acc = tail_level<T>(acc, e0, e1, a.lb_ptr[p0], a.lb_ptr[p1], a.lb_idx, fv, x, stage);
+    if (valid) {
+      x[i] = acc;
       z[a.iperm[i]] = (double)acc;
-      st_relaxed((typename B::U *)(y + i), B::sent());
     }
+    __syncthreads();
   }
 }
 
-hipError_t launch_trsv_fwd(const SolveArgs &a, const double *r, void *y, void *x, int prec,
-                           int waves, hipStream_t s) {
-  const int wg = (waves + 3) / 4;
-  if (prec == PARAC_PREC_MIXED)
-    hipLaunchKernelGGL(k_trsv_fwd<float>, dim3(wg), dim3(256), 0, s, a, r, (float *)y, (float *)x);
-  else
-    hipLaunchKernelGGL(k_trsv_fwd<double>, dim3(wg), dim3(256), 0, s, a, r, (double *)y,
-                       (double *)x);
+template <typename T>
+static hipError_t apply_t(const SolveArgs &a, const int64_t *hlptr, const double *r, T *y, T *x,
+                          double *z, hipStream_t s) {
+  for (int64_t L = 0; L < a.L0; ++L) {
+    const int64_t p0 = hlptr[L], p1 = hlptr[L + 1];
+    if (p1 > p0)
+      hipLaunchKernelGGL(k_level_fwd<T>, dim3((unsigned)((p1 - p0 + 255) / 256)), dim3(256), 0, s,
+                         a, p0, p1, r, y);
+  }
+  if (a.L0 < a.depth) {
+    hipLaunchKernelGGL(k_tail_fwd<T>, dim3(1), dim3(kTThreads), 0, s, a, r, y);
+    hipLaunchKernelGGL(k_tail_bwd<T>, dim3(1), dim3(kTThreads), 0, s, a, (const T *)y, x, z);
+  }
+  for (int64_t L = a.L0 - 1; L >= 0; --L) {
+    const int64_t p0 = hlptr[L], p1 = hlptr[L + 1];
+    if (p1 > p0)
+      hipLaunchKernelGGL(k_level_bwd<T>, dim3((unsigned)((p1 - p0 + 255) / 256)), dim3(256), 0, s,
+                         a, p0, p1, (const T *)y, x, z);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_trsv_bwd(const SolveArgs &a, void *y, void *x, double *z, int prec, int waves,
-                           hipStream_t s) {
-  const int wg = (waves + 3) / 4;
+hipError_t launch_apply(const SolveArgs &a, const int64_t *hlptr, const double *r, void *y, void *x,
+                        double *z, int prec, hipStream_t s) {
   if (prec == PARAC_PREC_MIXED)
-    hipLaunchKernelGGL(k_trsv_bwd<float>, dim3(wg), dim3(256), 0, s, a, (float *)y, (float *)x, z);
-  else
-    hipLaunchKernelGGL(k_trsv_bwd<double>, dim3(wg), dim3(256), 0, s, a, (double *)y, (double *)x,
-                       z);
+    return apply_t<float>(a, hlptr, r, (float *)y, (float *)x, z, s);
+  return apply_t<double>(a, hlptr, r, (double *)y, (double *)x, z, s);
+}
+
+// level-ordered copies: position p holds row order[p]'s entries of F (rows
+// for the forward solve; columns minus the ground row for the backward one)
+__global__ void k_level_lengths(int64_t n, const int32_t *__restrict__ order,
+                                const int64_t *__restrict__ rowptr_f,
+                                const int64_t *__restrict__ colptr,
+                                const int32_t *__restrict__ rowind, int32_t *flen, int32_t *blen) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t i = order[p];
+  flen[p] = (int32_t)(rowptr_f[i + 1] - rowptr_f[i]);
+  int64_t b = colptr[i], e = colptr[i + 1];
+  if (e > b && rowind[e - 1] >= n) --e;  // the ground row is dropped
+  blen[p] = (int32_t)(e - b);
+}
+
+__global__ void k_level_copy(int64_t n, const int32_t *__restrict__ order,
+                             const int64_t *__restrict__ rowptr_f,
+                             const int32_t *__restrict__ colind_f, const double *__restrict__ val_f,
+                             const int64_t *__restrict__ colptr, const int32_t *__restrict__ rowind,
+                             const double *__restrict__ val, const int64_t *__restrict__ lf_ptr,
+                             const int64_t *__restrict__ lb_ptr, int32_t *lf_idx, double *lf_val,
+                             int32_t *lb_idx, double *lb_val) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t i = order[p];
+  int64_t o = lf_ptr[p];
+  for (int64_t e = rowptr_f[i]; e < rowptr_f[i + 1]; ++e, ++o) {
+    lf_idx[o] = colind_f[e];
+    lf_val[o] = val_f[e];
+  }
+  o = lb_ptr[p];
+  const int64_t cnt = lb_ptr[p + 1] - lb_ptr[p];
+  for (int64_t t = 0; t < cnt; ++t, ++o) {
+    lb_idx[o] = rowind[colptr[i] + t];
+    lb_val[o] = val[colptr[i] + t];
+  }
+}
+
+hipError_t launch_level_layout(int64_t n, const int32_t *order, const int64_t *rowptr_f,
+                               const int64_t *colptr, const int32_t *rowind, int32_t *flen,
+                               int32_t *blen, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_lengths, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
+                     rowptr_f, colptr, rowind, flen, blen);
   return hipGetLastError();
 }
 
-int trsv_max_waves() {
-  int dev = 0, a = 0, b = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trsv_fwd<double>, 256, 0) != hipSuccess)
-    return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trsv_bwd<double>, 256, 0) != hipSuccess)
-    return 0;
-  int m = a < b ? a : b;
-  int c, d2;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_trsv_fwd<float>, 256, 0) != hipSuccess)
-    return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&d2, k_trsv_bwd<float>, 256, 0) != hipSuccess)
-    return 0;
-  m = m < c ? m : c;
-  m = m < d2 ? m : d2;
-  return m * prop.multiProcessorCount * 4;
+hipError_t launch_level_copy(int64_t n, const int32_t *order, const int64_t *rowptr_f,
+                             const int32_t *colind_f, const double *val_f, const int64_t *colptr,
+                             const int32_t *rowind, const double *val, const int64_t *lf_ptr,
+                             const int64_t *lb_ptr, int32_t *lf_idx, double *lf_val,
+                             int32_t *lb_idx, double *lb_val, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
+                     rowptr_f, colind_f, val_f, colptr, rowind, val, lf_ptr, lb_ptr, lf_idx,
+                     lf_val, lb_idx, lb_val);
+  return hipGetLastError();
 }
 
 // ==========================================================================
@@ -257,6 +223,8 @@ int trsv_max_waves() {
 // ==========================================================================
 constexpr int kRedBlocks = 1024;
 constexpr int kRedT = 256;
+constexpr int kSG = 8;              // lanes per row (SpMV)
+constexpr int kSRPW = kWave / kSG;  // SpMV rows per wave
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   const int t = threadIdx.x;

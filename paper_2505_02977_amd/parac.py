@@ -35,7 +35,7 @@ class parac_csr(C.Structure):
 class parac_factor_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("perm", C.c_void_p), ("mode", C.c_int32),
                 ("pool_factor", C.c_double), ("workers", C.c_int32), ("keep_fp32", C.c_int32),
-                ("timeout_s", C.c_double)]
+                ("timeout_s", C.c_double), ("tail_fraction", C.c_double)]
 
 
 class parac_factor_stats(C.Structure):
@@ -163,13 +163,14 @@ class Factor:
 
 
 def parac_factor(A: DeviceCSR, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, workers=0,
-                 keep_fp32=False, timeout_s=30.0, stream=None) -> Factor:
+                 keep_fp32=False, timeout_s=30.0, tail_fraction=0.0, stream=None) -> Factor:
     import torch
     pt = None
     if perm is not None:
         pt = torch.as_tensor(np.ascontiguousarray(perm, np.int32), device=A.rowptr.device)
     o = parac_factor_opts(int(seed) & (2**64 - 1), pt.data_ptr() if pt is not None else None,
-                          mode, pool_factor, workers, 1 if keep_fp32 else 0, timeout_s)
+                          mode, pool_factor, workers, 1 if keep_fp32 else 0, timeout_s,
+                          tail_fraction)
     h = C.c_void_p()
     _raise(lib().parac_factor(C.byref(A.c), C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h)

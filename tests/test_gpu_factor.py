@@ -40,6 +40,17 @@ def case_graphs():
     j = np.concatenate([np.arange(1, 300), np.arange(2, 400)])
     i, j = inputs.dedupe_edges(i, j)
     out.append(("hub", lap(n, i, j, rng.uniform(0.1, 1.0, len(i))), None))
+    # a big hub on a path of leaves, labelled mid-way: its gathered list runs
+    # past the rank-sort limit and holds several records per neighbour (the
+    # radix-sort path of both sorts)
+    n = 6001
+    i = np.concatenate([np.zeros(6000, int), np.arange(1, 6000)])
+    j = np.concatenate([np.arange(1, 6001), np.arange(2, 6001)])
+    out.append(("bighub", lap(n, i, j, rng.uniform(0.1, 1.0, len(i))), None))
+    # power-law degrees (Chung-Lu, beta 2.1)
+    i, j = inputs.chung_lu_edges(1 << 14, 16.0, 2.1, rng)
+    m, i, j, _ = inputs.largest_component(1 << 14, i, j)
+    out.append(("chung_lu_16k", lap(m, i, j, rng.uniform(0.5, 2.0, len(i))), None))
     # SDDM with a ground vertex
     n = 300
     i, j = inputs.connected_random_edges(n, 3 * n, rng)
@@ -61,9 +72,13 @@ def test_factor_bit_identical(orc, name, A, ex):
     need_gpu()
     rng = np.random.default_rng(sum(map(ord, name)) * 131 + A.n)
     perm = rng.permutation(A.n).astype(np.int32)
+    if name == "bighub":
+        perm[perm == 2500], perm[0] = perm[0], 2500  # the hub gets label 2500
     seed = 12345 + A.n
     ref = orc.factor(A, perm=perm, seed=seed)
     assert ref.status == 0
+    if name in ("bighub", "chung_lu_16k"):
+        assert ref.stats["max_gather"] > 2048
     f = gpu_factor(A, perm, seed)
     info = f.info()
     assert info["nnz_off"] == ref.nnz_off
@@ -93,6 +108,22 @@ def test_grid_size_invariance(orc, workers):
     perm = rng.permutation(n).astype(np.int32)
     ref = orc.factor(A, perm=perm, seed=99)
     f = gpu_factor(A, perm, 99, workers=workers)
+    compare_factor(f, ref)
+
+
+@pytest.mark.parametrize("tail", [-1.0, 0.3, 1.0])
+def test_tail_kernel_split_is_exact(orc, tail):
+    """The wide persistent kernel may hand the last pivots to the
+    single-workgroup tail kernel at any point (none, 30%, all): the factor
+    does not change."""
+    need_gpu()
+    rng = np.random.default_rng(15)
+    i, j = inputs.grid3d_edges(16, 15, 14)
+    n = 16 * 15 * 14
+    A = lap(n, i, j, 10.0 ** rng.uniform(-2, 2, len(i)))
+    perm = rng.permutation(n).astype(np.int32)
+    ref = orc.factor(A, perm=perm, seed=21)
+    f = gpu_factor(A, perm, 21, tail_fraction=tail)
     compare_factor(f, ref)
 
 
