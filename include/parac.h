@@ -133,10 +133,36 @@ parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
 /* z = M^+ r with M = P^T F D F^T P (SDDM: ground row/column dropped, §V).
  *   r, z       device pointers, original vertex order, n x nrhs row-major
  *   precision  PARAC_PREC_FP64, or PARAC_PREC_MIXED (needs keep_fp32)
- * The forward solve F y = P r and the backward solve F^T x = D^+ y run as
- * level-ordered sync-free triangular solves.  Errors: EINVAL. */
+ * The forward solve F y = P r and the backward solve F^T x = D^+ y run level
+ * by level (rows of one elimination level are independent).  With nrhs > 1
+ * the columns are solved together in chunks of 64 (factor read once per
+ * chunk); every column equals, bit for bit, the apply of that column alone.
+ * The call returns after the result is complete.  Errors: EINVAL. */
 parac_status parac_apply(parac_factor_t f, const double *r, double *z,
                          int64_t nrhs, int32_t precision, void *stream);
+
+/* Launch shape of the block (nrhs > 1) apply for chunks of `cols` columns
+ * (1..64) in one precision.  Results do not depend on it, only speed.
+ *   cpl        columns per lane: 1, 2 or 4
+ *   tail_rows  levels at most this wide, and all levels after them, are
+ *              solved by a single workgroup (the rest one launch per level)
+ * Unless set, the first block apply of a factor times the candidate shapes
+ * on its own input and keeps the fastest. */
+typedef struct {
+  int32_t cpl;
+  int64_t tail_rows;
+} parac_block_shape;
+
+/* Fix (shape != NULL) or forget (shape == NULL: time again on next use)
+ * the shape for (cols, precision).  Errors: EINVAL. */
+parac_status parac_block_shape_set(parac_factor_t f, int32_t cols,
+                                   int32_t precision,
+                                   const parac_block_shape *shape);
+
+/* The shape in use for (cols, precision); EINVAL if none is fixed yet. */
+parac_status parac_block_shape_get(parac_factor_t f, int32_t cols,
+                                   int32_t precision,
+                                   parac_block_shape *shape);
 
 typedef struct {
   double rtol;            /* stop when ||r_k|| <= rtol ||b|| (default 1e-6) */
@@ -161,8 +187,10 @@ typedef struct {
 
 /* Preconditioned conjugate gradients with x0 = 0 (§V methodology; the
  * textbook recurrence).  With nrhs > 1 the columns run as independent
- * recurrences in one block launch sequence (matrix and factor read once per
- * iteration for all columns).
+ * recurrences (own alpha, beta and stopping test) in one block launch
+ * sequence per chunk of 64 columns: matrix and factor are read once per
+ * iteration for all columns of a chunk; a converged column is frozen while
+ * the others go on.
  *   A      the matrix the factor was built from (device arrays)
  *   b, x   device pointers, n x nrhs row-major; x is output only
  *   st     host array of nrhs stats (may be NULL)
@@ -194,17 +222,32 @@ typedef struct {
 typedef struct {
   size_t hbm_budget;      /* bytes the stream may hold resident (0 = 80% of
                              free device memory)                            */
-  int32_t max_slots;      /* concurrently admitted systems (0 = 32)         */
+  int32_t max_slots;      /* concurrently admitted systems (0 = 32, at most
+                             256)                                           */
   int32_t precision;      /* PARAC_PREC_* for the batched PCG               */
   int32_t maxit;          /* per system (0 = 10000)                         */
+  int32_t check_every;    /* batched iterations between convergence checks
+                             (0 = 4)                                        */
 } parac_serve_opts;
 
-/* Continuous-batching serving loop: requests are admitted in arrival order
- * as slots and device memory allow, factored on arrival, and their PCG
- * iterations advance together in batched launches across all admitted
- * systems; results are copied to the caller's x as each system converges.
- * Errors: EINVAL for bad options; per-request failures (e.g. ENOMEM for a
- * system larger than the budget) are reported in out[i].status. */
+/* Continuous-batching serving loop (not in the paper, which solves one
+ * system at a time; each system here is the §III factorisation followed by
+ * the §V PCG).  Requests are replayed at their arrival times and admitted in
+ * arrival order while a slot is free and the budget holds the request's
+ * estimated peak footprint (input, elimination pools, factor, PCG vectors);
+ * once set up, the reservation shrinks to the bytes actually resident.  A
+ * worker thread uploads and factors admitted systems on its own stream while
+ * the PCG iterations of all set-up systems advance together: one launch per
+ * PCG phase covers every system in flight.  Each system's numbers depend on
+ * its own data only, so its x is bit for bit the one parac_factor +
+ * parac_pcg give for it alone (same seed, permutation and options).  Results
+ * go to the caller's x as each system converges or reaches maxit.
+ *   reqs, out  host arrays of n entries; request arrays are host memory,
+ *              borrowed until the call returns
+ * Errors: EINVAL for bad options, EDEVICE/ENOMEM if the device fails the
+ * loop itself; per-request failures (ENOMEM for a request larger than the
+ * whole budget, EINVAL, ENOTLAP, EINCONSISTENT, ENOCONV) go to
+ * out[i].status. */
 parac_status parac_serve(const parac_request *reqs, int64_t n,
                          const parac_serve_opts *o, parac_result *out);
 

@@ -7,6 +7,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -34,6 +39,8 @@ void chk(hipError_t e, const char *what) {
 // device allocations freed at scope exit unless kept
 struct Scratch {
   std::vector<void *> ptrs;
+  std::vector<size_t> sizes;
+  int64_t total = 0;  // bytes currently held
   template <class T>
   T *alloc(int64_t n, const char *what) {
     void *p = nullptr;
@@ -45,18 +52,27 @@ struct Scratch {
                                   " bytes for " + what + " failed"};
     }
     ptrs.push_back(p);
+    sizes.push_back(bytes);
+    total += (int64_t)bytes;
     return (T *)p;
   }
-  void keep(void *p, std::vector<void *> &dst) {
+  // hand p over to dst (not freed here any more); returns its size
+  int64_t keep(void *p, std::vector<void *> &dst) {
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
-    if (it != ptrs.end()) {
-      ptrs.erase(it);
-      dst.push_back(p);
-    }
+    if (it == ptrs.end()) return 0;
+    const size_t k = (size_t)(it - ptrs.begin());
+    const int64_t b = (int64_t)sizes[k];
+    ptrs.erase(it);
+    sizes.erase(sizes.begin() + (std::ptrdiff_t)k);
+    total -= b;
+    dst.push_back(p);
+    return b;
   }
   void release_all() {
     for (void *p : ptrs) (void)hipFree(p);
     ptrs.clear();
+    sizes.clear();
+    total = 0;
   }
   ~Scratch() { release_all(); }
 };
@@ -508,7 +524,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
                   (void *)F->lev, (void *)F->order, (void *)F->root, (void *)F->lptr,
                   (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
                   (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
-    if (p) tmp.keep(p, F->owned);
+    if (p) F->bytes += tmp.keep(p, F->owned);
   guard.ok = true;
   return F;
 }
@@ -549,6 +565,7 @@ static void ensure_work(parac_factor_t f, int prec) {
   f->owned.push_back(*py);
   chk(hipMalloc(px, m * el), "work vector");
   f->owned.push_back(*px);
+  f->bytes += 2 * (int64_t)(m * el);
 }
 
 static void apply_one(parac_factor_t f, const double *r, double *z, int prec, const int *skip,
@@ -559,6 +576,91 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, co
   void *y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
   void *x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
   chk(launch_apply(a, f->hlptr.data(), r, y, x, z, prec, s), "apply");
+}
+
+// ---------------------------------------------------------------------------
+// block apply (several right-hand sides, chunks of at most kBlockCols)
+// ---------------------------------------------------------------------------
+static int prec_slot(int prec) { return prec == PARAC_PREC_MIXED ? 1 : 0; }
+
+static void ensure_bwork(parac_factor_t f, int prec, int nc) {
+  const int k = prec_slot(prec);
+  if (f->bcols[k] >= nc) return;
+  const size_t el = k ? 4 : 8;
+  for (void **pp : {&f->bwy[k], &f->bwx[k]}) {
+    if (!*pp) continue;
+    f->owned.erase(std::remove(f->owned.begin(), f->owned.end(), *pp), f->owned.end());
+    (void)hipFree(*pp);
+    *pp = nullptr;
+    f->bytes -= (int64_t)((size_t)std::max<int64_t>(f->ntot, 1) * (size_t)f->bcols[k] * el);
+  }
+  f->bcols[k] = 0;
+  const size_t m = (size_t)std::max<int64_t>(f->ntot, 1) * (size_t)nc;
+  chk(hipMalloc(&f->bwy[k], m * el), "block work vector");
+  f->owned.push_back(f->bwy[k]);
+  chk(hipMalloc(&f->bwx[k], m * el), "block work vector");
+  f->owned.push_back(f->bwx[k]);
+  f->bcols[k] = nc;
+  f->bytes += 2 * (int64_t)(m * el);
+}
+
+// first level of the single-workgroup tail for a width threshold
+static int64_t tail_start(parac_factor_t f, int64_t rows) {
+  int64_t L0 = f->depth;
+  while (L0 > 0 && f->hlptr[L0] - f->hlptr[L0 - 1] <= rows) --L0;
+  return L0;
+}
+
+static void apply_block(parac_factor_t f, const parac_block_shape &shp, int nc, const double *r,
+                        int64_t ldr, double *z, int64_t ldz, int prec, const int *skip,
+                        hipStream_t s) {
+  if (f->n == 0) return;
+  ensure_bwork(f, prec, nc);
+  SolveArgs a = solve_args(f, skip);
+  BlockShape sh{shp.cpl, tail_start(f, shp.tail_rows)};
+  const int k = prec_slot(prec);
+  chk(launch_block_apply(a, f->hlptr.data(), sh, nc, r, ldr, f->bwy[k], f->bwx[k], z, ldz, prec,
+                         s),
+      "block apply");
+}
+
+// the shape for (nc, prec): fixed by the caller, or timed on this input
+// (r -> z, both overwritten by the real apply afterwards)
+static parac_block_shape block_shape(parac_factor_t f, int nc, int prec, const double *r,
+                                     int64_t ldr, double *z, int64_t ldz, hipStream_t s) {
+  const auto key = std::make_pair(nc, prec_slot(prec));
+  auto it = f->shapes.find(key);
+  if (it != f->shapes.end()) return it->second;
+  parac_block_shape best{1, kTailWidth};
+  if (f->n == 0) return best;
+  Events ev;
+  ev.create();
+  auto time_one = [&](const parac_block_shape &c) {
+    chk(hipEventRecord(ev.e[0], s), "hipEventRecord");
+    apply_block(f, c, nc, r, ldr, z, ldz, prec, nullptr, s);
+    chk(hipEventRecord(ev.e[1], s), "hipEventRecord");
+    chk(hipEventSynchronize(ev.e[1]), "sync");
+    return ev.ms(0, 1);
+  };
+  (void)time_one(best);  // warm-up
+  double tbest = time_one(best);
+  for (int cpl : {2, 4}) {  // columns per lane at the default tail
+    if (cpl > nc) continue;
+    parac_block_shape c{cpl, kTailWidth};
+    const double t = time_one(c);
+    if (t < tbest) tbest = t, best = c;
+  }
+  for (int64_t rows : {(int64_t)256, (int64_t)4096}) {  // then the tail threshold
+    parac_block_shape c{best.cpl, rows};
+    const double t = time_one(c);
+    if (t < tbest) tbest = t, best = c;
+  }
+  f->shapes[key] = best;
+  return best;
+}
+
+static bool shape_ok(const parac_block_shape &c) {
+  return (c.cpl == 1 || c.cpl == 2 || c.cpl == 4) && c.tail_rows >= 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -580,6 +682,89 @@ static void check_consistent(parac_factor_t f, const double *b, hipStream_t s) {
     throw Err{PARAC_EINCONSISTENT, "b has a nonzero sum on a component without excess"};
 }
 
+// device tables of one batch of systems (see serve.hip)
+struct Batch {
+  Scratch mem;
+  SlotBatch B;
+  std::vector<int32_t> htotal;
+};
+
+struct SlotView {
+  PcgSlot ps;  // blk0 / nblk are filled in by build_batch
+  parac_factor_t f;
+};
+
+// lay out the workgroups of a batch and upload its tables; partial must
+// hold the sum of slot_blocks(n) over the batch
+static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, double *partial,
+                        hipStream_t s) {
+  bt.mem.release_all();
+  bt.htotal.clear();
+  const int ns = (int)v.size();
+  std::vector<PcgSlot> ps(ns);
+  std::vector<ApplySlot> as(ns);
+  std::vector<int32_t> bslot, tsl;
+  int blk = 0;
+  int64_t maxL0 = 0;
+  for (int k = 0; k < ns; ++k) {
+    ps[k] = v[k].ps;
+    ps[k].nblk = slot_blocks(ps[k].n);
+    ps[k].blk0 = blk;
+    bslot.insert(bslot.end(), (size_t)ps[k].nblk, k);
+    blk += ps[k].nblk;
+    parac_factor_t f = v[k].f;
+    ensure_work(f, prec);
+    as[k].a = solve_args(f, ps[k].ist + 1);
+    as[k].r = ps[k].r;
+    as[k].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
+    as[k].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
+    as[k].z = ps[k].z;
+    maxL0 = std::max(maxL0, f->L0);
+    if (f->L0 < f->depth) tsl.push_back(k);
+  }
+  std::vector<int32_t> pre((size_t)std::max<int64_t>(maxL0, 1) * (ns + 1), 0);
+  bt.htotal.assign((size_t)maxL0, 0);
+  for (int64_t L = 0; L < maxL0; ++L) {
+    int32_t acc = 0;
+    for (int k = 0; k < ns; ++k) {
+      pre[L * (ns + 1) + k] = acc;
+      parac_factor_t f = v[k].f;
+      if (L < f->L0) acc += (int32_t)((f->hlptr[L + 1] - f->hlptr[L] + 255) / 256);
+    }
+    pre[L * (ns + 1) + ns] = acc;
+    bt.htotal[L] = acc;
+  }
+  PcgSlot *dps = bt.mem.alloc<PcgSlot>(ns, "batch slots");
+  ApplySlot *das = bt.mem.alloc<ApplySlot>(ns, "batch apply slots");
+  int32_t *dbs = bt.mem.alloc<int32_t>(blk, "batch block map");
+  int32_t *dpre = bt.mem.alloc<int32_t>((int64_t)pre.size(), "batch level table");
+  int32_t *dts = bt.mem.alloc<int32_t>((int64_t)tsl.size(), "batch tail slots");
+  chk(hipMemcpyAsync(dps, ps.data(), ns * sizeof(PcgSlot), hipMemcpyHostToDevice, s), "upload");
+  chk(hipMemcpyAsync(das, as.data(), ns * sizeof(ApplySlot), hipMemcpyHostToDevice, s), "upload");
+  chk(hipMemcpyAsync(dbs, bslot.data(), bslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+      "upload");
+  chk(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+      "upload");
+  if (!tsl.empty())
+    chk(hipMemcpyAsync(dts, tsl.data(), tsl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+        "upload");
+  chk(hipStreamSynchronize(s), "sync");  // the host tables above go out of scope
+  SlotBatch &B = bt.B;
+  B.nslots = ns;
+  B.nblocks = blk;
+  B.slots = dps;
+  B.bslot = dbs;
+  B.partial = partial;
+  B.aslots = das;
+  B.maxL0 = maxL0;
+  B.lvl_pre = dpre;
+  B.hlvl_total = bt.htotal.data();
+  B.ntail = (int)tsl.size();
+  B.tslot = dts;
+}
+
+// one system as a batch of one: the same launches, hence the same bits, as
+// when the system is served together with others
 static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double *x,
                    const parac_pcg_opts &o, parac_pcg_stats *st, hipStream_t s) {
   const int64_t n = f->n;
@@ -588,90 +773,548 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
   double *z = tmp.alloc<double>(n, "z");
   double *p = tmp.alloc<double>(n, "p");
   double *q = tmp.alloc<double>(n, "q");
-  const int nb = pcg_partials();
-  double *partial = tmp.alloc<double>(nb, "partials");
+  double *partial = tmp.alloc<double>(slot_blocks(n), "partials");
   double *dst = tmp.alloc<double>(8, "pcg scalars");
   int *ist = tmp.alloc<int>(4, "pcg flags");
+  const double hst0[8] = {0, 0, 0, 0, 0, 0, o.rtol, 0};
+  const int hist0[4] = {0, 0, o.maxit, 0};
+  chk(hipMemcpyAsync(dst, hst0, sizeof(hst0), hipMemcpyHostToDevice, s), "upload");
+  chk(hipMemcpyAsync(ist, hist0, sizeof(hist0), hipMemcpyHostToDevice, s), "upload");
+  Batch bt;
+  build_batch(bt, {SlotView{PcgSlot{n, A->rowptr, A->col, A->val, b, x, r, z, p, q, dst, ist, 0, 0},
+                            f}},
+              o.precision, partial, s);
+  const SlotBatch &B = bt.B;
   // optional phase timing: events bracket every apply
   std::vector<hipEvent_t> evs;
-  auto mark = [&]() {
-    if (!o.timing) return;
-    hipEvent_t e;
-    chk(hipEventCreate(&e), "hipEventCreate");
-    chk(hipEventRecord(e, s), "hipEventRecord");
-    evs.push_back(e);
-  };
   struct EvFree {
     std::vector<hipEvent_t> &v;
     ~EvFree() {
       for (auto e : v) (void)hipEventDestroy(e);
     }
   } evfree{evs};
-  hipEvent_t t0, t1;
-  chk(hipEventCreate(&t0), "hipEventCreate");
-  chk(hipEventCreate(&t1), "hipEventCreate");
-  evs.push_back(t0);
-  evs.push_back(t1);
-  const size_t napply_marks = 2;  // evs[0..1] are t0/t1
-  chk(hipEventRecord(t0, s), "hipEventRecord");
-  chk(hipMemsetAsync(dst, 0, 8 * sizeof(double), s), "memset");
-  chk(hipMemsetAsync(ist, 0, 4 * sizeof(int), s), "memset");
-  chk(hipMemsetAsync(p, 0, std::max<int64_t>(n, 1) * sizeof(double), s), "memset");
-  chk(hipMemcpyAsync(dst + 6, &o.rtol, sizeof(double), hipMemcpyHostToDevice, s), "copy");
-  chk(pcg_launch_init(n, b, x, r, partial, dst, ist, s), "pcg_init");
+  auto mark = [&](bool always) {
+    if (!o.timing && !always) return;
+    hipEvent_t e;
+    chk(hipEventCreate(&e), "hipEventCreate");
+    chk(hipEventRecord(e, s), "hipEventRecord");
+    evs.push_back(e);
+  };
+  mark(true);  // evs[0]: start
+  chk(slots_init(B, s), "pcg init");
   int applies = 0;
-  mark();
-  apply_one(f, r, z, o.precision, ist + 2, s);
-  mark();
+  mark(false);
+  chk(slots_apply(B, o.precision, s), "apply");
+  mark(false);
   ++applies;
-  chk(pcg_launch_rz(n, r, z, p, partial, dst, ist, 1, s), "pcg_rz");
+  chk(slots_rz(B, 1, s), "pcg rz");
   const int K = o.check_every > 0 ? o.check_every : 8;
   int launched = 0;
   int hist[2] = {0, 0};
   for (;;) {
-    int chunk = std::min(K, o.maxit - launched);
+    const int chunk = std::min(K, o.maxit - launched);
     if (chunk <= 0) break;
     for (int it = 0; it < chunk; ++it) {
-      chk(pcg_launch_step(n, A->rowptr, A->col, A->val, x, r, p, q, partial, dst, ist, s), "step");
-      mark();
-      apply_one(f, r, z, o.precision, ist + 2, s);
-      mark();
+      chk(slots_step(B, s), "pcg step");
+      mark(false);
+      chk(slots_apply(B, o.precision, s), "apply");
+      mark(false);
       ++applies;
-      chk(pcg_launch_rz(n, r, z, p, partial, dst, ist, 0, s), "pcg_rz");
+      chk(slots_rz(B, 0, s), "pcg rz");
     }
     launched += chunk;
     chk(hipMemcpyAsync(hist, ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read");
     chk(hipStreamSynchronize(s), "sync");
     if (hist[1]) break;
   }
-  chk(pcg_launch_true_res(n, A->rowptr, A->col, A->val, x, b, q, partial, dst, ist, s), "true_res");
-  chk(hipEventRecord(t1, s), "hipEventRecord");
+  chk(slots_true_res(B, s), "true residual");
+  mark(true);  // last: end
   double hst[8];
   chk(hipMemcpyAsync(hst, dst, sizeof(hst), hipMemcpyDeviceToHost, s), "read");
   chk(hipMemcpyAsync(hist, ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read");
   chk(hipStreamSynchronize(s), "sync");
-  const int done = hist[1];
+  const bool ok = hist[1] == 1;
   const double bn = sqrt(hst[0]);
   if (st) {
-    // applies that ran (skipped ones after convergence return at once)
+    // applies that ran (those after convergence return at once)
     const int ran = std::min(applies, hist[0] + 1);
     st->iterations = hist[0];
-    st->relres = bn > 0 ? sqrt(hst[3]) / bn : 0.0;
+    st->relres = (bn > 0 && hist[0] > 0) ? sqrt(hst[3]) / bn : 0.0;
     st->true_relres = bn > 0 ? sqrt(hst[7]) / bn : 0.0;
-    if (hist[0] == 0) st->relres = 0.0;
-    st->status = done ? PARAC_OK : PARAC_ENOCONV;
+    st->status = ok ? PARAC_OK : PARAC_ENOCONV;
     float ms = 0.f;
-    chk(hipEventElapsedTime(&ms, t0, t1), "elapsed");
+    chk(hipEventElapsedTime(&ms, evs.front(), evs.back()), "elapsed");
     st->ms_total = ms;
     st->ms_apply = 0.0;
     st->applies = ran;
-    for (size_t i = napply_marks; i + 1 < evs.size() && (int)((i - napply_marks) / 2) < ran;
-         i += 2) {
+    for (size_t i = 1; i + 2 < evs.size() && (int)((i - 1) / 2) < ran; i += 2) {
       chk(hipEventElapsedTime(&ms, evs[i], evs[i + 1]), "elapsed");
       st->ms_apply += ms;
     }
   }
-  return done ? PARAC_OK : PARAC_ENOCONV;
+  return ok ? PARAC_OK : PARAC_ENOCONV;
+}
+
+static void check_consistent_block(parac_factor_t f, const double *b, int64_t nrhs,
+                                   hipStream_t s) {
+  const int64_t n = f->n;
+  if (n == 0) return;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += kBlockCols) {
+    const int nc = (int)std::min<int64_t>(kBlockCols, nrhs - c0);
+    Scratch tmp;
+    const int64_t m = f->ntot * nc;
+    double *sum = tmp.alloc<double>(m, "sums");
+    double *sabs = tmp.alloc<double>(m, "sums");
+    int *bad = tmp.alloc<int>(1, "flag");
+    chk(hipMemsetAsync(sum, 0, m * sizeof(double), s), "memset");
+    chk(hipMemsetAsync(sabs, 0, m * sizeof(double), s), "memset");
+    chk(hipMemsetAsync(bad, 0, sizeof(int), s), "memset");
+    chk(launch_bcomp_check(n, nc, f->ntot > n ? n : -1, f->perm, f->root, b + c0, nrhs, sum,
+                           sabs, bad, s),
+        "comp_check");
+    if (read1(bad, s))
+      throw Err{PARAC_EINCONSISTENT,
+                "a column of b has a nonzero sum on a component without excess"};
+  }
+}
+
+// block PCG: chunks of at most kBlockCols columns, each chunk one sequence
+// of block launches with per-column scalars
+static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, double *x,
+                     int64_t nrhs, const parac_pcg_opts &o, parac_pcg_stats *st, hipStream_t s) {
+  const int64_t n = f->n;
+  int rc = PARAC_OK;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += kBlockCols) {
+    const int nc = (int)std::min<int64_t>(kBlockCols, nrhs - c0);
+    Scratch tmp;
+    const int64_t m = std::max<int64_t>(n, 1) * nc;
+    double *r = tmp.alloc<double>(m, "r");
+    double *z = tmp.alloc<double>(m, "z");
+    double *p = tmp.alloc<double>(m, "p");
+    double *q = tmp.alloc<double>(m, "q");
+    const int nb = bpcg_partials();
+    double *partial = tmp.alloc<double>((int64_t)nb * nc, "partials");
+    double *bst = tmp.alloc<double>(8 * nc, "pcg scalars");
+    int *bist = tmp.alloc<int>(4 * nc, "pcg flags");
+    int *gfl = tmp.alloc<int>(2, "pcg flags");
+    std::vector<hipEvent_t> evs;
+    struct EvFree {
+      std::vector<hipEvent_t> &v;
+      ~EvFree() {
+        for (auto e : v) (void)hipEventDestroy(e);
+      }
+    } evfree{evs};
+    auto mark = [&](bool always) {
+      if (!o.timing && !always) return;
+      hipEvent_t e;
+      chk(hipEventCreate(&e), "hipEventCreate");
+      chk(hipEventRecord(e, s), "hipEventRecord");
+      evs.push_back(e);
+    };
+    mark(true);  // evs[0]: start
+    chk(bpcg_launch_init(n, nc, o.rtol, b + c0, nrhs, x + c0, nrhs, r, p, partial, bst, bist, gfl,
+                         s),
+        "bpcg_init");
+    const parac_block_shape shp = block_shape(f, nc, o.precision, r, nc, z, nc, s);
+    int applies = 0;
+    mark(false);
+    apply_block(f, shp, nc, r, nc, z, nc, o.precision, gfl + 1, s);
+    mark(false);
+    ++applies;
+    chk(bpcg_launch_rz(n, nc, r, z, p, partial, bst, bist, gfl, 1, s), "bpcg_rz");
+    const int K = o.check_every > 0 ? o.check_every : 8;
+    int launched = 0;
+    int g[2] = {0, 0};
+    for (;;) {
+      const int chunk = std::min(K, o.maxit - launched);
+      if (chunk <= 0) break;
+      for (int it = 0; it < chunk; ++it) {
+        chk(bpcg_launch_step(n, nc, A->rowptr, A->col, A->val, x + c0, nrhs, r, p, q, partial, bst,
+                             bist, gfl, s),
+            "bpcg_step");
+        mark(false);
+        apply_block(f, shp, nc, r, nc, z, nc, o.precision, gfl + 1, s);
+        mark(false);
+        ++applies;
+        chk(bpcg_launch_rz(n, nc, r, z, p, partial, bst, bist, gfl, 0, s), "bpcg_rz");
+      }
+      launched += chunk;
+      chk(hipMemcpyAsync(g, gfl, sizeof(g), hipMemcpyDeviceToHost, s), "read");
+      chk(hipStreamSynchronize(s), "sync");
+      if (g[1]) break;
+    }
+    chk(bpcg_launch_true_res(n, nc, A->rowptr, A->col, A->val, x + c0, nrhs, b + c0, nrhs, q,
+                             partial, bst, bist, gfl, s),
+        "bpcg_true_res");
+    mark(true);  // last: end
+    std::vector<double> hst(8 * nc);
+    std::vector<int> hist(4 * nc);
+    chk(hipMemcpyAsync(hst.data(), bst, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s),
+        "read");
+    chk(hipMemcpyAsync(hist.data(), bist, hist.size() * sizeof(int), hipMemcpyDeviceToHost, s),
+        "read");
+    chk(hipStreamSynchronize(s), "sync");
+    int maxit_seen = 0;
+    for (int j = 0; j < nc; ++j) maxit_seen = std::max(maxit_seen, hist[4 * j]);
+    const int ran = std::min(applies, maxit_seen + 1);
+    float ms = 0.f;
+    chk(hipEventElapsedTime(&ms, evs.front(), evs.back()), "elapsed");
+    const double ms_total = ms;
+    double ms_apply = 0.0;
+    for (size_t i = 1; i + 2 < evs.size() && (int)((i - 1) / 2) < ran; i += 2) {
+      chk(hipEventElapsedTime(&ms, evs[i], evs[i + 1]), "elapsed");
+      ms_apply += ms;
+    }
+    for (int j = 0; j < nc; ++j) {
+      const double bn = sqrt(hst[8 * j]);
+      const bool done = hist[4 * j + 1] != 0;
+      if (!done) rc = PARAC_ENOCONV;
+      if (!st) continue;
+      parac_pcg_stats &o1 = st[c0 + j];
+      o1.iterations = hist[4 * j];
+      o1.relres = (bn > 0 && hist[4 * j] > 0) ? sqrt(hst[8 * j + 3]) / bn : 0.0;
+      o1.true_relres = bn > 0 ? sqrt(hst[8 * j + 7]) / bn : 0.0;
+      o1.status = done ? PARAC_OK : PARAC_ENOCONV;
+      o1.ms_total = ms_total;
+      o1.ms_apply = ms_apply;
+      o1.applies = ran;
+    }
+  }
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// serving loop
+// ---------------------------------------------------------------------------
+namespace {
+
+// one admitted system: its device copy of the request, factor and PCG state
+struct ServeSlot {
+  int64_t req = -1;
+  int id = -1;  // row of the per-call scalar pools
+  parac_factor_t f = nullptr;
+  Scratch mem;
+  int64_t n = 0;
+  const int64_t *rowptr = nullptr;
+  const int32_t *col = nullptr;
+  const double *val = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  int64_t est = 0, bytes = 0;
+  int status = PARAC_OK;
+  std::string err;
+  ~ServeSlot() {
+    if (f) {
+      for (void *ptr : f->owned) (void)hipFree(ptr);
+      delete f;
+    }
+  }
+};
+
+// estimated peak device bytes of one request: input, PCG vectors, and the
+// elimination's pools and factor arrays at their largest (pool_factor 4)
+int64_t serve_estimate(int64_t n, int64_t nnz) {
+  const int64_t ntot = n + 1;
+  return 12 * nnz + 8 * (n + 1) + 6 * 8 * n + 170 * nnz + 340 * ntot + (1 << 20);
+}
+
+struct SetupQueue {
+  std::mutex m;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::unique_ptr<ServeSlot>> todo, done;
+  bool stop = false;
+};
+
+// upload and factor one admitted request (worker thread, its own stream)
+void serve_setup(ServeSlot &sl, const parac_request &rq, int prec, int maxit, double *st_pool,
+                 int *ist_pool, hipStream_t s) {
+  const int64_t n = rq.A.n, nnz = rq.A.nnz;
+  if (n < 0 || nnz < 0 || rq.A.on_device ||
+      (n > 0 && (!rq.A.rowptr || !rq.A.col || !rq.A.val || !rq.b || !rq.x)))
+    throw Err{PARAC_EINVAL, "a request needs host CSR arrays, b and x"};
+  Scratch &M = sl.mem;
+  int64_t *rp = M.alloc<int64_t>(n + 1, "request rowptr");
+  int32_t *c = M.alloc<int32_t>(nnz, "request col");
+  double *v = M.alloc<double>(nnz, "request val");
+  double *b = M.alloc<double>(n, "request b");
+  int32_t *pm = rq.perm ? M.alloc<int32_t>(n, "request perm") : nullptr;
+  if (n > 0) {
+    chk(hipMemcpyAsync(rp, rq.A.rowptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s),
+        "upload");
+    chk(hipMemcpyAsync(c, rq.A.col, nnz * sizeof(int32_t), hipMemcpyHostToDevice, s), "upload");
+    chk(hipMemcpyAsync(v, rq.A.val, nnz * sizeof(double), hipMemcpyHostToDevice, s), "upload");
+    chk(hipMemcpyAsync(b, rq.b, n * sizeof(double), hipMemcpyHostToDevice, s), "upload");
+    if (pm) chk(hipMemcpyAsync(pm, rq.perm, n * sizeof(int32_t), hipMemcpyHostToDevice, s), "upload");
+  }
+  parac_csr dA{n, nnz, rp, c, v, 1};
+  parac_factor_opts fo{};
+  fo.seed = rq.seed;
+  fo.perm = pm;
+  fo.mode = PARAC_MODE_AUTO;
+  fo.pool_factor = 4.0;
+  fo.keep_fp32 = prec == PARAC_PREC_MIXED;
+  fo.timeout_s = 30.0;
+  sl.f = factor_impl(&dA, &fo, s);
+  if (sl.f->mode == PARAC_MODE_LAPLACIAN) check_consistent(sl.f, b, s);
+  sl.n = n;
+  sl.rowptr = rp;
+  sl.col = c;
+  sl.val = v;
+  sl.b = b;
+  sl.x = M.alloc<double>(n, "x");
+  sl.r = M.alloc<double>(n, "r");
+  sl.z = M.alloc<double>(n, "z");
+  sl.p = M.alloc<double>(n, "p");
+  sl.q = M.alloc<double>(n, "q");
+  ensure_work(sl.f, prec);
+  const double rtol = rq.rtol >= 0 ? rq.rtol : 1e-6;
+  const double hst0[8] = {0, 0, 0, 0, 0, 0, rtol, 0};
+  const int hist0[4] = {0, 0, maxit, 0};
+  chk(hipMemcpyAsync(st_pool + 8 * sl.id, hst0, sizeof(hst0), hipMemcpyHostToDevice, s), "upload");
+  chk(hipMemcpyAsync(ist_pool + 4 * sl.id, hist0, sizeof(hist0), hipMemcpyHostToDevice, s),
+      "upload");
+  chk(hipStreamSynchronize(s), "sync");
+  sl.bytes = M.total + sl.f->bytes;
+}
+
+SlotView slot_view(ServeSlot &sl, double *st_pool, int *ist_pool) {
+  return SlotView{PcgSlot{sl.n, sl.rowptr, sl.col, sl.val, sl.b, sl.x, sl.r, sl.z, sl.p, sl.q,
+                          st_pool + 8 * sl.id, ist_pool + 4 * sl.id, 0, 0},
+                  sl.f};
+}
+
+}  // namespace
+
+static int serve_impl(const parac_request *reqs, int64_t nreq, const parac_serve_opts &o,
+                      parac_result *out) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto now = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  const int prec = o.precision;
+  const int max_slots = o.max_slots;
+  const int K = o.check_every;
+  int dev = 0;
+  chk(hipGetDevice(&dev), "hipGetDevice");
+  size_t budget = o.hbm_budget;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    chk(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    budget = (size_t)(0.8 * (double)fr);
+  }
+  for (int64_t i = 0; i < nreq; ++i) {
+    out[i] = parac_result{};
+    out[i].status = PARAC_OK;
+    out[i].t_arrive = reqs[i].arrival_s;
+  }
+  std::vector<int64_t> order(nreq);
+  for (int64_t i = 0; i < nreq; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return reqs[a].arrival_s < reqs[b].arrival_s;
+  });
+
+  Scratch pools;
+  double *st_pool = pools.alloc<double>(8 * (int64_t)max_slots, "serve scalars");
+  int *ist_pool = pools.alloc<int>(4 * (int64_t)max_slots, "serve flags");
+  double *partial = pools.alloc<double>((int64_t)max_slots * kSlotMaxBlocks, "serve partials");
+  hipStream_t cs = nullptr;
+  chk(hipStreamCreate(&cs), "hipStreamCreate");
+  struct StreamFree {
+    hipStream_t &s;
+    ~StreamFree() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } csfree{cs};
+
+  // the setup worker
+  SetupQueue Q;
+  std::thread worker([&]() {
+    (void)hipSetDevice(dev);
+    hipStream_t ss = nullptr;
+    const bool have_stream = hipStreamCreate(&ss) == hipSuccess;
+    for (;;) {
+      std::unique_ptr<ServeSlot> sl;
+      {
+        std::unique_lock<std::mutex> lk(Q.m);
+        Q.cv_work.wait(lk, [&] { return Q.stop || !Q.todo.empty(); });
+        if (Q.todo.empty()) break;
+        sl = std::move(Q.todo.front());
+        Q.todo.pop_front();
+      }
+      try {
+        if (!have_stream) throw Err{PARAC_EDEVICE, "setup stream"};
+        serve_setup(*sl, reqs[sl->req], prec, o.maxit, st_pool, ist_pool, ss);
+      } catch (Err &e) {
+        sl->status = e.code;
+        sl->err = e.msg;
+      } catch (std::exception &e) {
+        sl->status = PARAC_EINTERNAL;
+        sl->err = e.what();
+      }
+      {
+        std::lock_guard<std::mutex> lk(Q.m);
+        Q.done.push_back(std::move(sl));
+      }
+      Q.cv_done.notify_one();
+    }
+    if (ss) (void)hipStreamDestroy(ss);
+  });
+  struct Joiner {
+    SetupQueue &Q;
+    std::thread &t;
+    ~Joiner() {
+      {
+        std::lock_guard<std::mutex> lk(Q.m);
+        Q.stop = true;
+      }
+      Q.cv_work.notify_all();
+      if (t.joinable()) t.join();
+    }
+  } joiner{Q, worker};
+
+  std::vector<int> free_ids;
+  for (int k = max_slots - 1; k >= 0; --k) free_ids.push_back(k);
+  std::vector<std::unique_ptr<ServeSlot>> active;
+  int64_t next = 0, finished = 0, inflight = 0;
+  size_t reserved = 0;
+  Batch bt;
+  bool dirty = true;
+  std::vector<int> hflags(4 * (size_t)max_slots);
+
+  auto retire = [&](ServeSlot &sl, int status) {
+    parac_result &r = out[sl.req];
+    r.status = status;
+    r.t_done = now();
+    r.bytes_resident = sl.bytes;
+    reserved -= (size_t)(sl.bytes ? sl.bytes : sl.est);
+    free_ids.push_back(sl.id);
+    --inflight;
+    ++finished;
+  };
+
+  while (finished < nreq) {
+    // 1. admission in arrival order
+    const double t = now();
+    while (next < nreq && reqs[order[next]].arrival_s <= t) {
+      const int64_t i = order[next];
+      const int64_t est = serve_estimate(std::max<int64_t>(reqs[i].A.n, 0),
+                                         std::max<int64_t>(reqs[i].A.nnz, 0));
+      if ((size_t)est > budget) {
+        out[i].status = PARAC_ENOMEM;
+        out[i].t_admit = out[i].t_done = t;
+        ++next;
+        ++finished;
+        continue;
+      }
+      if (free_ids.empty() || reserved + (size_t)est > budget) break;
+      auto sl = std::make_unique<ServeSlot>();
+      sl->req = i;
+      sl->id = free_ids.back();
+      free_ids.pop_back();
+      sl->est = est;
+      reserved += (size_t)est;
+      ++inflight;
+      out[i].t_admit = t;
+      {
+        std::lock_guard<std::mutex> lk(Q.m);
+        Q.todo.push_back(std::move(sl));
+      }
+      Q.cv_work.notify_one();
+      ++next;
+    }
+    // 2. systems the worker has set up: start their PCG, then join the batch
+    std::vector<std::unique_ptr<ServeSlot>> fresh;
+    {
+      std::lock_guard<std::mutex> lk(Q.m);
+      while (!Q.done.empty()) {
+        fresh.push_back(std::move(Q.done.front()));
+        Q.done.pop_front();
+      }
+    }
+    std::vector<std::unique_ptr<ServeSlot>> started;
+    for (auto &sl : fresh) {
+      if (sl->status != PARAC_OK) {
+        retire(*sl, sl->status);
+        continue;
+      }
+      reserved = reserved - (size_t)sl->est + (size_t)sl->bytes;
+      started.push_back(std::move(sl));
+    }
+    if (!started.empty()) {
+      std::vector<SlotView> v;
+      for (auto &sl : started) v.push_back(slot_view(*sl, st_pool, ist_pool));
+      Batch nb;
+      build_batch(nb, v, prec, partial, cs);
+      chk(slots_init(nb.B, cs), "serve init");
+      chk(slots_apply(nb.B, prec, cs), "serve apply");
+      chk(slots_rz(nb.B, 1, cs), "serve rz");
+      chk(hipStreamSynchronize(cs), "sync");
+      for (auto &sl : started) active.push_back(std::move(sl));
+      dirty = true;
+    }
+    if (active.empty()) {
+      // nothing to iterate: wait for the worker or the next arrival
+      std::unique_lock<std::mutex> lk(Q.m);
+      double wait = 1e-3;
+      if (inflight == 0 && next < nreq)
+        wait = std::max(0.0, reqs[order[next]].arrival_s - now());
+      if (Q.done.empty())
+        Q.cv_done.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.05)));
+      continue;
+    }
+    // 3. K batched iterations over every system in flight
+    if (dirty) {
+      std::vector<SlotView> v;
+      for (auto &sl : active) v.push_back(slot_view(*sl, st_pool, ist_pool));
+      build_batch(bt, v, prec, partial, cs);
+      dirty = false;
+    }
+    for (int it = 0; it < K; ++it) {
+      chk(slots_step(bt.B, cs), "serve step");
+      chk(slots_apply(bt.B, prec, cs), "serve apply");
+      chk(slots_rz(bt.B, 0, cs), "serve rz");
+    }
+    chk(hipMemcpyAsync(hflags.data(), ist_pool, hflags.size() * sizeof(int),
+                       hipMemcpyDeviceToHost, cs),
+        "read");
+    chk(hipStreamSynchronize(cs), "sync");
+    // 4. finished systems: true residual, x back to the caller, release
+    std::vector<std::unique_ptr<ServeSlot>> fin, keep;
+    for (auto &sl : active) {
+      if (hflags[4 * sl->id + 1]) fin.push_back(std::move(sl));
+      else keep.push_back(std::move(sl));
+    }
+    if (fin.empty()) continue;
+    active = std::move(keep);
+    dirty = true;
+    {
+      std::vector<SlotView> v;
+      for (auto &sl : fin) v.push_back(slot_view(*sl, st_pool, ist_pool));
+      Batch fb;
+      build_batch(fb, v, prec, partial, cs);
+      chk(slots_true_res(fb.B, cs), "serve residual");
+    }
+    std::vector<double> hst(8 * (size_t)max_slots);
+    chk(hipMemcpyAsync(hst.data(), st_pool, hst.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       cs),
+        "read");
+    chk(hipMemcpyAsync(hflags.data(), ist_pool, hflags.size() * sizeof(int),
+                       hipMemcpyDeviceToHost, cs),
+        "read");
+    for (auto &sl : fin)
+      if (sl->n > 0)
+        chk(hipMemcpyAsync(reqs[sl->req].x, sl->x, sl->n * sizeof(double), hipMemcpyDeviceToHost,
+                           cs),
+            "result copy");
+    chk(hipStreamSynchronize(cs), "sync");
+    for (auto &sl : fin) {
+      const int id = sl->id;
+      const double bn = sqrt(hst[8 * id]);
+      parac_result &r = out[sl->req];
+      r.iterations = hflags[4 * id];
+      r.true_relres = bn > 0 ? sqrt(hst[8 * id + 7]) / bn : 0.0;
+      retire(*sl, hflags[4 * id + 1] == 1 ? PARAC_OK : PARAC_ENOCONV);
+    }
+  }
+  return PARAC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -741,13 +1384,17 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z, int64_t n
     g_last_error = "bad precision";
     return PARAC_EINVAL;
   }
-  if (nrhs != 1) {
-    g_last_error = "apply: use parac_pcg for several right-hand sides";
-    return PARAC_EINVAL;
-  }
   try {
     hipStream_t s = (hipStream_t)stream;
-    apply_one(f, r, z, precision, nullptr, s);
+    if (nrhs == 1) {
+      apply_one(f, r, z, precision, nullptr, s);
+    } else {
+      for (int64_t c0 = 0; c0 < nrhs; c0 += kBlockCols) {
+        const int nc = (int)std::min<int64_t>(kBlockCols, nrhs - c0);
+        const parac_block_shape shp = block_shape(f, nc, precision, r + c0, nrhs, z + c0, nrhs, s);
+        apply_block(f, shp, nc, r + c0, nrhs, z + c0, nrhs, precision, nullptr, s);
+      }
+    }
     chk(hipStreamSynchronize(s), "sync");
     return PARAC_OK;
   } catch (Err &e) {
@@ -775,23 +1422,74 @@ parac_status parac_pcg(const parac_csr *A, parac_factor_t f, const double *b, do
   }
   try {
     hipStream_t s = (hipStream_t)stream;
-    if (nrhs != 1) throw Err{PARAC_EINVAL, "block PCG not available in this build"};
-    check_consistent(f, b, s);
-    return pcg_one(A, f, b, x, opt, st, s);
+    if (nrhs == 1) {
+      check_consistent(f, b, s);
+      return pcg_one(A, f, b, x, opt, st, s);
+    }
+    check_consistent_block(f, b, nrhs, s);
+    return pcg_block(A, f, b, x, nrhs, opt, st, s);
   } catch (Err &e) {
-    if (st) st->status = e.code;
+    if (st)
+      for (int64_t j = 0; j < nrhs; ++j) st[j].status = e.code;
     return status_from(e);
   }
 }
 
+parac_status parac_block_shape_set(parac_factor_t f, int32_t cols, int32_t precision,
+                                   const parac_block_shape *shape) {
+  if (!f || cols < 1 || cols > kBlockCols ||
+      (precision != PARAC_PREC_FP64 && precision != PARAC_PREC_MIXED) ||
+      (shape && !shape_ok(*shape))) {
+    g_last_error = "bad block shape arguments";
+    return PARAC_EINVAL;
+  }
+  const auto key = std::make_pair((int)cols, prec_slot(precision));
+  if (shape)
+    f->shapes[key] = *shape;
+  else
+    f->shapes.erase(key);
+  return PARAC_OK;
+}
+
+parac_status parac_block_shape_get(parac_factor_t f, int32_t cols, int32_t precision,
+                                   parac_block_shape *shape) {
+  if (!f || !shape) {
+    g_last_error = "null argument";
+    return PARAC_EINVAL;
+  }
+  auto it = f->shapes.find(std::make_pair((int)cols, prec_slot(precision)));
+  if (it == f->shapes.end()) {
+    g_last_error = "no block shape fixed for these columns and precision";
+    return PARAC_EINVAL;
+  }
+  *shape = it->second;
+  return PARAC_OK;
+}
+
 parac_status parac_serve(const parac_request *reqs, int64_t n, const parac_serve_opts *o,
                          parac_result *out) {
-  (void)reqs;
-  (void)n;
-  (void)o;
-  (void)out;
-  g_last_error = "serving loop not available in this build";
-  return PARAC_EINVAL;
+  if (n < 0 || (n > 0 && (!reqs || !out))) {
+    g_last_error = "bad serve arguments";
+    return PARAC_EINVAL;
+  }
+  parac_serve_opts opt{};
+  if (o) opt = *o;
+  if (opt.max_slots == 0) opt.max_slots = 32;
+  if (opt.maxit <= 0) opt.maxit = 10000;
+  if (opt.check_every <= 0) opt.check_every = 4;
+  if (opt.max_slots < 1 || opt.max_slots > 256 ||
+      (opt.precision != PARAC_PREC_FP64 && opt.precision != PARAC_PREC_MIXED)) {
+    g_last_error = "bad serve options";
+    return PARAC_EINVAL;
+  }
+  try {
+    return serve_impl(reqs, n, opt, out);
+  } catch (Err &e) {
+    return status_from(e);
+  } catch (std::exception &e) {
+    g_last_error = e.what();
+    return PARAC_EINTERNAL;
+  }
 }
 
 void parac_factor_free(parac_factor_t f) {

@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <string>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "parac.h"
@@ -145,23 +147,76 @@ hipError_t launch_level_copy(int64_t n, const int32_t *order, const int64_t *row
                              const int64_t *lb_ptr, int32_t *lf_idx, double *lf_val,
                              int32_t *lb_idx, double *lb_val, hipStream_t s);
 constexpr int kTailWidth = 1024;  // levels this narrow (and all above) form the tail
-int pcg_partials();
-hipError_t pcg_launch_init(int64_t n, const double *b, double *x, double *r, double *partial,
-                           double *st, int *ist, hipStream_t s);
-hipError_t pcg_launch_rz(int64_t n, const double *r, const double *z, double *p, double *partial,
-                         double *st, int *ist, int first, hipStream_t s);
-hipError_t pcg_launch_step(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-                           double *x, double *r, double *p, double *q, double *partial, double *st,
-                           int *ist, hipStream_t s);
-hipError_t pcg_launch_true_res(int64_t n, const int64_t *rowptr, const int32_t *col,
-                               const double *val, const double *x, const double *b, double *tmp,
-                               double *partial, double *st, int *ist, hipStream_t s);
 hipError_t launch_comp_init(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
                             int32_t *parent, hipStream_t s);
 hipError_t launch_comp_jump(int64_t ntot, const int32_t *src, int32_t *dst, int *changed,
                             hipStream_t s);
 hipError_t launch_comp_check(int64_t n, int64_t ground, const int32_t *perm, const int32_t *root,
                              const double *b, double *sum, double *sabs, int *bad, hipStream_t s);
+
+// --- block.hip (several right-hand sides, row-major blocks of nc columns) ---
+constexpr int kBlockCols = 64;  // columns per block launch
+struct BlockShape {
+  int cpl;     // columns per lane: 1, 2 or 4
+  int64_t L0;  // first level solved by the single-workgroup tail
+};
+hipError_t launch_block_apply(const SolveArgs &a, const int64_t *hlptr, const BlockShape &sh,
+                              int nc, const double *r, int64_t ldr, void *y, void *x, double *z,
+                              int64_t ldz, int prec, hipStream_t s);
+int bpcg_partials();
+hipError_t bpcg_launch_init(int64_t n, int nc, double rtol, const double *b, int64_t ldb,
+                            double *x, int64_t ldx, double *r, double *p, double *partial,
+                            double *bst, int *bist, int *gfl, hipStream_t s);
+hipError_t bpcg_launch_rz(int64_t n, int nc, const double *r, const double *z, double *p,
+                          double *partial, double *bst, int *bist, int *gfl, int first,
+                          hipStream_t s);
+hipError_t bpcg_launch_step(int64_t n, int nc, const int64_t *rowptr, const int32_t *col,
+                            const double *val, double *x, int64_t ldx, double *r, double *p,
+                            double *q, double *partial, double *bst, int *bist, int *gfl,
+                            hipStream_t s);
+hipError_t bpcg_launch_true_res(int64_t n, int nc, const int64_t *rowptr, const int32_t *col,
+                                const double *val, const double *x, int64_t ldx, const double *b,
+                                int64_t ldb, double *tmp, double *partial, double *bst, int *bist,
+                                int *gfl, hipStream_t s);
+hipError_t launch_bcomp_check(int64_t n, int nc, int64_t ground, const int32_t *perm,
+                              const int32_t *root, const double *b, int64_t ldb, double *sum,
+                              double *sabs, int *bad, hipStream_t s);
+
+// --- serve.hip (PCG over a batch of independent systems) ---
+constexpr int kSlotMaxBlocks = 1024;  // reduction workgroups of one system
+struct PcgSlot {
+  int64_t n;
+  const int64_t *rowptr; const int32_t *col; const double *val;  // A (device)
+  const double *b;
+  double *x, *r, *z, *p, *q;
+  double *st;  // 8 scalars: ||b||^2, r.z, p.q, r.r, alpha, beta, rtol, true res^2
+  int *ist;    // iterations, done (1 converged, 2 iteration cap), cap, unused
+  int32_t blk0, nblk;  // the system's workgroups in a batched launch
+};
+struct ApplySlot {
+  SolveArgs a;  // a.skip points at the system's done flag
+  const double *r;
+  void *y, *x;  // label-space work vectors (precision of the apply)
+  double *z;
+};
+struct SlotBatch {
+  int nslots = 0, nblocks = 0;
+  const PcgSlot *slots = nullptr;   // device [nslots]
+  const int32_t *bslot = nullptr;   // device [nblocks]: slot of each workgroup
+  double *partial = nullptr;        // device [nblocks]
+  const ApplySlot *aslots = nullptr;  // device [nslots]
+  int64_t maxL0 = 0;
+  const int32_t *lvl_pre = nullptr;   // device [maxL0 * (nslots + 1)]
+  const int32_t *hlvl_total = nullptr;  // host [maxL0]: workgroups of each level launch
+  int ntail = 0;
+  const int32_t *tslot = nullptr;   // device [ntail]: slots with a thin tail
+};
+int slot_blocks(int64_t n);
+hipError_t slots_init(const SlotBatch &B, hipStream_t s);
+hipError_t slots_rz(const SlotBatch &B, int first, hipStream_t s);
+hipError_t slots_step(const SlotBatch &B, hipStream_t s);
+hipError_t slots_true_res(const SlotBatch &B, hipStream_t s);
+hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s);
 
 }  // namespace parac
 
@@ -187,5 +242,11 @@ struct parac_factor_s {
   std::vector<int64_t> hlptr;  // host copy of lptr
   // solve work vectors (label space)
   void *wy64 = nullptr, *wx64 = nullptr, *wy32 = nullptr, *wx32 = nullptr;
+  // block work vectors (ntot x bcols) per precision, launch shape per
+  // (columns, precision): set by the caller or picked by timing
+  void *bwy[2] = {nullptr, nullptr}, *bwx[2] = {nullptr, nullptr};
+  int64_t bcols[2] = {0, 0};
+  std::map<std::pair<int, int>, parac_block_shape> shapes;
   std::vector<void *> owned;
+  int64_t bytes = 0;  // device bytes held by the factor's own arrays
 };

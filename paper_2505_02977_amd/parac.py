@@ -59,6 +59,10 @@ class parac_pcg_stats(C.Structure):
                 ("applies", C.c_int32)]
 
 
+class parac_block_shape(C.Structure):
+    _fields_ = [("cpl", C.c_int32), ("tail_rows", C.c_int64)]
+
+
 class parac_request(C.Structure):
     _fields_ = [("A", parac_csr), ("perm", C.c_void_p), ("b", C.c_void_p), ("x", C.c_void_p),
                 ("seed", C.c_uint64), ("rtol", C.c_double), ("arrival_s", C.c_double)]
@@ -72,7 +76,7 @@ class parac_result(C.Structure):
 
 class parac_serve_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("precision", C.c_int32),
-                ("maxit", C.c_int32)]
+                ("maxit", C.c_int32), ("check_every", C.c_int32)]
 
 
 _lib = None
@@ -96,12 +100,14 @@ def lib():
                                 C.POINTER(parac_pcg_opts), C.POINTER(parac_pcg_stats), P]
         L.parac_serve.argtypes = [C.POINTER(parac_request), C.c_int64,
                                   C.POINTER(parac_serve_opts), C.POINTER(parac_result)]
+        L.parac_block_shape_set.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(parac_block_shape)]
+        L.parac_block_shape_get.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(parac_block_shape)]
         L.parac_factor_free.argtypes = [P]
         L.parac_status_str.restype = C.c_char_p
         L.parac_status_str.argtypes = [C.c_int]
         L.parac_last_error.restype = C.c_char_p
         for name in ("parac_factor", "parac_factor_info", "parac_factor_export", "parac_apply",
-                     "parac_pcg", "parac_serve"):
+                     "parac_pcg", "parac_serve", "parac_block_shape_set", "parac_block_shape_get"):
             getattr(L, name).restype = C.c_int
         L.parac_factor_free.restype = None
         _lib = L
@@ -177,16 +183,34 @@ def parac_factor(A: DeviceCSR, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.
 
 
 def parac_apply(f: Factor, r, z, precision=PREC_FP64, stream=None):
-    """z = M^+ r for device tensors r, z (float64, length n)."""
-    _raise(lib().parac_apply(f.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), 1,
+    """z = M^+ r for contiguous float64 device tensors r, z of shape (n,)
+    or (n, nrhs)."""
+    nrhs = 1 if r.dim() == 1 else int(r.shape[1])
+    _raise(lib().parac_apply(f.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), nrhs,
                              precision, _stream(stream)))
     return z
 
 
-def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=1, rtol=1e-6, maxit=10000,
+def parac_block_shape_set(f: Factor, cols, precision=PREC_FP64, cpl=None, tail_rows=1024):
+    """Fix the block-apply shape for chunks of `cols` columns (cpl=None
+    forgets it, so the next block apply times the candidates again)."""
+    sh = None if cpl is None else C.byref(parac_block_shape(cpl, tail_rows))
+    _raise(lib().parac_block_shape_set(f.h, cols, precision, sh))
+
+
+def parac_block_shape_get(f: Factor, cols, precision=PREC_FP64):
+    sh = parac_block_shape()
+    _raise(lib().parac_block_shape_get(f.h, cols, precision, C.byref(sh)))
+    return dict(cpl=sh.cpl, tail_rows=sh.tail_rows)
+
+
+def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=None, rtol=1e-6, maxit=10000,
               precision=PREC_FP64, check_every=8, timing=False, stream=None):
-    """PCG (x0 = 0) on device tensors b, x (n x nrhs row-major).  Returns a
-    list of per-column stat dicts; raises on EINVAL/EINCONSISTENT."""
+    """PCG (x0 = 0) on contiguous device tensors b, x of shape (n,) or
+    (n, nrhs).  Returns a list of per-column stat dicts; raises on
+    EINVAL/EINCONSISTENT."""
+    if nrhs is None:
+        nrhs = 1 if b.dim() == 1 else int(b.shape[1])
     o = parac_pcg_opts(rtol, maxit, precision, check_every, 1 if timing else 0)
     st = (parac_pcg_stats * nrhs)()
     rc = lib().parac_pcg(C.byref(A.c), f.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
@@ -196,6 +220,37 @@ def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=1, rtol=1e-6, maxit=10000,
     return [dict(status=s.status, iterations=s.iterations, relres=s.relres,
                  true_relres=s.true_relres, ms_total=s.ms_total, ms_apply=s.ms_apply,
                  applies=s.applies) for s in st]
+
+
+def parac_serve(requests, hbm_budget=0, max_slots=0, precision=PREC_FP64, maxit=0,
+                check_every=0):
+    """Serve a stream of systems.  Each request is a dict with A (host CSR
+    with n, rowptr, col, val), b, and optionally perm, seed, rtol and
+    arrival_s.  Returns (results, xs): per-request result dicts and solution
+    arrays (host float64)."""
+    keep, xs = [], []
+    reqs = (parac_request * len(requests))()
+    for k, rq in enumerate(requests):
+        A = rq["A"]
+        n = int(A.n)
+        rowptr = np.ascontiguousarray(A.rowptr, np.int64)
+        col = np.ascontiguousarray(A.col, np.int32)
+        val = np.ascontiguousarray(A.val, np.float64)
+        b = np.ascontiguousarray(rq["b"], np.float64)
+        perm = rq.get("perm")
+        perm = None if perm is None else np.ascontiguousarray(perm, np.int32)
+        x = np.zeros(max(n, 1), np.float64)
+        keep.append((rowptr, col, val, b, perm))
+        xs.append(x)
+        p = lambda a: a.ctypes.data if a is not None else None  # noqa: E731
+        reqs[k] = parac_request(parac_csr(n, int(col.size), p(rowptr), p(col), p(val), 0),
+                                p(perm), p(b), p(x), int(rq.get("seed", 0)) & (2**64 - 1),
+                                float(rq.get("rtol", 1e-6)), float(rq.get("arrival_s", 0.0)))
+    out = (parac_result * len(requests))()
+    o = parac_serve_opts(int(hbm_budget), max_slots, precision, maxit, check_every)
+    _raise(lib().parac_serve(reqs, len(requests), C.byref(o), out))
+    res = [{k: getattr(r, k) for k, _ in parac_result._fields_} for r in out]
+    return res, [x[:int(rq["A"].n)] for x, rq in zip(xs, requests)]
 
 
 def status_str(st):

@@ -1,0 +1,155 @@
+"""GPU parity of the block (several right-hand sides) path.
+
+The block apply is bit-identical, column by column, to the oracle's apply of
+that column, for every launch shape (columns per lane, tail threshold) and
+for the shape the timing picks; block PCG runs an independent recurrence per
+column, so each column reaches the relative residual and agrees with the
+oracle's single-vector PCG of that column."""
+import numpy as np
+import pytest
+
+from paper_2505_02977_amd import inputs
+from tests.gpu_util import need_gpu, same_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def lap(n, i, j, w, excess=None):
+    return inputs.laplacian_from_edges(n, i, j, w, excess)
+
+
+def setup_case(kind, nrhs):
+    rng = np.random.default_rng({"grid": 11, "sddm": 12}[kind] * 100 + nrhs)
+    if kind == "grid":
+        W = inputs.grid2d_workload()
+        A, perm, seed, ex = W.A, W.perm, W.seed, None
+    else:
+        n = 3000
+        i, j = inputs.connected_random_edges(n, 4 * n, rng)
+        ex = np.zeros(n)
+        hot = rng.choice(n, 300, replace=False)
+        ex[hot] = rng.random(300)
+        A = lap(n, i, j, rng.uniform(0.05, 3.0, len(i)), ex)
+        perm = rng.permutation(n).astype(np.int32)
+        seed = 777
+    B = rng.standard_normal((A.n, nrhs))
+    B *= 10.0 ** rng.uniform(-3, 3, nrhs)  # columns of very different scale
+    if ex is None:
+        B -= B.mean(axis=0)
+    return A, perm, seed, np.ascontiguousarray(B), ex is not None
+
+
+SHAPES = [(c, t) for c in (1, 2, 4) for t in (0, 64, 1024, 1 << 40)]
+
+
+@pytest.mark.parametrize("kind", ["grid", "sddm"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_block_apply_every_shape_bit_identical(orc, kind, precision):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    nrhs = 32
+    A, perm, seed, B, _ = setup_case(kind, nrhs)
+    ref = orc.factor(A, perm=perm, seed=seed)
+    want = np.stack([orc.apply(ref, B[:, j].copy(), precision=precision)
+                     for j in range(nrhs)], axis=1)
+    f = parac.parac_factor(parac.DeviceCSR(A), perm=perm, seed=seed, keep_fp32=True)
+    r = torch.tensor(B, device="cuda")
+    z = torch.empty_like(r)
+    for cpl, tail in SHAPES:
+        parac.parac_block_shape_set(f, nrhs, precision, cpl=cpl, tail_rows=tail)
+        z.fill_(np.nan)
+        parac.parac_apply(f, r, z, precision=precision)
+        assert same_bits(z.cpu().numpy(), want), (kind, precision, cpl, tail)
+
+
+@pytest.mark.parametrize("nrhs", [2, 7, 70])
+def test_block_apply_tuned_shape(orc, nrhs):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    A, perm, seed, B, _ = setup_case("grid", nrhs)
+    ref = orc.factor(A, perm=perm, seed=seed)
+    f = parac.parac_factor(parac.DeviceCSR(A), perm=perm, seed=seed)
+    r = torch.tensor(B, device="cuda")
+    z = torch.empty_like(r)
+    parac.parac_apply(f, r, z)
+    got = z.cpu().numpy()
+    for j in range(nrhs):
+        assert same_bits(got[:, j], orc.apply(ref, B[:, j].copy())), j
+    # chunks of at most 64 columns, each with a shape fixed by the timing
+    for cols in sorted({min(64, nrhs - c0) for c0 in range(0, nrhs, 64)}):
+        sh = parac.parac_block_shape_get(f, cols)
+        assert sh["cpl"] in (1, 2, 4) and sh["tail_rows"] >= 0
+    # the single-vector path agrees as well
+    z1 = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    parac.parac_apply(f, r[:, 0].contiguous(), z1)
+    assert same_bits(z1.cpu().numpy(), got[:, 0])
+
+
+@pytest.mark.parametrize("kind", ["grid", "sddm"])
+def test_block_pcg_fp64_per_column(orc, kind):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    nrhs = 6
+    A, perm, seed, B, sddm = setup_case(kind, nrhs)
+    B[:, 3] = 0.0  # a zero column is done before the first iteration
+    ref = orc.factor(A, perm=perm, seed=seed)
+    dA = parac.DeviceCSR(A)
+    f = parac.parac_factor(dA, perm=perm, seed=seed)
+    bt = torch.tensor(B, device="cuda")
+    xt = torch.full_like(bt, np.nan)
+    sts = parac.parac_pcg(dA, f, bt, xt, rtol=1e-6)
+    X = xt.cpu().numpy()
+    L = A.to_scipy()
+    for j in range(nrhs):
+        st = sts[j]
+        assert st["status"] == 0, (j, st)
+        if j == 3:
+            assert st["iterations"] == 0 and not X[:, j].any()
+            continue
+        b = B[:, j]
+        res = np.linalg.norm(b - L @ X[:, j]) / np.linalg.norm(b)
+        assert res <= 1e-6 and abs(res - st["true_relres"]) <= 1e-9, (j, res, st)
+        xr, sr = orc.pcg(A, ref, b.copy(), rtol=1e-6)
+        if sr["iterations"] != st["iterations"]:
+            xr, sr = orc.pcg(A, ref, b.copy(), rtol=0.0, maxit=st["iterations"])
+        x = X[:, j]
+        if not sddm:
+            x, xr = x - x.mean(), xr - xr.mean()
+        assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr), j
+
+
+def test_block_pcg_mixed_and_chunks(orc):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    nrhs = 70  # two chunks: 64 + 6 columns
+    A, perm, seed, B, _ = setup_case("grid", nrhs)
+    dA = parac.DeviceCSR(A)
+    f = parac.parac_factor(dA, perm=perm, seed=seed, keep_fp32=True)
+    bt = torch.tensor(B, device="cuda")
+    xt = torch.empty_like(bt)
+    sts = parac.parac_pcg(dA, f, bt, xt, rtol=1e-6, precision=parac.PREC_MIXED)
+    X = xt.cpu().numpy()
+    L = A.to_scipy()
+    ref = orc.factor(A, perm=perm, seed=seed)
+    for j in (0, 5, 63, 64, 69):
+        b = B[:, j]
+        res = np.linalg.norm(b - L @ X[:, j]) / np.linalg.norm(b)
+        assert sts[j]["status"] == 0 and res <= 1e-6, (j, res)
+        _, sr = orc.pcg(A, ref, b.copy(), rtol=1e-6, precision=1)
+        assert abs(sr["iterations"] - sts[j]["iterations"]) <= 2, j
+
+
+def test_block_inconsistent_column_rejected(orc):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    A, perm, seed, B, _ = setup_case("grid", 5)
+    B[:, 2] += 1.0
+    dA = parac.DeviceCSR(A)
+    f = parac.parac_factor(dA, perm=perm, seed=seed)
+    bt = torch.tensor(B, device="cuda")
+    xt = torch.empty_like(bt)
+    with pytest.raises(parac.ParacError) as e:
+        parac.parac_pcg(dA, f, bt, xt)
+    assert e.value.status == parac.EINCONSISTENT
+    assert orc.check_consistent(A, 1, B[:, 2].copy()) == orc.EINCONSISTENT
+    assert orc.check_consistent(A, 1, B[:, 1].copy()) == 0

@@ -1,0 +1,115 @@
+"""GPU tests of the serving loop (continuous batching of many systems).
+
+Every number a system computes depends on its own data only, so its result
+is the same bit for bit alone, in a mix, and through parac_factor +
+parac_pcg; it reaches the relative residual (checked here in FP64) and agrees
+with the oracle's PCG solution.  Admission respects the slot count and the
+memory budget; a request that cannot fit the whole budget is refused."""
+import numpy as np
+import pytest
+
+from paper_2505_02977_amd import inputs
+from tests.gpu_util import need_gpu, same_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def stream(count=10, nmax=3e4, rate=400.0):
+    """SDDM systems of mixed families and sizes, plus one Laplacian grid;
+    Poisson arrivals fast enough that they overlap on the device."""
+    t = inputs.poisson_arrivals(count + 1, rate)
+    reqs, meta = [], []
+    for k in range(count):
+        W = inputs.sddm_system(k, nmin=1e3, nmax=nmax)
+        reqs.append(dict(A=W.A, b=W.b, perm=W.perm, seed=W.seed, rtol=1e-6,
+                         arrival_s=float(t[k])))
+        meta.append(W)
+    W = inputs.grid2d_workload()
+    reqs.append(dict(A=W.A, b=W.b, perm=W.perm, seed=W.seed, rtol=1e-6,
+                     arrival_s=float(t[count])))
+    meta.append(W)
+    return reqs, meta
+
+
+def rel_residual(A, x, b):
+    return np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b)
+
+
+def test_serve_mix_alone_and_single_agree(orc):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    reqs, meta = stream()
+    res, xs = parac.parac_serve(reqs, max_slots=4)
+    for k, (r, x) in enumerate(zip(res, xs)):
+        assert r["status"] == 0, (k, r)
+        assert r["t_arrive"] <= r["t_admit"] <= r["t_done"], (k, r)
+        assert r["bytes_resident"] > 0
+        res_h = rel_residual(reqs[k]["A"], x, reqs[k]["b"])
+        assert res_h <= 1e-6 and abs(res_h - r["true_relres"]) <= 1e-9, (k, res_h, r)
+    # never more than max_slots systems admitted at once
+    ev = sorted([(r["t_admit"], 1) for r in res] + [(r["t_done"], -1) for r in res],
+                key=lambda e: (e[0], e[1]))
+    live = peak = 0
+    for _, d in ev:
+        live += d
+        peak = max(peak, live)
+    assert peak <= 4
+    # the same request alone, and through factor + pcg: the same bits
+    for k in (0, 3, len(reqs) - 1):
+        r1, x1 = parac.parac_serve([dict(reqs[k], arrival_s=0.0)])
+        assert r1[0]["status"] == 0 and r1[0]["iterations"] == res[k]["iterations"]
+        assert same_bits(x1[0], xs[k]), k
+        dA = parac.DeviceCSR(reqs[k]["A"])
+        f = parac.parac_factor(dA, perm=reqs[k]["perm"], seed=reqs[k]["seed"])
+        bt = torch.tensor(reqs[k]["b"], device="cuda")
+        xt = torch.empty_like(bt)
+        st = parac.parac_pcg(dA, f, bt, xt, rtol=1e-6)[0]
+        assert st["iterations"] == res[k]["iterations"]
+        assert same_bits(xt.cpu().numpy(), xs[k]), k
+    # the oracle's solution of the smallest system
+    k = int(np.argmin([W.A.n for W in meta[:-1]]))
+    W = meta[k]
+    ref = orc.factor(W.A, perm=W.perm, seed=W.seed)
+    xr, sr = orc.pcg(W.A, ref, W.b, rtol=1e-6)
+    if sr["iterations"] != res[k]["iterations"]:
+        xr, sr = orc.pcg(W.A, ref, W.b, rtol=0.0, maxit=res[k]["iterations"])
+    assert np.linalg.norm(xs[k] - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+def test_serve_mixed_precision_matches_single(orc):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    reqs, _ = stream(count=5, nmax=1e4)
+    res, xs = parac.parac_serve(reqs, precision=parac.PREC_MIXED, max_slots=3)
+    for k, (r, x) in enumerate(zip(res, xs)):
+        assert r["status"] == 0, (k, r)
+        assert rel_residual(reqs[k]["A"], x, reqs[k]["b"]) <= 1e-6
+    k = 2
+    dA = parac.DeviceCSR(reqs[k]["A"])
+    f = parac.parac_factor(dA, perm=reqs[k]["perm"], seed=reqs[k]["seed"], keep_fp32=True)
+    bt = torch.tensor(reqs[k]["b"], device="cuda")
+    xt = torch.empty_like(bt)
+    st = parac.parac_pcg(dA, f, bt, xt, rtol=1e-6, precision=parac.PREC_MIXED)[0]
+    assert st["iterations"] == res[k]["iterations"]
+    assert same_bits(xt.cpu().numpy(), xs[k])
+
+
+def test_serve_budget_and_request_errors(orc):
+    need_gpu()
+    from paper_2505_02977_amd import parac
+    reqs, _ = stream(count=4, nmax=5e3)
+    big = inputs.grid2d_workload(side=300)  # 90,000 vertices
+    reqs.append(dict(A=big.A, b=big.b, perm=big.perm, seed=big.seed, arrival_s=0.0))
+    # a Laplacian request whose b has a nonzero sum
+    W = inputs.grid2d_workload(side=20)
+    reqs.append(dict(A=W.A, b=W.b + 1.0, perm=W.perm, seed=W.seed, arrival_s=0.0))
+    budget = 60 << 20  # fits every small system, not the big one
+    res, xs = parac.parac_serve(reqs, hbm_budget=budget, max_slots=2)
+    assert res[4]["status"] == parac.ENOMEM
+    assert res[5]["status"] == parac.EINCONSISTENT
+    for k in range(4):
+        assert res[k]["status"] == 0, (k, res[k])
+        assert rel_residual(reqs[k]["A"], xs[k], reqs[k]["b"]) <= 1e-6
+    with pytest.raises(parac.ParacError) as e:
+        parac.parac_serve(reqs[:1], max_slots=1000)
+    assert e.value.status == parac.EINVAL
