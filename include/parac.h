@@ -85,7 +85,7 @@ typedef struct {
   int32_t keep_fp32;      /* also build the FP32 copy used by MIXED apply   */
   double timeout_s;       /* elimination watchdog (0 = 30 s)                */
   double tail_fraction;   /* share of pivots left to the single-workgroup
-                             tail kernel (0 = 0.04; negative = none; 1 = all) */
+                             tail kernel (0 or negative = none; 1 = all)    */
 } parac_factor_opts;
 
 typedef struct {

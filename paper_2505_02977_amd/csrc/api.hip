@@ -346,7 +346,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     {
       // the wide kernel leaves the last `tail_fraction` of the pivots (the
       // thin end of the dependency DAG) to the single-workgroup kernel
-      const double tf = opt.tail_fraction == 0.0 ? 0.04 : opt.tail_fraction;
+      const double tf = opt.tail_fraction == 0.0 ? -1.0 : opt.tail_fraction;
       if (tf >= 1.0) {
         ea.stop_at = 0;
       } else if (tf < 0.0) {
@@ -1277,12 +1277,16 @@ static int serve_impl(const parac_request *reqs, int64_t nreq, const parac_serve
         "read");
     chk(hipStreamSynchronize(cs), "sync");
     // 4. finished systems: true residual, x back to the caller, release
+    // (the batch tables point into every active slot: slots leave `active`
+    // only together with a rebuild of the batch)
+    bool any_done = false;
+    for (auto &sl : active) any_done |= hflags[4 * sl->id + 1] != 0;
+    if (!any_done) continue;
     std::vector<std::unique_ptr<ServeSlot>> fin, keep;
     for (auto &sl : active) {
       if (hflags[4 * sl->id + 1]) fin.push_back(std::move(sl));
       else keep.push_back(std::move(sl));
     }
-    if (fin.empty()) continue;
     active = std::move(keep);
     dirty = true;
     {

@@ -80,6 +80,17 @@ __device__ __forceinline__ void fence_release() {
 __device__ __forceinline__ void fence_acq_rel() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
 }
+// the compiler keeps memory accesses on their side of this point
+__device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+// wait until every earlier memory access of this wave has completed; with
+// agent-scope (cache-coherent) stores this makes them visible to the agent
+// before any later access is issued.  s_waitcnt vmcnt(0) expcnt(7)
+// lgkmcnt(15) in the GFX9 encoding.
+__device__ __forceinline__ void store_wait() {
+  compiler_fence();
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  compiler_fence();
+}
 // orders this wave's own global/LDS accesses (same CU)
 __device__ __forceinline__ void fence_wave_local() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");

@@ -44,6 +44,19 @@ __device__ __forceinline__ void page_of(int r, int &j, int &off) {
   off = r - kInline * ((1 << j) - 1);
 }
 
+// Fill records and page-table entries cross waves (and XCDs).  They are
+// written and read only by agent-scope relaxed accesses, which bypass the
+// caches that are not coherent across XCDs; a producer waits for its stores
+// to complete before it decrements any counter (store_wait), so a consumer
+// that has seen its own counter at zero reads complete records without
+// invalidating any cache.
+__device__ __forceinline__ void store_rec(Rec *dst, int32_t other, int32_t src, double w) {
+  uint64_t *d = (uint64_t *)dst;
+  const uint64_t head = (uint64_t)(uint32_t)other | ((uint64_t)(uint32_t)src << 32);
+  __hip_atomic_store(d, head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(d + 1, dbits(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ Rec load_rec(const ElimArgs &a, int32_t k, int r) {
   int j, off;
   page_of(r, j, off);
@@ -51,10 +64,24 @@ __device__ __forceinline__ Rec load_rec(const ElimArgs &a, int32_t k, int r) {
   if (j == 0) {
     p = a.inl + (int64_t)k * kInline + off;
   } else {
-    int32_t base = a.ptab[(int64_t)k * (kPages - 1) + j - 1];
+    int32_t base = ld_acq_relaxed(&a.ptab[(int64_t)k * (kPages - 1) + j - 1]);
+    if (base < 0) {  // never published: an invalid record (the caller's range check fails)
+      Rec bad;
+      bad.other = -1;
+      bad.src = -1;
+      bad.w = 0.0;
+      return bad;
+    }
     p = a.pool + (int64_t)base + off;
   }
-  return *p;
+  const uint64_t *q = (const uint64_t *)p;
+  const uint64_t head = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t wbits = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  Rec rc;
+  rc.other = (int32_t)(uint32_t)head;
+  rc.src = (int32_t)(uint32_t)(head >> 32);
+  rc.w = bitsd(wbits);
+  return rc;
 }
 
 __device__ __forceinline__ bool timed_out(const ElimArgs &a, uint64_t deadline) {
@@ -129,11 +156,7 @@ __device__ bool insert_records(const ElimArgs &a, Worker &wk, bool ins, int32_t 
   }
   if (ins) {
     Rec *dst = (j == 0) ? a.inl + (int64_t)tgt * kInline + off : a.pool + pbase + off;
-    Rec rec;
-    rec.other = oth;
-    rec.src = k;
-    rec.w = c;
-    *dst = rec;
+    store_rec(dst, oth, k, c);
     fetch_add(&a.dp[oth], 1);
   }
   return true;
@@ -158,13 +181,17 @@ __device__ __forceinline__ bool alloc_column(const ElimArgs &a, Worker &wk, int 
   return true;
 }
 
-// Synchronisation policies.  The wide kernel runs on every XCD: a pivot
-// publishes its fill and factor column with an agent-scope release fence and
-// enqueues into the sharded queue.  The tail kernel is one workgroup on one
-// CU: workgroup-scope fences suffice, and it has its own queue.
+// Synchronisation policies.  The wide kernel runs on every XCD: everything
+// another pivot reads from this one (fill records, page-table entries,
+// levels, counters, queue slots) goes through agent-scope atomics, so a pivot
+// publishes by waiting for its stores to complete before its counter
+// decrements (no cache write-back), and a consumer needs no cache
+// invalidation after seeing its counter at zero.  The tail kernel is one
+// workgroup on one CU: workgroup-scope fences suffice, and it has its own
+// queue.
 struct WideSync {
-  static __device__ __forceinline__ void release() { fence_release(); }
-  static __device__ __forceinline__ void acquire() { fence_acquire(); }
+  static __device__ __forceinline__ void release() { store_wait(); }
+  static __device__ __forceinline__ void acquire() { compiler_fence(); }
   static __device__ __forceinline__ bool enqueue(const ElimArgs &a, int32_t u) {
     const int x = u & (kSubQueues - 1);
     const int pos = fetch_add(&a.qtail[x * kTailStride], 1);
@@ -686,10 +713,9 @@ __device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64
   return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h);
 }
 
-// After a slot has delivered label k: read k's counter by a read-modify-write
-// (it returns the last value of the counter's modification order, zero), so
-// the acquire fence that follows synchronises with the release fence of every
-// pivot that touched k.
+// After a slot has delivered label k: read k's counter (agent scope).  Zero
+// means every pivot that could write to k's inbox has completed its stores
+// and decremented the counter, so the records read afterwards are complete.
 template <class Sync>
 __device__ __forceinline__ bool sync_with_producers(const ElimArgs &a, int32_t k) {
   int v = 0;
