@@ -141,13 +141,15 @@ parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
 parac_status parac_apply(parac_factor_t f, const double *r, double *z,
                          int64_t nrhs, int32_t precision, void *stream);
 
-/* Launch shape of the block (nrhs > 1) apply for chunks of `cols` columns
- * (1..64) in one precision.  Results do not depend on it, only speed.
- *   cpl        columns per lane: 1, 2 or 4
+/* Launch shape of the apply for chunks of `cols` columns (1..64) in one
+ * precision.  Results do not depend on it, only speed.
+ *   cpl        columns per lane: 1, 2 or 4 (ignored for cols = 1)
  *   tail_rows  levels at most this wide, and all levels after them, are
- *              solved by a single workgroup (the rest one launch per level)
- * Unless set, the first block apply of a factor times the candidate shapes
- * on its own input and keeps the fastest. */
+ *              solved by a single workgroup (the rest one launch per level);
+ *              for cols = 1 at most 1024
+ * Unless set, the first block apply (cols > 1) of a factor times the
+ * candidate shapes on its own input and keeps the fastest; the
+ * single-vector apply (cols = 1) uses the factor's default threshold. */
 typedef struct {
   int32_t cpl;
   int64_t tail_rows;

@@ -277,15 +277,21 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   double ms_elim = 0.0;
   for (;;) {
     const int64_t base_entries = std::max<int64_t>(nnz, 64);
-    const int64_t pool_base = (int64_t)(pf * (double)base_entries);
-    const int64_t f_base = (int64_t)(0.5 * pf * (double)base_entries) + ntot;
+    // pages double in size, so up to half of a target's page chain can be
+    // unused: twice the expected record count
+    const int64_t pool_base = (int64_t)(2.0 * pf * (double)base_entries);
+    // factor entries: about 1.6 nnz on grids, about 3 nnz on power-law graphs
+    const int64_t f_base = (int64_t)(pf * (double)base_entries) + ntot;
     // per-worker reservations: small enough that their slack stays a fraction
     // of the pools
     const int pg_chunk = (int)std::min<int64_t>(kPageChunk, std::max<int64_t>(64, pool_base / (8 * workers)));
     const int f_chunk = (int)std::min<int64_t>(kFChunk, std::max<int64_t>(64, f_base / (8 * workers)));
     pool_cap = std::min<int64_t>(pool_base + (int64_t)workers * pg_chunk, (int64_t)INT32_MAX - 1);
     f_cap = f_base + (int64_t)workers * f_chunk;
-    arena_cap = (int64_t)(pf * (double)base_entries) * 16 + (int64_t)workers * 8192;
+    // scratch of the large-neighbourhood path: every worker keeps its own
+    // region (grown geometrically), so besides a share of the fill volume
+    // each worker gets room for a few thousand entries (68 bytes each)
+    arena_cap = (int64_t)(pf * (double)base_entries) * 16 + (int64_t)workers * 68 * 4096;
     pool = tmp.alloc<Rec>(pool_cap, "fill pool");
     frow = tmp.alloc<int32_t>(f_cap, "factor rows");
     fval = tmp.alloc<double>(f_cap, "factor values");
@@ -416,7 +422,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
         "transpose");
     chk(launch_sort_rows(ntot, rowptr_f, colind_f, val_f, long_rows, flags + 2, s),
         "sort_rows");
-    chk(launch_sort_long_rows(rowptr_f, colind_f, val_f, long_rows, flags + 2, frow, fval,
+    chk(launch_sort_long_rows(rowptr_f, colind_f, val_f, long_rows, flags + 2, frow, fval, ntot,
                               s),
         "sort_long_rows");
   }
@@ -445,9 +451,9 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
         "read");
     chk(hipStreamSynchronize(s), "sync");
     // the thin tail: the smallest level from which every level has at most
-    // kTailWidth rows
+    // kTailDefault rows
     int64_t L0 = depth;
-    while (L0 > 0 && F->hlptr[L0] - F->hlptr[L0 - 1] <= kTailWidth) --L0;
+    while (L0 > 0 && F->hlptr[L0] - F->hlptr[L0 - 1] <= kTailDefault) --L0;
     F->L0 = L0;
     // level-ordered copies of the rows (forward) and columns (backward) of F
     int32_t *flen = tmp.alloc<int32_t>(n, "flen");
@@ -463,10 +469,21 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     F->lf_val = tmp.alloc<double>(nf, "lf_val");
     F->lb_idx = tmp.alloc<int32_t>(nbk, "lb_idx");
     F->lb_val = tmp.alloc<double>(nbk, "lb_val");
-    chk(launch_level_copy(n, F->order, rowptr_f, colind_f, val_f, F->colptr, F->rowind,
+    // position space of the solves: posof / src maps and D^+ by position
+    int32_t *posof = tmp.alloc<int32_t>(n, "posof");
+    F->src = tmp.alloc<int32_t>(n, "src");
+    F->Dinv = tmp.alloc<double>(n, "Dinv");
+    if (opt.keep_fp32) F->Dinv32 = tmp.alloc<float>(n, "Dinv32");
+    chk(launch_position_maps(n, F->order, F->iperm, F->D, posof, F->src, F->Dinv, F->Dinv32, s),
+        "position maps");
+    chk(launch_level_copy(n, F->order, posof, rowptr_f, colind_f, val_f, F->colptr, F->rowind,
                           F->val, F->lf_ptr, F->lb_ptr, F->lf_idx, F->lf_val, F->lb_idx,
                           F->lb_val, s),
         "level_copy");
+    F->lqf = tmp.alloc<int64_t>(depth + 1, "lqf");
+    F->lqb = tmp.alloc<int64_t>(depth + 1, "lqb");
+    chk(launch_level_offsets(depth, F->lptr, F->lf_ptr, F->lb_ptr, F->lqf, F->lqb, s),
+        "level offsets");
     if (opt.keep_fp32) {
       F->lf_val32 = tmp.alloc<float>(nf, "lf_val32");
       F->lb_val32 = tmp.alloc<float>(nbk, "lb_val32");
@@ -474,11 +491,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
       chk(launch_cast32(nbk, F->lb_val, F->lb_val32, s), "cast");
     }
   }
-  F->Dinv = tmp.alloc<double>(ntot, "Dinv");
-  float *Dinv32 = nullptr;
-  if (opt.keep_fp32) Dinv32 = tmp.alloc<float>(ntot, "Dinv32");
-  F->Dinv32 = Dinv32;
-  if (ntot > 0) chk(launch_dinv(ntot, F->D, F->Dinv, Dinv32, s), "dinv");
+  if (!F->Dinv) F->Dinv = tmp.alloc<double>(1, "Dinv");  // n = 0
+  if (opt.keep_fp32 && !F->Dinv32) F->Dinv32 = tmp.alloc<float>(1, "Dinv32");
   // component roots (last label of each component) by pointer jumping
   F->root = tmp.alloc<int32_t>(ntot, "root");
   if (ntot > 0) {
@@ -522,6 +536,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   for (void *p : {(void *)F->perm, (void *)F->iperm, (void *)F->colptr, (void *)F->rowind,
                   (void *)F->val, (void *)F->D, (void *)F->Dinv, (void *)F->Dinv32,
                   (void *)F->lev, (void *)F->order, (void *)F->root, (void *)F->lptr,
+                  (void *)F->src, (void *)F->lqf, (void *)F->lqb,
                   (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
                   (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
     if (p) F->bytes += tmp.keep(p, F->owned);
@@ -532,13 +547,32 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
 // ---------------------------------------------------------------------------
 // apply
 // ---------------------------------------------------------------------------
-static SolveArgs solve_args(parac_factor_t f, const int *skip) {
+static int prec_slot(int prec) { return prec == PARAC_PREC_MIXED ? 1 : 0; }
+
+// first level of the single-workgroup tail for a width threshold
+static int64_t tail_start(parac_factor_t f, int64_t rows) {
+  int64_t L0 = f->depth;
+  while (L0 > 0 && f->hlptr[L0] - f->hlptr[L0 - 1] <= rows) --L0;
+  return L0;
+}
+
+// the single-vector apply's tail threshold (at most the tail kernel's one
+// row per thread): fixed through the shape calls with one column, else the
+// factor's default
+static int64_t single_tail_start(parac_factor_t f, int prec) {
+  auto it = f->shapes.find(std::make_pair(1, prec_slot(prec)));
+  if (it == f->shapes.end()) return f->L0;
+  return tail_start(f, std::min<int64_t>(it->second.tail_rows, kTailWidth));
+}
+
+static SolveArgs solve_args(parac_factor_t f, const int *skip, int prec) {
   SolveArgs a{};
   a.n = f->n;
-  a.order = f->order;
   a.lptr = f->lptr;
+  a.lqf = f->lqf;
+  a.lqb = f->lqb;
   a.depth = f->depth;
-  a.L0 = f->L0;
+  a.L0 = single_tail_start(f, prec);
   a.lf_ptr = f->lf_ptr;
   a.lf_idx = f->lf_idx;
   a.lf_val = f->lf_val;
@@ -549,7 +583,7 @@ static SolveArgs solve_args(parac_factor_t f, const int *skip) {
   a.lb_val32 = f->lb_val32;
   a.Dinv = f->Dinv;
   a.Dinv32 = f->Dinv32;
-  a.iperm = f->iperm;
+  a.src = f->src;
   a.skip = skip;
   return a;
 }
@@ -572,7 +606,7 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, co
                       hipStream_t s) {
   if (f->n == 0) return;
   ensure_work(f, prec);
-  SolveArgs a = solve_args(f, skip);
+  SolveArgs a = solve_args(f, skip, prec);
   void *y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
   void *x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
   chk(launch_apply(a, f->hlptr.data(), r, y, x, z, prec, s), "apply");
@@ -581,8 +615,6 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, co
 // ---------------------------------------------------------------------------
 // block apply (several right-hand sides, chunks of at most kBlockCols)
 // ---------------------------------------------------------------------------
-static int prec_slot(int prec) { return prec == PARAC_PREC_MIXED ? 1 : 0; }
-
 static void ensure_bwork(parac_factor_t f, int prec, int nc) {
   const int k = prec_slot(prec);
   if (f->bcols[k] >= nc) return;
@@ -604,19 +636,12 @@ static void ensure_bwork(parac_factor_t f, int prec, int nc) {
   f->bytes += 2 * (int64_t)(m * el);
 }
 
-// first level of the single-workgroup tail for a width threshold
-static int64_t tail_start(parac_factor_t f, int64_t rows) {
-  int64_t L0 = f->depth;
-  while (L0 > 0 && f->hlptr[L0] - f->hlptr[L0 - 1] <= rows) --L0;
-  return L0;
-}
-
 static void apply_block(parac_factor_t f, const parac_block_shape &shp, int nc, const double *r,
                         int64_t ldr, double *z, int64_t ldz, int prec, const int *skip,
                         hipStream_t s) {
   if (f->n == 0) return;
   ensure_bwork(f, prec, nc);
-  SolveArgs a = solve_args(f, skip);
+  SolveArgs a = solve_args(f, skip, prec);
   BlockShape sh{shp.cpl, tail_start(f, shp.tail_rows)};
   const int k = prec_slot(prec);
   chk(launch_block_apply(a, f->hlptr.data(), sh, nc, r, ldr, f->bwy[k], f->bwx[k], z, ldz, prec,
@@ -631,7 +656,7 @@ static parac_block_shape block_shape(parac_factor_t f, int nc, int prec, const d
   const auto key = std::make_pair(nc, prec_slot(prec));
   auto it = f->shapes.find(key);
   if (it != f->shapes.end()) return it->second;
-  parac_block_shape best{1, kTailWidth};
+  parac_block_shape best{1, kTailDefault};
   if (f->n == 0) return best;
   Events ev;
   ev.create();
@@ -646,11 +671,11 @@ static parac_block_shape block_shape(parac_factor_t f, int nc, int prec, const d
   double tbest = time_one(best);
   for (int cpl : {2, 4}) {  // columns per lane at the default tail
     if (cpl > nc) continue;
-    parac_block_shape c{cpl, kTailWidth};
+    parac_block_shape c{cpl, kTailDefault};
     const double t = time_one(c);
     if (t < tbest) tbest = t, best = c;
   }
-  for (int64_t rows : {(int64_t)256, (int64_t)4096}) {  // then the tail threshold
+  for (int64_t rows : {(int64_t)64, (int64_t)1024}) {  // then the tail threshold
     parac_block_shape c{best.cpl, rows};
     const double t = time_one(c);
     if (t < tbest) tbest = t, best = c;
@@ -714,13 +739,13 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     blk += ps[k].nblk;
     parac_factor_t f = v[k].f;
     ensure_work(f, prec);
-    as[k].a = solve_args(f, ps[k].ist + 1);
+    as[k].a = solve_args(f, ps[k].ist + 1, prec);
     as[k].r = ps[k].r;
     as[k].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
     as[k].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
     as[k].z = ps[k].z;
-    maxL0 = std::max(maxL0, f->L0);
-    if (f->L0 < f->depth) tsl.push_back(k);
+    maxL0 = std::max(maxL0, as[k].a.L0);
+    if (as[k].a.L0 < f->depth) tsl.push_back(k);
   }
   std::vector<int32_t> pre((size_t)std::max<int64_t>(maxL0, 1) * (ns + 1), 0);
   bt.htotal.assign((size_t)maxL0, 0);
@@ -729,7 +754,7 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     for (int k = 0; k < ns; ++k) {
       pre[L * (ns + 1) + k] = acc;
       parac_factor_t f = v[k].f;
-      if (L < f->L0) acc += (int32_t)((f->hlptr[L + 1] - f->hlptr[L] + 255) / 256);
+      if (L < as[k].a.L0) acc += (int32_t)((f->hlptr[L + 1] - f->hlptr[L] + 255) / 256);
     }
     pre[L * (ns + 1) + ns] = acc;
     bt.htotal[L] = acc;

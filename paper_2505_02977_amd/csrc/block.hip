@@ -17,13 +17,12 @@
 
 namespace parac {
 
-// forward row: y(i, :) = r(perm i, :) - sum_e F(i, c_e) y(c_e, :)
+// forward row at position pos: y(pos, :) = r(src pos, :) - sum_e F y(c_e, :)
 template <typename T, int CPL>
 __device__ __forceinline__ void brow_fwd(const SolveArgs &a, int64_t pos, int j0, int G, int nc,
                                          const double *__restrict__ r, int64_t ldr, T *y) {
-  const int32_t i = a.order[pos];
   const T *fv = FactorVals<T>::fwd(a);
-  const double *ri = r + (int64_t)a.iperm[i] * ldr;
+  const double *ri = r + (int64_t)a.src[pos] * ldr;
   T acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
@@ -40,7 +39,7 @@ __device__ __forceinline__ void brow_fwd(const SolveArgs &a, int64_t pos, int j0
       if (j < nc) acc[c] = acc[c] - f * yc[j];
     }
   }
-  T *yi = y + (int64_t)i * nc;
+  T *yi = y + pos * nc;
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     const int j = j0 + c * G;
@@ -48,15 +47,14 @@ __device__ __forceinline__ void brow_fwd(const SolveArgs &a, int64_t pos, int j0
   }
 }
 
-// backward row: x(i, :) = D^+_i y(i, :) - sum_e F(c_e, i) x(c_e, :);
-// z(perm i, :) = x(i, :)
+// backward row at position pos: x(pos, :) = D^+ y(pos, :) - sum_e F x(c_e, :);
+// z(src pos, :) = x(pos, :)
 template <typename T, int CPL>
 __device__ __forceinline__ void brow_bwd(const SolveArgs &a, int64_t pos, int j0, int G, int nc,
                                          const T *__restrict__ y, T *x, double *z, int64_t ldz) {
-  const int32_t i = a.order[pos];
   const T *fv = FactorVals<T>::bwd(a);
-  const T di = FactorVals<T>::dinv(a)[i];
-  const T *yi = y + (int64_t)i * nc;
+  const T di = FactorVals<T>::dinv(a)[pos];
+  const T *yi = y + pos * nc;
   T acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
@@ -73,8 +71,8 @@ __device__ __forceinline__ void brow_bwd(const SolveArgs &a, int64_t pos, int j0
       if (j < nc) acc[c] = acc[c] - f * xc[j];
     }
   }
-  T *xi = x + (int64_t)i * nc;
-  double *zi = z + (int64_t)a.iperm[i] * ldz;
+  T *xi = x + pos * nc;
+  double *zi = z + (int64_t)a.src[pos] * ldz;
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     const int j = j0 + c * G;

@@ -178,4 +178,75 @@ __device__ __forceinline__ int bitonic_partner(int l, int p, int j, bool first) 
   return first ? (l ^ (p - 1)) : (l ^ j);
 }
 
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (key, payload) pairs by one wave, ping-ponging
+// between two buffers: 8-bit digits at the given shifts, a 256-bucket
+// histogram in the wave's LDS slice h, in-wave ranks by matching digits with
+// ballots.  Returns true when the sorted data ends in the first buffer.
+// ---------------------------------------------------------------------------
+template <typename K, typename V>
+__device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *shifts, int npass,
+                                int *h) {
+  const int l = lane();
+  bool in_a = true;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int sh = shifts[pass];
+    K *ks = in_a ? ka : kb;
+    V *vs = in_a ? va : vb;
+    K *kd = in_a ? kb : ka;
+    V *vd = in_a ? vb : va;
+    for (int t = l; t < 256; t += kWave) h[t] = 0;
+    fence_wave_local();
+#pragma unroll 4
+    for (int base = 0; base < n; base += kWave) {
+      const int i = base + l;
+      if (i < n) atomicAdd(&h[(int)(((uint64_t)ks[i] >> sh) & 255)], 1);
+    }
+    fence_wave_local();
+    // exclusive scan of the 256 buckets, four per lane
+    const int c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
+    const int tot = c0 + c1 + c2 + c3;
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      int y = __shfl_up(incl, o, kWave);
+      if (l >= o) incl += y;
+    }
+    const int ex = incl - tot;
+    fence_wave_local();
+    h[4 * l] = ex;
+    h[4 * l + 1] = ex + c0;
+    h[4 * l + 2] = ex + c0 + c1;
+    h[4 * l + 3] = ex + c0 + c1 + c2;
+    fence_wave_local();
+    // stable scatter, 64 elements at a time in index order
+    for (int base = 0; base < n; base += kWave) {
+      const int i = base + l;
+      const bool valid = i < n;
+      const K k = valid ? ks[i] : (K)0;
+      const V v = valid ? vs[i] : (V)0;
+      const int d = (int)(((uint64_t)k >> sh) & 255);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bm = __ballot(valid && ((d >> b) & 1));
+        peers &= ((d >> b) & 1) ? bm : ~bm;
+      }
+      const int off = valid ? h[d] : 0;
+      fence_wave_local();
+      if (valid) {
+        const int rank = __popcll(peers & lanemask_lt());
+        kd[off + rank] = k;
+        vd[off + rank] = v;
+        if (rank == 0) h[d] = off + __popcll(peers);
+      }
+      fence_wave_local();
+    }
+    fence_wave_local();
+    in_a = !in_a;
+  }
+  return in_a;
+}
+
 }  // namespace parac

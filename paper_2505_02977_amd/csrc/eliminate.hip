@@ -377,74 +377,7 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   return decrement<Sync>(a, l < d, mu, mm);
 }
 
-// ---------------------------------------------------------------------------
-// Stable LSD radix sort of (key, payload) pairs by one wave, ping-ponging
-// between two scratch buffers: 8-bit digits, a 256-bucket histogram in the
-// wave's LDS slice, in-wave ranks by matching digits with ballots.  Returns
-// true when the sorted data ends in the first buffer.
-// ---------------------------------------------------------------------------
 constexpr int kRankMax = 2048;  // above this the radix sort replaces ranking
-
-__device__ __forceinline__ void lds_sync() { fence_wave_local(); }
-
-__device__ bool wave_radix_sort(uint64_t *ka, uint64_t *va, uint64_t *kb, uint64_t *vb, int n,
-                                const int *shifts, int npass, int *h) {
-  const int l = lane();
-  bool in_a = true;
-  for (int pass = 0; pass < npass; ++pass) {
-    const int sh = shifts[pass];
-    uint64_t *ks = in_a ? ka : kb, *vs = in_a ? va : vb;
-    uint64_t *kd = in_a ? kb : ka, *vd = in_a ? vb : va;
-    for (int t = l; t < 256; t += kWave) h[t] = 0;
-    lds_sync();
-    for (int base = 0; base < n; base += kWave) {
-      const int i = base + l;
-      if (i < n) atomicAdd(&h[(int)((ks[i] >> sh) & 255)], 1);
-    }
-    lds_sync();
-    // exclusive scan of the 256 buckets, four per lane
-    int c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
-    int tot = c0 + c1 + c2 + c3, incl = tot;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      int y = __shfl_up(incl, o, kWave);
-      if (l >= o) incl += y;
-    }
-    const int ex = incl - tot;
-    lds_sync();
-    h[4 * l] = ex;
-    h[4 * l + 1] = ex + c0;
-    h[4 * l + 2] = ex + c0 + c1;
-    h[4 * l + 3] = ex + c0 + c1 + c2;
-    lds_sync();
-    // stable scatter, 64 elements at a time in index order
-    for (int base = 0; base < n; base += kWave) {
-      const int i = base + l;
-      const bool valid = i < n;
-      const uint64_t k = valid ? ks[i] : 0;
-      const uint64_t v = valid ? vs[i] : 0;
-      const int d = (int)((k >> sh) & 255);
-      uint64_t peers = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const uint64_t bm = __ballot(valid && ((d >> b) & 1));
-        peers &= ((d >> b) & 1) ? bm : ~bm;
-      }
-      const int off = valid ? h[d] : 0;
-      lds_sync();
-      if (valid) {
-        const int rank = __popcll(peers & lanemask_lt());
-        kd[off + rank] = k;
-        vd[off + rank] = v;
-        if (rank == 0) h[d] = off + __popcll(peers);
-      }
-      lds_sync();
-    }
-    fence_wave_local();
-    in_a = !in_a;
-  }
-  return in_a;
-}
 
 // ---------------------------------------------------------------------------
 // larger neighbourhoods: the same steps over wave-private scratch in HBM;
@@ -523,7 +456,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     int shifts[8], np = 0;
     for (int b = 0; b < nb; b += 8) shifts[np++] = b;
     for (int b = 0; b < nb; b += 8) shifts[np++] = 32 + b;
-    const bool in_a = wave_radix_sort(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g, shifts, np, h);
+    const bool in_a = wave_radix_sort<uint64_t, uint64_t>(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g, shifts, np, h);
     if (in_a) {
       keyS = keyA;
       wS = wA;
@@ -603,7 +536,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     fence_wave_local();
     int shifts[8];
     for (int p2 = 0; p2 < 8; ++p2) shifts[p2] = 8 * p2;
-    const bool in_x = wave_radix_sort(kx, vx, ky, vy, d, shifts, 8, h);
+    const bool in_x = wave_radix_sort<uint64_t, uint64_t>(kx, vx, ky, vy, d, shifts, 8, h);
     const uint64_t *kr = in_x ? kx : ky, *vr = in_x ? vx : vy;
     for (int i = l; i < d; i += kWave) {
       sw[i] = bitsd(kr[i]);

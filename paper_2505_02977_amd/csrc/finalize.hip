@@ -90,38 +90,33 @@ __global__ void k_sort_rows(int64_t ntot, const int64_t *__restrict__ rowptr_f, 
   }
 }
 
-// long rows: one wave per row, rank sort (columns are distinct) through the
-// scratch arrays tmp_c / tmp_v at the row's own offsets
-__global__ void k_sort_long_rows(const int64_t *__restrict__ rowptr_f, int32_t *colind_f,
-                                 double *val_f, const int32_t *__restrict__ long_rows,
-                                 const int32_t *__restrict__ n_long, int32_t *tmp_c,
-                                 double *tmp_v) {
+// long rows: one wave per row, stable radix sort on the column label bits,
+// ping-ponging with the scratch arrays tmp_c / tmp_v at the row's own offsets
+__global__ __launch_bounds__(256) void k_sort_long_rows(const int64_t *__restrict__ rowptr_f,
+                                                        int32_t *colind_f, double *val_f,
+                                                        const int32_t *__restrict__ long_rows,
+                                                        const int32_t *__restrict__ n_long,
+                                                        int32_t *tmp_c, double *tmp_v,
+                                                        int nbits) {
+  __shared__ int hist[4][256];
+  int *h = hist[threadIdx.x >> 6];
   const int l = lane();
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nw = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
   const int cnt = *n_long;
+  int shifts[4], np = 0;
+  for (int b = 0; b < nbits && np < 4; b += 8) shifts[np++] = b;
   for (int r = wid; r < cnt; r += nw) {
     const int32_t row = long_rows[r];
     const int64_t b = rowptr_f[row];
     const int len = (int)(rowptr_f[row + 1] - b);
-    for (int ib = 0; ib < len; ib += kWave) {
-      const int i = ib + l;
-      const int32_t ci = i < len ? colind_f[b + i] : 0x7fffffff;
-      int rank = 0;
-      for (int jb = 0; jb < len; jb += kWave) {
-        const int32_t cj = jb + l < len ? colind_f[b + jb + l] : 0x7fffffff;
-        const int lim = len - jb < kWave ? len - jb : kWave;
-        for (int jj = 0; jj < lim; ++jj) rank += __builtin_amdgcn_readlane(cj, jj) < ci ? 1 : 0;
+    const bool in_a = wave_radix_sort<int32_t, double>(colind_f + b, val_f + b, tmp_c + b,
+                                                       tmp_v + b, len, shifts, np, h);
+    if (!in_a) {
+      for (int i = l; i < len; i += kWave) {
+        colind_f[b + i] = tmp_c[b + i];
+        val_f[b + i] = tmp_v[b + i];
       }
-      if (i < len) {
-        tmp_c[b + rank] = ci;
-        tmp_v[b + rank] = val_f[b + i];
-      }
-    }
-    fence_wave_local();
-    for (int i = l; i < len; i += kWave) {
-      colind_f[b + i] = tmp_c[b + i];
-      val_f[b + i] = tmp_v[b + i];
     }
     fence_wave_local();
   }
@@ -136,9 +131,11 @@ hipError_t launch_sort_rows(int64_t ntot, const int64_t *rowptr_f, int32_t *coli
 
 hipError_t launch_sort_long_rows(const int64_t *rowptr_f, int32_t *colind_f, double *val_f,
                                  const int32_t *long_rows, const int32_t *n_long, int32_t *tmp_c,
-                                 double *tmp_v, hipStream_t s) {
+                                 double *tmp_v, int64_t ntot, hipStream_t s) {
+  int nbits = 0;
+  while (nbits < 31 && ((int64_t)1 << nbits) < ntot) ++nbits;
   hipLaunchKernelGGL(k_sort_long_rows, dim3(1024), dim3(256), 0, s, rowptr_f, colind_f, val_f,
-                     long_rows, n_long, tmp_c, tmp_v);
+                     long_rows, n_long, tmp_c, tmp_v, nbits);
   return hipGetLastError();
 }
 
@@ -228,21 +225,6 @@ hipError_t launch_level_place(int64_t nrows, const int32_t *lev, const int64_t *
                               int32_t *lcursor, int32_t *order, hipStream_t s) {
   hipLaunchKernelGGL(k_level_place, dim3(nblk(nrows, kLvT * kLvItems)), dim3(kLvT), 0, s, nrows, lev,
                      lptr, lcursor, order);
-  return hipGetLastError();
-}
-
-__global__ void k_dinv(int64_t ntot, const double *__restrict__ D, double *Dinv, float *Dinv32) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ntot) return;
-  double d = D[k];
-  double v = d > 0.0 ? 1.0 / d : 0.0;  // D^+ (zero pivots: one per component)
-  Dinv[k] = v;
-  if (Dinv32) Dinv32[k] = (float)v;
-}
-
-hipError_t launch_dinv(int64_t ntot, const double *D, double *Dinv, float *Dinv32,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_dinv, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, D, Dinv, Dinv32);
   return hipGetLastError();
 }
 

@@ -111,9 +111,7 @@ hipError_t launch_level_place(int64_t nrows, const int32_t *lev, const int64_t *
                               int32_t *lcursor, int32_t *order, hipStream_t s);
 hipError_t launch_sort_long_rows(const int64_t *rowptr_f, int32_t *colind_f, double *val_f,
                                  const int32_t *long_rows, const int32_t *n_long, int32_t *tmp_c,
-                                 double *tmp_v, hipStream_t s);
-hipError_t launch_dinv(int64_t ntot, const double *D, double *Dinv, float *Dinv32,
-                       hipStream_t s);
+                                 double *tmp_v, int64_t ntot, hipStream_t s);
 hipError_t launch_cast32(int64_t n, const double *a, float *b, hipStream_t s);
 hipError_t launch_max_stats(int64_t ntot, const int64_t *uptr, const int32_t *fill_cnt,
                             const int32_t *colcnt, const int32_t *lev, unsigned long long *out,
@@ -122,17 +120,21 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
 // --- solve.hip ---
+// The solves work in position space: position p is the p-th row in level
+// order (rows of one level are contiguous), the work vectors are indexed by
+// position, and the level-ordered copies of F store positions as indices.
 struct SolveArgs {
   int64_t n;             // solved rows (labels 0..n-1)
-  const int32_t *order;  // rows by ascending level
-  const int64_t *lptr;   // row prefix over levels [depth+1]
+  const int64_t *lptr;   // position prefix over levels [depth+1]
+  const int64_t *lqf, *lqb;  // entry offset of each level's first position
+                             // in the forward / backward copy [depth+1]
   int64_t depth;
   int64_t L0;            // first level of the thin tail (solved by one workgroup)
   // level-ordered copies of F: forward rows, backward columns (no ground)
   const int64_t *lf_ptr; const int32_t *lf_idx; const double *lf_val; const float *lf_val32;
   const int64_t *lb_ptr; const int32_t *lb_idx; const double *lb_val; const float *lb_val32;
-  const double *Dinv; const float *Dinv32;
-  const int32_t *iperm;  // label -> vertex
+  const double *Dinv; const float *Dinv32;  // D^+ by position
+  const int32_t *src;    // position -> vertex of the original ordering
   const int *skip;       // device flag: nonzero => return immediately
 };
 // z = M^+ r; hlptr is the host copy of lptr
@@ -141,12 +143,19 @@ hipError_t launch_apply(const SolveArgs &a, const int64_t *hlptr, const double *
 hipError_t launch_level_layout(int64_t n, const int32_t *order, const int64_t *rowptr_f,
                                const int64_t *colptr, const int32_t *rowind, int32_t *flen,
                                int32_t *blen, hipStream_t s);
-hipError_t launch_level_copy(int64_t n, const int32_t *order, const int64_t *rowptr_f,
-                             const int32_t *colind_f, const double *val_f, const int64_t *colptr,
-                             const int32_t *rowind, const double *val, const int64_t *lf_ptr,
-                             const int64_t *lb_ptr, int32_t *lf_idx, double *lf_val,
-                             int32_t *lb_idx, double *lb_val, hipStream_t s);
-constexpr int kTailWidth = 1024;  // levels this narrow (and all above) form the tail
+hipError_t launch_level_offsets(int64_t depth, const int64_t *lptr, const int64_t *lf_ptr,
+                                const int64_t *lb_ptr, int64_t *lqf, int64_t *lqb, hipStream_t s);
+hipError_t launch_position_maps(int64_t n, const int32_t *order, const int32_t *iperm,
+                                const double *D, int32_t *posof, int32_t *src, double *pdinv,
+                                float *pdinv32, hipStream_t s);
+hipError_t launch_level_copy(int64_t n, const int32_t *order, const int32_t *posof,
+                             const int64_t *rowptr_f, const int32_t *colind_f,
+                             const double *val_f, const int64_t *colptr, const int32_t *rowind,
+                             const double *val, const int64_t *lf_ptr, const int64_t *lb_ptr,
+                             int32_t *lf_idx, double *lf_val, int32_t *lb_idx, double *lb_val,
+                             hipStream_t s);
+constexpr int kTailWidth = 1024;   // widest level the single-workgroup tail can take
+constexpr int kTailDefault = 256;  // default: levels this narrow (and all above) form the tail
 hipError_t launch_comp_init(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
                             int32_t *parent, hipStream_t s);
 hipError_t launch_comp_jump(int64_t ntot, const int32_t *src, int32_t *dst, int *changed,
@@ -233,8 +242,8 @@ struct parac_factor_s {
   double *val = nullptr;
   double *D = nullptr, *Dinv = nullptr;
   float *Dinv32 = nullptr;
-  int32_t *lev = nullptr, *order = nullptr, *root = nullptr;
-  int64_t *lptr = nullptr;
+  int32_t *lev = nullptr, *order = nullptr, *root = nullptr, *src = nullptr;
+  int64_t *lptr = nullptr, *lqf = nullptr, *lqb = nullptr;
   int64_t *lf_ptr = nullptr, *lb_ptr = nullptr;
   int32_t *lf_idx = nullptr, *lb_idx = nullptr;
   double *lf_val = nullptr, *lb_val = nullptr;

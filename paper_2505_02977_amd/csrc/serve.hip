@@ -44,16 +44,17 @@ __device__ __forceinline__ double sblock_sum(double v, double *sh) {
   return r;
 }
 
-// this workgroup's slot, its local block index and the slot's block count
+// this workgroup's slot (a copy: the kernels' stores cannot alias it, so its
+// fields stay in registers), its local block index and the slot's block count
 struct SlotBlock {
-  const PcgSlot *s;
+  PcgSlot s;
   int64_t lb, nb;
   __device__ SlotBlock(const PcgSlot *S, const int32_t *bslot) {
-    s = &S[bslot[blockIdx.x]];
-    lb = (int64_t)blockIdx.x - s->blk0;
-    nb = s->nblk;
+    s = S[bslot[blockIdx.x]];
+    lb = (int64_t)blockIdx.x - s.blk0;
+    nb = s.nblk;
   }
-  __device__ bool done() const { return s->ist[1] != 0; }
+  __device__ bool done() const { return s.ist[1] != 0; }
   __device__ void put(double v, double *sh, double *partial) const {
     const double b = sblock_sum(v, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = b;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kST) void k_sinit(const PcgSlot *S, const int32_t *
                                                double *partial) {
   __shared__ double sh[kST];
   SlotBlock sb(S, bslot);
-  const PcgSlot &s = *sb.s;
+  const PcgSlot &s = sb.s;
   double acc = 0.0;
   for (int64_t i = sb.lb * kST + threadIdx.x; i < s.n; i += sb.nb * kST) {
     const double v = s.b[i];
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kST) void k_sspmv(const PcgSlot *S, const int32_t *
                                                double *partial) {
   __shared__ double sh[kST];
   SlotBlock sb(S, bslot);
-  const PcgSlot &s = *sb.s;
+  const PcgSlot &s = sb.s;
   if (!RESID && sb.done()) return;
   const double *v = RESID ? s.x : s.p;
   const int l = lane(), grp = l / kSG, sub = l % kSG;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kST) void k_sdot(const PcgSlot *S, const int32_t *b
                                               double *partial) {
   __shared__ double sh[kST];
   SlotBlock sb(S, bslot);
-  const PcgSlot &s = *sb.s;
+  const PcgSlot &s = sb.s;
   if (sb.done()) return;
   double acc = 0.0;
   for (int64_t i = sb.lb * kST + threadIdx.x; i < s.n; i += sb.nb * kST)
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(kST) void k_saxpy2(const PcgSlot *S, const int32_t 
                                                 double *partial) {
   __shared__ double sh[kST];
   SlotBlock sb(S, bslot);
-  const PcgSlot &s = *sb.s;
+  const PcgSlot &s = sb.s;
   if (sb.done()) return;
   const double alpha = s.st[4];
   double acc = 0.0;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kST) void k_saxpy2(const PcgSlot *S, const int32_t 
 // p = z + beta p
 __global__ __launch_bounds__(kST) void k_sxpby(const PcgSlot *S, const int32_t *bslot) {
   SlotBlock sb(S, bslot);
-  const PcgSlot &s = *sb.s;
+  const PcgSlot &s = sb.s;
   if (sb.done()) return;
   const double beta = s.st[5];
   for (int64_t i = sb.lb * kST + threadIdx.x; i < s.n; i += sb.nb * kST)
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kST) void k_sxpby(const PcgSlot *S, const int32_t *
 __global__ __launch_bounds__(kST) void k_sreduce(const PcgSlot *S, const double *partial, int mode,
                                                  int first) {
   __shared__ double sh[kST];
-  const PcgSlot &s = S[blockIdx.x];
+  const PcgSlot s = S[blockIdx.x];
   if (mode != 0 && mode != 4 && s.ist[1]) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < s.nblk; i += kST) acc = acc + partial[s.blk0 + i];
@@ -238,7 +239,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_slevel_fwd(const ApplySlot *AS, const int32_t *pre,
                                                     int ns, int64_t L) {
   const int k = slot_of(pre, ns, blockIdx.x);
-  const ApplySlot &q = AS[k];
+  const ApplySlot q = AS[k];
   if (*q.a.skip) return;
   const int64_t pos = q.a.lptr[L] + (int64_t)(blockIdx.x - pre[k]) * 256 + threadIdx.x;
   if (pos < q.a.lptr[L + 1]) fwd_row<T>(q.a, pos, q.r, (T *)q.y);
@@ -248,7 +249,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_slevel_bwd(const ApplySlot *AS, const int32_t *pre,
                                                     int ns, int64_t L) {
   const int k = slot_of(pre, ns, blockIdx.x);
-  const ApplySlot &q = AS[k];
+  const ApplySlot q = AS[k];
   if (*q.a.skip) return;
   const int64_t pos = q.a.lptr[L] + (int64_t)(blockIdx.x - pre[k]) * 256 + threadIdx.x;
   if (pos < q.a.lptr[L + 1]) bwd_row<T>(q.a, pos, (const T *)q.y, (T *)q.x, q.z);
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void k_slevel_bwd(const ApplySlot *AS, const i
 template <typename T>
 __global__ __launch_bounds__(kTThreads) void k_stail(const ApplySlot *AS, const int32_t *tslot) {
   __shared__ T stage[kTStage];
-  const ApplySlot &q = AS[tslot[blockIdx.x]];
+  const ApplySlot q = AS[tslot[blockIdx.x]];
   if (*q.a.skip) return;
   tail_fwd<T>(q.a, q.r, (T *)q.y, stage);
   __syncthreads();

@@ -104,7 +104,26 @@ __global__ void k_level_lengths(int64_t n, const int32_t *__restrict__ order,
   blen[p] = (int32_t)(e - b);
 }
 
+// position maps: posof[label] = position, src[position] = original vertex,
+// D^+ by position (zero pivots give zero: one per component)
+__global__ void k_position_maps(int64_t n, const int32_t *__restrict__ order,
+                                const int32_t *__restrict__ iperm, const double *__restrict__ D,
+                                int32_t *posof, int32_t *src, double *pdinv, float *pdinv32) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t i = order[p];
+  posof[i] = (int32_t)p;
+  src[p] = iperm[i];
+  const double d = D[i];
+  const double v = d > 0.0 ? 1.0 / d : 0.0;
+  pdinv[p] = v;
+  if (pdinv32) pdinv32[p] = (float)v;
+}
+
+// position p holds row order[p]'s entries of F (rows for the forward solve;
+// columns minus the ground row for the backward one), indices as positions
 __global__ void k_level_copy(int64_t n, const int32_t *__restrict__ order,
+                             const int32_t *__restrict__ posof,
                              const int64_t *__restrict__ rowptr_f,
                              const int32_t *__restrict__ colind_f, const double *__restrict__ val_f,
                              const int64_t *__restrict__ colptr, const int32_t *__restrict__ rowind,
@@ -116,13 +135,13 @@ __global__ void k_level_copy(int64_t n, const int32_t *__restrict__ order,
   const int32_t i = order[p];
   int64_t o = lf_ptr[p];
   for (int64_t e = rowptr_f[i]; e < rowptr_f[i + 1]; ++e, ++o) {
-    lf_idx[o] = colind_f[e];
+    lf_idx[o] = posof[colind_f[e]];
     lf_val[o] = val_f[e];
   }
   o = lb_ptr[p];
   const int64_t cnt = lb_ptr[p + 1] - lb_ptr[p];
   for (int64_t t = 0; t < cnt; ++t, ++o) {
-    lb_idx[o] = rowind[colptr[i] + t];
+    lb_idx[o] = posof[rowind[colptr[i] + t]];
     lb_val[o] = val[colptr[i] + t];
   }
 }
@@ -136,14 +155,40 @@ hipError_t launch_level_layout(int64_t n, const int32_t *order, const int64_t *r
   return hipGetLastError();
 }
 
-hipError_t launch_level_copy(int64_t n, const int32_t *order, const int64_t *rowptr_f,
-                             const int32_t *colind_f, const double *val_f, const int64_t *colptr,
-                             const int32_t *rowind, const double *val, const int64_t *lf_ptr,
-                             const int64_t *lb_ptr, int32_t *lf_idx, double *lf_val,
-                             int32_t *lb_idx, double *lb_val, hipStream_t s) {
+__global__ void k_level_offsets(int64_t depth, const int64_t *__restrict__ lptr,
+                                const int64_t *__restrict__ lf_ptr,
+                                const int64_t *__restrict__ lb_ptr, int64_t *lqf, int64_t *lqb) {
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L > depth) return;
+  lqf[L] = lf_ptr[lptr[L]];
+  lqb[L] = lb_ptr[lptr[L]];
+}
+
+hipError_t launch_level_offsets(int64_t depth, const int64_t *lptr, const int64_t *lf_ptr,
+                                const int64_t *lb_ptr, int64_t *lqf, int64_t *lqb, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_offsets, dim3((unsigned)((depth + 256) / 256)), dim3(256), 0, s,
+                     depth, lptr, lf_ptr, lb_ptr, lqf, lqb);
+  return hipGetLastError();
+}
+
+hipError_t launch_position_maps(int64_t n, const int32_t *order, const int32_t *iperm,
+                                const double *D, int32_t *posof, int32_t *src, double *pdinv,
+                                float *pdinv32, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_position_maps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
+                     iperm, D, posof, src, pdinv, pdinv32);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_copy(int64_t n, const int32_t *order, const int32_t *posof,
+                             const int64_t *rowptr_f, const int32_t *colind_f,
+                             const double *val_f, const int64_t *colptr, const int32_t *rowind,
+                             const double *val, const int64_t *lf_ptr, const int64_t *lb_ptr,
+                             int32_t *lf_idx, double *lf_val, int32_t *lb_idx, double *lb_val,
+                             hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_level_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
-                     rowptr_f, colind_f, val_f, colptr, rowind, val, lf_ptr, lb_ptr, lf_idx,
+                     posof, rowptr_f, colind_f, val_f, colptr, rowind, val, lf_ptr, lb_ptr, lf_idx,
                      lf_val, lb_idx, lb_val);
   return hipGetLastError();
 }
