@@ -41,6 +41,12 @@
  *      the sampled pair, with dp[larger]++ (Alg. 3/4).
  *  R8  F(u,k) = -(w_u / D_k) for the merged neighbours, rows ascending.
  *  R9  D_k = 0 for an empty neighbourhood; the apply uses D^+.
+ *  R10 apply (§V uses vendor triangular solves, whose summation order is
+ *      not given): a row of F y = P r or F^T x = D^+ y with start value s
+ *      and products p_1..p_m in ascending column order is summed in chunks
+ *      of 64 consecutive products; each chunk sum is a left fold from its
+ *      first product, and the row value is s minus the chunk sums, folded
+ *      left in chunk order: ((s - c_1) - c_2) - ...
  */
 #include "parac_oracle.h"
 
@@ -662,6 +668,42 @@ done:
 /* ------------------------------------------------------------------------ */
 /* Preconditioner apply (R9, R10)                                           */
 /* ------------------------------------------------------------------------ */
+#define ORC_CHUNK 64
+
+/* one row of a triangular solve (R10): s minus the sum of
+ * val[e] * vec[idx[e]] over e in [b, e1), in chunks of ORC_CHUNK products */
+static double orc_row64(double s, int64_t b, int64_t e1, const int32_t *idx,
+                        const double *val, const double *vec) {
+  double acc = s;
+  for (int64_t a = b; a < e1; a += ORC_CHUNK) {
+    int64_t end = a + ORC_CHUNK < e1 ? a + ORC_CHUNK : e1;
+    double c = val[a] * vec[idx[a]];
+    for (int64_t e = a + 1; e < end; ++e) c = c + val[e] * vec[idx[e]];
+    acc = acc - c;
+  }
+  return acc;
+}
+
+static float orc_row32(float s, int64_t b, int64_t e1, const int32_t *idx,
+                       const double *val, const float *vec) {
+  float acc = s;
+  for (int64_t a = b; a < e1; a += ORC_CHUNK) {
+    int64_t end = a + ORC_CHUNK < e1 ? a + ORC_CHUNK : e1;
+    float c = (float)val[a] * vec[idx[a]];
+    for (int64_t e = a + 1; e < end; ++e) c = c + (float)val[e] * vec[idx[e]];
+    acc = acc - c;
+  }
+  return acc;
+}
+
+/* entries of column i of F without the ground row (the largest row, so the
+ * kept entries are a prefix) */
+static int64_t orc_col_end(const orc_factor_result *f, int64_t i) {
+  int64_t e = f->colptr[i + 1];
+  if (e > f->colptr[i] && f->rowind[e - 1] >= f->n) --e; /* SDDM ground (§V) */
+  return e;
+}
+
 int orc_apply(const orc_factor_result *f, const int32_t *perm, const double *r,
               double *z) {
   if (!f || f->status) return ORC_EINVAL;
@@ -669,23 +711,14 @@ int orc_apply(const orc_factor_result *f, const int32_t *perm, const double *r,
   double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
   if (!y) return ORC_ENOMEM;
   for (int64_t v = 0; v < n; ++v) y[perm ? perm[v] : v] = r[v];
-  /* forward: F y = P r, rows ascending, left fold over ascending columns */
-  for (int64_t i = 0; i < n; ++i) {
-    double acc = y[i];
-    for (int64_t e = f->rowptr_f[i]; e < f->rowptr_f[i + 1]; ++e)
-      acc = acc - f->val_f[e] * y[f->colind_f[e]];
-    y[i] = acc;
-  }
-  /* diagonal D^+ then backward: F^T x = D^+ y, rows descending */
+  /* forward: F y = P r, rows ascending; row i uses row i of F */
+  for (int64_t i = 0; i < n; ++i)
+    y[i] = orc_row64(y[i], f->rowptr_f[i], f->rowptr_f[i + 1], f->colind_f, f->val_f, y);
+  /* diagonal D^+ then backward: F^T x = D^+ y, rows descending; row i uses
+   * column i of F */
   for (int64_t i = n - 1; i >= 0; --i) {
     double dinv = f->D[i] > 0.0 ? 1.0 / f->D[i] : 0.0;
-    double acc = dinv * y[i];
-    for (int64_t e = f->colptr[i]; e < f->colptr[i + 1]; ++e) {
-      int32_t j = f->rowind[e];
-      if (j >= n) continue; /* SDDM: ground row/column dropped (§V) */
-      acc = acc - f->val[e] * y[j];
-    }
-    y[i] = acc;
+    y[i] = orc_row64(dinv * y[i], f->colptr[i], orc_col_end(f, i), f->rowind, f->val, y);
   }
   for (int64_t v = 0; v < n; ++v) z[v] = y[perm ? perm[v] : v];
   free(y);
@@ -699,21 +732,11 @@ int orc_apply32(const orc_factor_result *f, const int32_t *perm,
   float *y = (float *)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
   if (!y) return ORC_ENOMEM;
   for (int64_t v = 0; v < n; ++v) y[perm ? perm[v] : v] = (float)r[v];
-  for (int64_t i = 0; i < n; ++i) {
-    float acc = y[i];
-    for (int64_t e = f->rowptr_f[i]; e < f->rowptr_f[i + 1]; ++e)
-      acc = acc - (float)f->val_f[e] * y[f->colind_f[e]];
-    y[i] = acc;
-  }
+  for (int64_t i = 0; i < n; ++i)
+    y[i] = orc_row32(y[i], f->rowptr_f[i], f->rowptr_f[i + 1], f->colind_f, f->val_f, y);
   for (int64_t i = n - 1; i >= 0; --i) {
     float dinv = (float)(f->D[i] > 0.0 ? 1.0 / f->D[i] : 0.0);
-    float acc = dinv * y[i];
-    for (int64_t e = f->colptr[i]; e < f->colptr[i + 1]; ++e) {
-      int32_t j = f->rowind[e];
-      if (j >= n) continue;
-      acc = acc - (float)f->val[e] * y[j];
-    }
-    y[i] = acc;
+    y[i] = orc_row32(dinv * y[i], f->colptr[i], orc_col_end(f, i), f->rowind, f->val, y);
   }
   for (int64_t v = 0; v < n; ++v) z[v] = (double)y[perm ? perm[v] : v];
   free(y);

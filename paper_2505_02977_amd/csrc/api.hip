@@ -124,6 +124,21 @@ int status_from(Err &e) {
 
 }  // namespace
 
+// first level of the single-workgroup tail for a width threshold: every
+// level from it on has at most `rows` rows and at most kTailEntries entries
+// in each direction
+static int64_t tail_start(parac_factor_t f, int64_t rows) {
+  int64_t L0 = f->depth;
+  while (L0 > 0) {
+    const int64_t L = L0 - 1;
+    if (f->hlptr[L + 1] - f->hlptr[L] > rows) break;
+    if (f->hlqf[L + 1] - f->hlqf[L] > kTailEntries) break;
+    if (f->hlqb[L + 1] - f->hlqb[L] > kTailEntries) break;
+    --L0;
+  }
+  return L0;
+}
+
 // ---------------------------------------------------------------------------
 // factor
 // ---------------------------------------------------------------------------
@@ -450,11 +465,6 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
                        hipMemcpyDeviceToHost, s),
         "read");
     chk(hipStreamSynchronize(s), "sync");
-    // the thin tail: the smallest level from which every level has at most
-    // kTailDefault rows
-    int64_t L0 = depth;
-    while (L0 > 0 && F->hlptr[L0] - F->hlptr[L0 - 1] <= kTailDefault) --L0;
-    F->L0 = L0;
     // level-ordered copies of the rows (forward) and columns (backward) of F
     int32_t *flen = tmp.alloc<int32_t>(n, "flen");
     int32_t *blen = tmp.alloc<int32_t>(n, "blen");
@@ -484,6 +494,50 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     F->lqb = tmp.alloc<int64_t>(depth + 1, "lqb");
     chk(launch_level_offsets(depth, F->lptr, F->lf_ptr, F->lb_ptr, F->lqf, F->lqb, s),
         "level offsets");
+    F->hlqf.resize(depth + 1);
+    F->hlqb.resize(depth + 1);
+    chk(hipMemcpyAsync(F->hlqf.data(), F->lqf, (depth + 1) * sizeof(int64_t),
+                       hipMemcpyDeviceToHost, s),
+        "read");
+    chk(hipMemcpyAsync(F->hlqb.data(), F->lqb, (depth + 1) * sizeof(int64_t),
+                       hipMemcpyDeviceToHost, s),
+        "read");
+    // row classes of the wide levels, per direction: positions of each level
+    // ordered [thread rows | wave rows | workgroup rows]
+    int32_t *ccount = tmp.alloc<int32_t>(3 * depth, "class counts");
+    int64_t *cbase = tmp.alloc<int64_t>(3 * depth, "class bases");
+    std::vector<int32_t> hcc(3 * depth);
+    std::vector<int64_t> hcb(3 * depth);
+    for (int dir = 0; dir < 2; ++dir) {
+      const int64_t *ptr = dir == 0 ? F->lf_ptr : F->lb_ptr;
+      int32_t *&list = dir == 0 ? F->flist : F->blist;
+      int32_t *&cnt = dir == 0 ? F->fcnt : F->bcnt;
+      std::vector<int32_t> &hcnt = dir == 0 ? F->hfcnt : F->hbcnt;
+      chk(hipMemsetAsync(ccount, 0, 3 * depth * sizeof(int32_t), s), "memset");
+      chk(launch_class_count(n, F->order, F->lev, ptr, ccount, s), "class count");
+      chk(hipMemcpyAsync(hcc.data(), ccount, 3 * depth * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         s),
+          "read");
+      chk(hipStreamSynchronize(s), "sync");
+      hcnt.resize(2 * depth);
+      for (int64_t L = 0; L < depth; ++L) {
+        hcnt[2 * L] = hcc[3 * L];
+        hcnt[2 * L + 1] = hcc[3 * L + 1];
+        hcb[3 * L] = F->hlptr[L];
+        hcb[3 * L + 1] = F->hlptr[L] + hcc[3 * L];
+        hcb[3 * L + 2] = F->hlptr[L] + hcc[3 * L] + hcc[3 * L + 1];
+      }
+      list = tmp.alloc<int32_t>(n, "class list");
+      cnt = tmp.alloc<int32_t>(2 * depth, "class counts");
+      chk(hipMemcpyAsync(cnt, hcnt.data(), 2 * depth * sizeof(int32_t), hipMemcpyHostToDevice, s),
+          "upload");
+      chk(hipMemcpyAsync(cbase, hcb.data(), 3 * depth * sizeof(int64_t), hipMemcpyHostToDevice, s),
+          "upload");
+      chk(hipMemsetAsync(ccount, 0, 3 * depth * sizeof(int32_t), s), "memset");
+      chk(launch_class_place(n, F->order, F->lev, ptr, cbase, ccount, list, s), "class place");
+      chk(hipStreamSynchronize(s), "sync");  // host tables reused by the next direction
+    }
+    F->L0 = tail_start(F, kTailDefault);
     if (opt.keep_fp32) {
       F->lf_val32 = tmp.alloc<float>(nf, "lf_val32");
       F->lb_val32 = tmp.alloc<float>(nbk, "lb_val32");
@@ -492,6 +546,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     }
   }
   if (!F->Dinv) F->Dinv = tmp.alloc<double>(1, "Dinv");  // n = 0
+  F->zero = tmp.alloc<int>(1, "zero flag");
+  chk(hipMemsetAsync(F->zero, 0, sizeof(int), s), "memset");
   if (opt.keep_fp32 && !F->Dinv32) F->Dinv32 = tmp.alloc<float>(1, "Dinv32");
   // component roots (last label of each component) by pointer jumping
   F->root = tmp.alloc<int32_t>(ntot, "root");
@@ -536,7 +592,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   for (void *p : {(void *)F->perm, (void *)F->iperm, (void *)F->colptr, (void *)F->rowind,
                   (void *)F->val, (void *)F->D, (void *)F->Dinv, (void *)F->Dinv32,
                   (void *)F->lev, (void *)F->order, (void *)F->root, (void *)F->lptr,
-                  (void *)F->src, (void *)F->lqf, (void *)F->lqb,
+                  (void *)F->src, (void *)F->lqf, (void *)F->lqb, (void *)F->flist,
+                  (void *)F->blist, (void *)F->fcnt, (void *)F->bcnt, (void *)F->zero,
                   (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
                   (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
     if (p) F->bytes += tmp.keep(p, F->owned);
@@ -549,12 +606,6 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
 // ---------------------------------------------------------------------------
 static int prec_slot(int prec) { return prec == PARAC_PREC_MIXED ? 1 : 0; }
 
-// first level of the single-workgroup tail for a width threshold
-static int64_t tail_start(parac_factor_t f, int64_t rows) {
-  int64_t L0 = f->depth;
-  while (L0 > 0 && f->hlptr[L0] - f->hlptr[L0 - 1] <= rows) --L0;
-  return L0;
-}
 
 // the single-vector apply's tail threshold (at most the tail kernel's one
 // row per thread): fixed through the shape calls with one column, else the
@@ -584,6 +635,10 @@ static SolveArgs solve_args(parac_factor_t f, const int *skip, int prec) {
   a.Dinv = f->Dinv;
   a.Dinv32 = f->Dinv32;
   a.src = f->src;
+  a.flist = f->flist;
+  a.blist = f->blist;
+  a.fcnt = f->fcnt;
+  a.bcnt = f->bcnt;
   a.skip = skip;
   return a;
 }
@@ -602,15 +657,6 @@ static void ensure_work(parac_factor_t f, int prec) {
   f->bytes += 2 * (int64_t)(m * el);
 }
 
-static void apply_one(parac_factor_t f, const double *r, double *z, int prec, const int *skip,
-                      hipStream_t s) {
-  if (f->n == 0) return;
-  ensure_work(f, prec);
-  SolveArgs a = solve_args(f, skip, prec);
-  void *y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
-  void *x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
-  chk(launch_apply(a, f->hlptr.data(), r, y, x, z, prec, s), "apply");
-}
 
 // ---------------------------------------------------------------------------
 // block apply (several right-hand sides, chunks of at most kBlockCols)
@@ -711,7 +757,8 @@ static void check_consistent(parac_factor_t f, const double *b, hipStream_t s) {
 struct Batch {
   Scratch mem;
   SlotBatch B;
-  std::vector<int32_t> htotal;
+  std::vector<int32_t> htot_f, htot_b;
+  std::vector<uint8_t> hmix_f, hmix_b;
 };
 
 struct SlotView {
@@ -719,18 +766,100 @@ struct SlotView {
   parac_factor_t f;
 };
 
+// workgroups of one wide level of one system: with the lean kernel (thread
+// rows only) and with the mixed one (thread rows, wave rows four to a
+// workgroup, one workgroup per group row); mixed = the level has long rows
+static void level_groups(const std::vector<int64_t> &hlptr, const std::vector<int32_t> &cnt,
+                         int64_t L, int32_t &lean, int32_t &mixed, bool &has_long) {
+  const int64_t rows = hlptr[L + 1] - hlptr[L];
+  const int64_t nthr = cnt[2 * L], nwave = cnt[2 * L + 1];
+  lean = (int32_t)((nthr + kThrThreadsHost - 1) / kThrThreadsHost);
+  mixed = lean + (int32_t)((nwave + kWavesPerGroupHost - 1) / kWavesPerGroupHost +
+                           (rows - nthr - nwave));
+  has_long = rows > nthr;
+}
+
+// the apply tables of a batch (apply slots, wide-level workgroup prefixes per
+// direction, slots with a tail); uploads into bt.mem
+static void build_apply_tables(Batch &bt, const std::vector<ApplySlot> &as,
+                               const std::vector<parac_factor_t> &fs, hipStream_t s) {
+  const int ns = (int)as.size();
+  int64_t maxL0 = 0;
+  std::vector<int32_t> tsl;
+  for (int k = 0; k < ns; ++k) {
+    maxL0 = std::max(maxL0, as[k].a.L0);
+    if (as[k].a.L0 < fs[k]->depth) tsl.push_back(k);
+  }
+  const size_t w = (size_t)(ns + 1);
+  const size_t nl = (size_t)std::max<int64_t>(maxL0, 1);
+  std::vector<int32_t> pf(nl * w, 0), pb(nl * w, 0);
+  bt.htot_f.assign(nl, 0);
+  bt.htot_b.assign(nl, 0);
+  bt.hmix_f.assign(nl, 0);
+  bt.hmix_b.assign(nl, 0);
+  std::vector<int32_t> lf(ns), mf(ns), lbk(ns), mb(ns);
+  for (int64_t L = 0; L < maxL0; ++L) {
+    bool anyf = false, anyb = false;
+    for (int k = 0; k < ns; ++k) {
+      lf[k] = mf[k] = lbk[k] = mb[k] = 0;
+      if (L >= as[k].a.L0) continue;
+      bool hl;
+      level_groups(fs[k]->hlptr, fs[k]->hfcnt, L, lf[k], mf[k], hl);
+      anyf |= hl;
+      level_groups(fs[k]->hlptr, fs[k]->hbcnt, L, lbk[k], mb[k], hl);
+      anyb |= hl;
+    }
+    int32_t af = 0, ab = 0;
+    for (int k = 0; k < ns; ++k) {
+      pf[L * w + k] = af;
+      pb[L * w + k] = ab;
+      af += anyf ? mf[k] : lf[k];
+      ab += anyb ? mb[k] : lbk[k];
+    }
+    pf[L * w + ns] = af;
+    pb[L * w + ns] = ab;
+    bt.htot_f[L] = af;
+    bt.htot_b[L] = ab;
+    bt.hmix_f[L] = anyf;
+    bt.hmix_b[L] = anyb;
+  }
+  ApplySlot *das = bt.mem.alloc<ApplySlot>(ns, "batch apply slots");
+  int32_t *dpf = bt.mem.alloc<int32_t>((int64_t)pf.size(), "batch level table");
+  int32_t *dpb = bt.mem.alloc<int32_t>((int64_t)pb.size(), "batch level table");
+  int32_t *dts = bt.mem.alloc<int32_t>((int64_t)tsl.size(), "batch tail slots");
+  chk(hipMemcpyAsync(das, as.data(), ns * sizeof(ApplySlot), hipMemcpyHostToDevice, s), "upload");
+  chk(hipMemcpyAsync(dpf, pf.data(), pf.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+      "upload");
+  chk(hipMemcpyAsync(dpb, pb.data(), pb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+      "upload");
+  if (!tsl.empty())
+    chk(hipMemcpyAsync(dts, tsl.data(), tsl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+        "upload");
+  chk(hipStreamSynchronize(s), "sync");  // the host tables above go out of scope
+  SlotBatch &B = bt.B;
+  B.aslots = das;
+  B.maxL0 = maxL0;
+  B.pre_f = dpf;
+  B.pre_b = dpb;
+  B.htot_f = bt.htot_f.data();
+  B.htot_b = bt.htot_b.data();
+  B.hmix_f = bt.hmix_f.data();
+  B.hmix_b = bt.hmix_b.data();
+  B.ntail = (int)tsl.size();
+  B.tslot = dts;
+}
+
 // lay out the workgroups of a batch and upload its tables; partial must
 // hold the sum of slot_blocks(n) over the batch
 static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, double *partial,
                         hipStream_t s) {
   bt.mem.release_all();
-  bt.htotal.clear();
   const int ns = (int)v.size();
   std::vector<PcgSlot> ps(ns);
   std::vector<ApplySlot> as(ns);
-  std::vector<int32_t> bslot, tsl;
+  std::vector<parac_factor_t> fs(ns);
+  std::vector<int32_t> bslot;
   int blk = 0;
-  int64_t maxL0 = 0;
   for (int k = 0; k < ns; ++k) {
     ps[k] = v[k].ps;
     ps[k].nblk = slot_blocks(ps[k].n);
@@ -738,54 +867,43 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     bslot.insert(bslot.end(), (size_t)ps[k].nblk, k);
     blk += ps[k].nblk;
     parac_factor_t f = v[k].f;
+    fs[k] = f;
     ensure_work(f, prec);
     as[k].a = solve_args(f, ps[k].ist + 1, prec);
     as[k].r = ps[k].r;
     as[k].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
     as[k].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
     as[k].z = ps[k].z;
-    maxL0 = std::max(maxL0, as[k].a.L0);
-    if (as[k].a.L0 < f->depth) tsl.push_back(k);
-  }
-  std::vector<int32_t> pre((size_t)std::max<int64_t>(maxL0, 1) * (ns + 1), 0);
-  bt.htotal.assign((size_t)maxL0, 0);
-  for (int64_t L = 0; L < maxL0; ++L) {
-    int32_t acc = 0;
-    for (int k = 0; k < ns; ++k) {
-      pre[L * (ns + 1) + k] = acc;
-      parac_factor_t f = v[k].f;
-      if (L < as[k].a.L0) acc += (int32_t)((f->hlptr[L + 1] - f->hlptr[L] + 255) / 256);
-    }
-    pre[L * (ns + 1) + ns] = acc;
-    bt.htotal[L] = acc;
   }
   PcgSlot *dps = bt.mem.alloc<PcgSlot>(ns, "batch slots");
-  ApplySlot *das = bt.mem.alloc<ApplySlot>(ns, "batch apply slots");
   int32_t *dbs = bt.mem.alloc<int32_t>(blk, "batch block map");
-  int32_t *dpre = bt.mem.alloc<int32_t>((int64_t)pre.size(), "batch level table");
-  int32_t *dts = bt.mem.alloc<int32_t>((int64_t)tsl.size(), "batch tail slots");
   chk(hipMemcpyAsync(dps, ps.data(), ns * sizeof(PcgSlot), hipMemcpyHostToDevice, s), "upload");
-  chk(hipMemcpyAsync(das, as.data(), ns * sizeof(ApplySlot), hipMemcpyHostToDevice, s), "upload");
   chk(hipMemcpyAsync(dbs, bslot.data(), bslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
       "upload");
-  chk(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
-      "upload");
-  if (!tsl.empty())
-    chk(hipMemcpyAsync(dts, tsl.data(), tsl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
-        "upload");
-  chk(hipStreamSynchronize(s), "sync");  // the host tables above go out of scope
+  build_apply_tables(bt, as, fs, s);  // synchronises the stream
   SlotBatch &B = bt.B;
   B.nslots = ns;
   B.nblocks = blk;
   B.slots = dps;
   B.bslot = dbs;
   B.partial = partial;
-  B.aslots = das;
-  B.maxL0 = maxL0;
-  B.lvl_pre = dpre;
-  B.hlvl_total = bt.htotal.data();
-  B.ntail = (int)tsl.size();
-  B.tslot = dts;
+}
+
+// z = M^+ r for one vector: the batched apply with a batch of one
+static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hipStream_t s) {
+  if (f->n == 0) return;
+  ensure_work(f, prec);
+  std::vector<ApplySlot> as(1);
+  as[0].a = solve_args(f, f->zero, prec);
+  as[0].r = r;
+  as[0].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
+  as[0].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
+  as[0].z = z;
+  Batch bt;
+  build_apply_tables(bt, as, {f}, s);
+  bt.B.nslots = 1;
+  chk(slots_apply(bt.B, prec, s), "apply");
+  chk(hipStreamSynchronize(s), "sync");
 }
 
 // one system as a batch of one: the same launches, hence the same bits, as
@@ -1416,7 +1534,7 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z, int64_t n
   try {
     hipStream_t s = (hipStream_t)stream;
     if (nrhs == 1) {
-      apply_one(f, r, z, precision, nullptr, s);
+      apply_one(f, r, z, precision, s);
     } else {
       for (int64_t c0 = 0; c0 < nrhs; c0 += kBlockCols) {
         const int nc = (int)std::min<int64_t>(kBlockCols, nrhs - c0);

@@ -6,10 +6,10 @@
 // are read once for all columns (every lane of a group reads the same
 // address), the vector entries of one row are contiguous.
 //
-// Every column of the apply is folded exactly like a single-vector apply
-// (left fold in ascending column order), so each column of the block result
-// is bit for bit the single apply of that column, whatever G, CPL or the
-// level at which the single-workgroup tail starts.  The PCG recurrences of
+// Every column of the apply is summed exactly like a single-vector apply
+// (chunks of 64 products, each a left fold, subtracted in order), so each
+// column of the block result is bit for bit the single apply of that column,
+// whatever G, CPL or the level at which the single-workgroup tail starts.  The PCG recurrences of
 // the columns are independent (their own alpha, beta and stopping test).
 #include "device.hpp"
 #include "internal.hpp"
@@ -18,6 +18,7 @@
 namespace parac {
 
 // forward row at position pos: y(pos, :) = r(src pos, :) - sum_e F y(c_e, :)
+// (one lane group per row, columns across its lanes, chunks in sequence)
 template <typename T, int CPL>
 __device__ __forceinline__ void brow_fwd(const SolveArgs &a, int64_t pos, int j0, int G, int nc,
                                          const double *__restrict__ r, int64_t ldr, T *y) {
@@ -30,14 +31,29 @@ __device__ __forceinline__ void brow_fwd(const SolveArgs &a, int64_t pos, int j0
     acc[c] = j < nc ? (T)ri[j] : (T)0;
   }
   const int64_t e1 = a.lf_ptr[pos + 1];
-  for (int64_t e = a.lf_ptr[pos]; e < e1; ++e) {
-    const T f = fv[e];
-    const T *yc = y + (int64_t)a.lf_idx[e] * nc;
+  for (int64_t ch = a.lf_ptr[pos]; ch < e1; ch += kChunk) {  // chunks of the row
+    const int64_t end = ch + kChunk < e1 ? ch + kChunk : e1;
+    T cs[CPL];
+    {
+      const T f = fv[ch];
+      const T *yc = y + (int64_t)a.lf_idx[ch] * nc;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int j = j0 + c * G;
-      if (j < nc) acc[c] = acc[c] - f * yc[j];
+      for (int c = 0; c < CPL; ++c) {
+        const int j = j0 + c * G;
+        cs[c] = j < nc ? f * yc[j] : (T)0;
+      }
     }
+    for (int64_t e = ch + 1; e < end; ++e) {
+      const T f = fv[e];
+      const T *yc = y + (int64_t)a.lf_idx[e] * nc;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int j = j0 + c * G;
+        if (j < nc) cs[c] = cs[c] + f * yc[j];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = acc[c] - cs[c];
   }
   T *yi = y + pos * nc;
 #pragma unroll
@@ -62,14 +78,29 @@ __device__ __forceinline__ void brow_bwd(const SolveArgs &a, int64_t pos, int j0
     acc[c] = j < nc ? di * yi[j] : (T)0;
   }
   const int64_t e1 = a.lb_ptr[pos + 1];
-  for (int64_t e = a.lb_ptr[pos]; e < e1; ++e) {
-    const T f = fv[e];
-    const T *xc = x + (int64_t)a.lb_idx[e] * nc;
+  for (int64_t ch = a.lb_ptr[pos]; ch < e1; ch += kChunk) {  // chunks of the row
+    const int64_t end = ch + kChunk < e1 ? ch + kChunk : e1;
+    T cs[CPL];
+    {
+      const T f = fv[ch];
+      const T *xc = x + (int64_t)a.lb_idx[ch] * nc;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int j = j0 + c * G;
-      if (j < nc) acc[c] = acc[c] - f * xc[j];
+      for (int c = 0; c < CPL; ++c) {
+        const int j = j0 + c * G;
+        cs[c] = j < nc ? f * xc[j] : (T)0;
+      }
     }
+    for (int64_t e = ch + 1; e < end; ++e) {
+      const T f = fv[e];
+      const T *xc = x + (int64_t)a.lb_idx[e] * nc;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int j = j0 + c * G;
+        if (j < nc) cs[c] = cs[c] + f * xc[j];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = acc[c] - cs[c];
   }
   T *xi = x + pos * nc;
   double *zi = z + (int64_t)a.src[pos] * ldz;

@@ -135,14 +135,22 @@ struct SolveArgs {
   const int64_t *lb_ptr; const int32_t *lb_idx; const double *lb_val; const float *lb_val32;
   const double *Dinv; const float *Dinv32;  // D^+ by position
   const int32_t *src;    // position -> vertex of the original ordering
+  // wide levels: positions of each level ordered by row class (thread, wave,
+  // workgroup rows) per direction; cnt[2L], cnt[2L+1] = thread / wave rows
+  const int32_t *flist, *blist;
+  const int32_t *fcnt, *bcnt;
   const int *skip;       // device flag: nonzero => return immediately
 };
-// z = M^+ r; hlptr is the host copy of lptr
-hipError_t launch_apply(const SolveArgs &a, const int64_t *hlptr, const double *r, void *y, void *x,
-                        double *z, int prec, hipStream_t s);
 hipError_t launch_level_layout(int64_t n, const int32_t *order, const int64_t *rowptr_f,
                                const int64_t *colptr, const int32_t *rowind, int32_t *flen,
                                int32_t *blen, hipStream_t s);
+// row classes of the wide levels (by entries: at most 64, at most 4096,
+// more); counts per (level, class), then placement into per-level lists
+hipError_t launch_class_count(int64_t n, const int32_t *order, const int32_t *lev,
+                              const int64_t *ptr, int32_t *ccount, hipStream_t s);
+hipError_t launch_class_place(int64_t n, const int32_t *order, const int32_t *lev,
+                              const int64_t *ptr, const int64_t *cbase, int32_t *ccursor,
+                              int32_t *list, hipStream_t s);
 hipError_t launch_level_offsets(int64_t depth, const int64_t *lptr, const int64_t *lf_ptr,
                                 const int64_t *lb_ptr, int64_t *lqf, int64_t *lqb, hipStream_t s);
 hipError_t launch_position_maps(int64_t n, const int32_t *order, const int32_t *iperm,
@@ -156,6 +164,9 @@ hipError_t launch_level_copy(int64_t n, const int32_t *order, const int32_t *pos
                              hipStream_t s);
 constexpr int kTailWidth = 1024;   // widest level the single-workgroup tail can take
 constexpr int kTailDefault = 256;  // default: levels this narrow (and all above) form the tail
+constexpr int kTailEntries = 16384;  // most entries of a tail level (per direction)
+constexpr int kThrThreadsHost = 256;     // workgroup of a wide-level launch
+constexpr int kWavesPerGroupHost = 4;    // wave rows per workgroup
 hipError_t launch_comp_init(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
                             int32_t *parent, hipStream_t s);
 hipError_t launch_comp_jump(int64_t ntot, const int32_t *src, int32_t *dst, int *changed,
@@ -215,8 +226,12 @@ struct SlotBatch {
   double *partial = nullptr;        // device [nblocks]
   const ApplySlot *aslots = nullptr;  // device [nslots]
   int64_t maxL0 = 0;
-  const int32_t *lvl_pre = nullptr;   // device [maxL0 * (nslots + 1)]
-  const int32_t *hlvl_total = nullptr;  // host [maxL0]: workgroups of each level launch
+  // per direction, one launch per wide level L: workgroup prefix of the
+  // slots, total workgroups, and whether any slot has wave or group rows
+  // there (the mixed kernel)
+  const int32_t *pre_f = nullptr, *pre_b = nullptr;  // device [maxL0 (nslots + 1)]
+  const int32_t *htot_f = nullptr, *htot_b = nullptr;  // host [maxL0]
+  const uint8_t *hmix_f = nullptr, *hmix_b = nullptr;  // host [maxL0]
   int ntail = 0;
   const int32_t *tslot = nullptr;   // device [ntail]: slots with a thin tail
 };
@@ -243,12 +258,16 @@ struct parac_factor_s {
   double *D = nullptr, *Dinv = nullptr;
   float *Dinv32 = nullptr;
   int32_t *lev = nullptr, *order = nullptr, *root = nullptr, *src = nullptr;
+  int32_t *flist = nullptr, *blist = nullptr, *fcnt = nullptr, *bcnt = nullptr;
+  int *zero = nullptr;  // device flag that stays 0 (apply without a skip flag)
   int64_t *lptr = nullptr, *lqf = nullptr, *lqb = nullptr;
   int64_t *lf_ptr = nullptr, *lb_ptr = nullptr;
   int32_t *lf_idx = nullptr, *lb_idx = nullptr;
   double *lf_val = nullptr, *lb_val = nullptr;
   float *lf_val32 = nullptr, *lb_val32 = nullptr;
   std::vector<int64_t> hlptr;  // host copy of lptr
+  std::vector<int64_t> hlqf, hlqb;  // host copies of the level entry offsets
+  std::vector<int32_t> hfcnt, hbcnt;  // host copies of the class counts
   // solve work vectors (label space)
   void *wy64 = nullptr, *wx64 = nullptr, *wy32 = nullptr, *wx32 = nullptr;
   // block work vectors (ntot x bcols) per precision, launch shape per

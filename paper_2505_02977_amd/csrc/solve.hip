@@ -13,80 +13,70 @@
 namespace parac {
 
 // ---------------------------------------------------------------------------
-// Preconditioner apply.  The factor is stored twice in level order: the rows
-// of F for the forward solve and its columns (without the ground row) for
-// the backward solve; position p of either copy is the row order[p].  Rows of
-// one level are independent.
-//
-//  * wide levels (below L0): one launch per level, one thread per row;
-//    the level's dependencies were written by earlier launches;
-//  * the thin tail (L0 and above, at most kTailWidth rows per level): one
-//    workgroup walks the levels; per level it gathers all products into LDS
-//    with coalesced reads, then each row folds its own products.
-//
-// Every row is folded left in ascending column order, starting from the
-// right-hand side (forward) or D^+ y (backward): the order of the CPU
-// reference, so the result is the same bit for bit.
+// Layout of the preconditioner apply.  The factor is stored twice in level
+// order: the rows of F for the forward solve and its columns (without the
+// ground row) for the backward solve; position p of either copy is the row
+// order[p].  Rows of one level are independent.  The apply kernels are in
+// serve.hip (one launch per wide level for every system of a batch, one
+// workgroup per system for the thin tail), the row arithmetic in rows.hpp.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_level_fwd(SolveArgs a, int64_t p0, int64_t p1,
-                                                   const double *__restrict__ r, T *y) {
-  if (a.skip && *a.skip) return;
-  const int64_t pos = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos < p1) fwd_row<T>(a, pos, r, y);
+// row class of a wide-level row by its number of entries
+__device__ __forceinline__ int row_class(int64_t m) {
+  return m < kWaveRowMin ? 0 : (m < kGroupRowMin ? 1 : 2);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_level_bwd(SolveArgs a, int64_t p0, int64_t p1,
-                                                   const T *__restrict__ y, T *x, double *z) {
-  if (a.skip && *a.skip) return;
-  const int64_t pos = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos < p1) bwd_row<T>(a, pos, y, x, z);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kTThreads) void k_tail_fwd(SolveArgs a, const double *__restrict__ r,
-                                                        T *y) {
-  __shared__ T stage[kTStage];
-  if (a.skip && *a.skip) return;
-  tail_fwd<T>(a, r, y, stage);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kTThreads) void k_tail_bwd(SolveArgs a, const T *__restrict__ y,
-                                                        T *x, double *z) {
-  __shared__ T stage[kTStage];
-  if (a.skip && *a.skip) return;
-  tail_bwd<T>(a, y, x, z, stage);
-}
-
-template <typename T>
-static hipError_t apply_t(const SolveArgs &a, const int64_t *hlptr, const double *r, T *y, T *x,
-                          double *z, hipStream_t s) {
-  for (int64_t L = 0; L < a.L0; ++L) {
-    const int64_t p0 = hlptr[L], p1 = hlptr[L + 1];
-    if (p1 > p0)
-      hipLaunchKernelGGL(k_level_fwd<T>, dim3((unsigned)((p1 - p0 + 255) / 256)), dim3(256), 0, s,
-                         a, p0, p1, r, y);
+__global__ void k_class_count(int64_t n, const int32_t *__restrict__ order,
+                              const int32_t *__restrict__ lev, const int64_t *__restrict__ ptr,
+                              int32_t *ccount) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = p < n;
+  const int key = valid ? lev[order[p]] * 3 + row_class(ptr[p + 1] - ptr[p]) : 0;
+  // one atomic per distinct key of the wave
+  uint64_t act = __ballot(valid);
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int kl = __shfl(key, leader, kWave);
+    const uint64_t peers = __ballot(valid && key == kl) & act;
+    if (lane() == leader) atomicAdd(&ccount[kl], __popcll(peers));
+    act &= ~peers;
   }
-  if (a.L0 < a.depth) {
-    hipLaunchKernelGGL(k_tail_fwd<T>, dim3(1), dim3(kTThreads), 0, s, a, r, y);
-    hipLaunchKernelGGL(k_tail_bwd<T>, dim3(1), dim3(kTThreads), 0, s, a, (const T *)y, x, z);
+}
+
+__global__ void k_class_place(int64_t n, const int32_t *__restrict__ order,
+                              const int32_t *__restrict__ lev, const int64_t *__restrict__ ptr,
+                              const int64_t *__restrict__ cbase, int32_t *ccursor, int32_t *list) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = p < n;
+  const int key = valid ? lev[order[p]] * 3 + row_class(ptr[p + 1] - ptr[p]) : 0;
+  uint64_t act = __ballot(valid);
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int kl = __shfl(key, leader, kWave);
+    const uint64_t peers = __ballot(valid && key == kl) & act;
+    int base = 0;
+    if (lane() == leader) base = atomicAdd(&ccursor[kl], __popcll(peers));
+    base = __shfl(base, leader, kWave);
+    if ((peers >> lane()) & 1ull)
+      list[cbase[kl] + base + __popcll(peers & lanemask_lt())] = (int32_t)p;
+    act &= ~peers;
   }
-  for (int64_t L = a.L0 - 1; L >= 0; --L) {
-    const int64_t p0 = hlptr[L], p1 = hlptr[L + 1];
-    if (p1 > p0)
-      hipLaunchKernelGGL(k_level_bwd<T>, dim3((unsigned)((p1 - p0 + 255) / 256)), dim3(256), 0, s,
-                         a, p0, p1, (const T *)y, x, z);
-  }
+}
+
+hipError_t launch_class_count(int64_t n, const int32_t *order, const int32_t *lev,
+                              const int64_t *ptr, int32_t *ccount, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_class_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
+                     lev, ptr, ccount);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(const SolveArgs &a, const int64_t *hlptr, const double *r, void *y, void *x,
-                        double *z, int prec, hipStream_t s) {
-  if (prec == PARAC_PREC_MIXED)
-    return apply_t<float>(a, hlptr, r, (float *)y, (float *)x, z, s);
-  return apply_t<double>(a, hlptr, r, (double *)y, (double *)x, z, s);
+hipError_t launch_class_place(int64_t n, const int32_t *order, const int32_t *lev,
+                              const int64_t *ptr, const int64_t *cbase, int32_t *ccursor,
+                              int32_t *list, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_class_place, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
+                     lev, ptr, cbase, ccursor, list);
+  return hipGetLastError();
 }
 
 // level-ordered copies: position p holds row order[p]'s entries of F (rows

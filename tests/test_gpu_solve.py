@@ -20,10 +20,30 @@ def project(x):
 
 
 def setup_case(kind):
-    rng = np.random.default_rng({"grid": 1, "sddm": 2, "rand": 3}[kind])
+    rng = np.random.default_rng({"grid": 1, "sddm": 2, "rand": 3, "star_last": 4,
+                                 "star_first": 5, "chunglu": 6}[kind])
     if kind == "grid":
         W = inputs.grid2d_workload()
         return W.A, W.perm, W.seed, W.b, False
+    if kind.startswith("star"):
+        # a 10,000-leaf star plus a path through the leaves: the hub's row
+        # (hub last) or column (hub first) of F runs past 4096 entries, the
+        # workgroup row class of the solves
+        d = 10000
+        i = np.concatenate([np.zeros(d, int), np.arange(1, d)])
+        j = np.concatenate([np.arange(1, d + 1), np.arange(2, d + 1)])
+        A = lap(d + 1, i, j, rng.uniform(0.5, 2.0, len(i)))
+        perm = rng.permutation(d + 1).astype(np.int32)
+        k = int(np.argmax(perm == (d if kind == "star_last" else 0)))
+        perm[k], perm[0] = perm[0], perm[k]
+        b = rng.standard_normal(d + 1)
+        return A, perm, 99, b - b.mean(), False
+    if kind == "chunglu":
+        i, j = inputs.chung_lu_edges(1 << 14, 16.0, 2.1, rng)
+        n, i, j, _ = inputs.largest_component(1 << 14, i, j)
+        A = lap(n, i, j, rng.uniform(0.5, 2.0, len(i)))
+        b = rng.standard_normal(n)
+        return A, rng.permutation(n).astype(np.int32), 31, b - b.mean(), False
     n = 2500
     i, j = inputs.connected_random_edges(n, 4 * n, rng)
     ex = None
@@ -39,7 +59,7 @@ def setup_case(kind):
     return A, perm, 4242, b, ex is not None
 
 
-@pytest.mark.parametrize("kind", ["grid", "sddm", "rand"])
+@pytest.mark.parametrize("kind", ["grid", "sddm", "rand", "star_last", "star_first", "chunglu"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_apply_bit_identical(orc, kind, precision):
     torch = need_gpu()

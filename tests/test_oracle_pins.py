@@ -485,6 +485,44 @@ def test_apply_is_exact_inverse_on_exact_factor(orc):
     assert np.linalg.norm(z32 - z) <= 1e-5 * np.linalg.norm(z)
 
 
+@pytest.mark.parametrize("hub_last", [True, False])
+def test_apply_long_rows_exact_on_star(orc, hub_last):
+    """With 300 leaves the hub's row of F (hub eliminated last: forward
+    solve) or its column (hub first: backward solve) has 300 entries, so the
+    apply sums it in several 64-entry chunks (R10).  The result must equal
+    P^T F^-T D^+ F^-1 P b from dense triangular solves to rounding; with the
+    hub last the star is eliminated exactly (leaves have degree one), so
+    M^+ b also solves L z = b.  A dropped or repeated chunk, or a chunk added
+    instead of subtracted, fails both checks."""
+    rng = np.random.default_rng(21)
+    d = 300
+    A = lap(d + 1, np.zeros(d, int), np.arange(1, d + 1), rng.uniform(0.5, 2.0, d))
+    perm = np.arange(d + 1, dtype=np.int32)
+    if hub_last:
+        perm = np.roll(perm, 1).astype(np.int32)  # hub (vertex 0) gets label d
+    f = orc.factor(A, perm=perm, seed=3)
+    hub = int(perm[0])
+    if hub_last:
+        assert np.sum(f.rowind == hub) == d  # row of F with d entries
+    else:
+        assert f.colptr[hub + 1] - f.colptr[hub] == d  # column with d entries
+    b = inputs.rhs(d + 1, rng)
+    z = orc.apply(f, b)
+    F = f.dense_F()
+    Dp = np.where(f.D > 0, 1.0 / np.where(f.D > 0, f.D, 1.0), 0.0)
+    pb = np.empty(d + 1)
+    pb[perm] = b  # label space
+    y = np.linalg.solve(F, pb)
+    xl = np.linalg.solve(F.T, Dp * y)
+    zd = xl[perm]
+    assert np.linalg.norm(z - zd) <= 1e-12 * np.linalg.norm(zd)
+    if hub_last:
+        r = b - A.to_dense() @ z
+        assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
+    z32 = orc.apply(f, b, precision=1)
+    assert np.linalg.norm(z32 - z) <= 1e-5 * np.linalg.norm(z)
+
+
 # ----------------------------------------------------------------------------
 # R4: suffix sums
 # ----------------------------------------------------------------------------
