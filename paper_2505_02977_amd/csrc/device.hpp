@@ -220,12 +220,19 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
     h[4 * l + 2] = ex + c0 + c1;
     h[4 * l + 3] = ex + c0 + c1 + c2;
     fence_wave_local();
-    // stable scatter, 64 elements at a time in index order
+    // stable scatter, 64 elements at a time in index order (the next
+    // chunk's elements are loaded while the current one is placed)
+    K knext = l < n ? ks[l] : (K)0;
+    V vnext = l < n ? vs[l] : (V)0;
     for (int base = 0; base < n; base += kWave) {
       const int i = base + l;
       const bool valid = i < n;
-      const K k = valid ? ks[i] : (K)0;
-      const V v = valid ? vs[i] : (V)0;
+      const K k = knext;
+      const V v = vnext;
+      if (i + kWave < n) {
+        knext = ks[i + kWave];
+        vnext = vs[i + kWave];
+      }
       const int d = (int)(((uint64_t)k >> sh) & 255);
       uint64_t peers = __ballot(valid);
 #pragma unroll

@@ -377,7 +377,75 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   return decrement<Sync>(a, l < d, mu, mm);
 }
 
-constexpr int kRankMax = 2048;  // above this the radix sort replaces ranking
+constexpr int kRankMax = 256;   // above this the radix sort replaces ranking
+constexpr int kCoarse = 512;    // coarse suffix-sum points per wave (LDS)
+
+// Rank sorts: an entry's rank is the number of entries before it in the
+// order (keys are distinct), counted with readlanes over 64-key blocks; the
+// blocks are loaded four at a time so that their latencies overlap.
+__device__ __forceinline__ void rank_sort_key(const uint64_t *keyA, const double *wA,
+                                              uint64_t *keyB, double *wB, int g) {
+  const int l = lane();
+  for (int ib = 0; ib < g; ib += kWave) {
+    const int i = ib + l;
+    const uint64_t ki = i < g ? keyA[i] : ~0ull;
+    const double wi = i < g ? wA[i] : 0.0;
+    int rank = 0;
+    for (int jb = 0; jb < g; jb += 4 * kWave) {
+      uint64_t kj[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jb + r * kWave + l;
+        kj[r] = j < g ? keyA[j] : ~0ull;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b0 = jb + r * kWave;
+        const int lim = g - b0 < kWave ? g - b0 : kWave;
+        for (int jj = 0; jj < lim; ++jj) rank += readlane_u64(kj[r], jj) < ki ? 1 : 0;
+      }
+    }
+    if (i < g) {
+      keyB[rank] = ki;
+      wB[rank] = wi;
+    }
+  }
+}
+
+__device__ __forceinline__ void rank_sort_wu(const double *mw, const int32_t *mu, double *sw,
+                                             int32_t *su, int d) {
+  const int l = lane();
+  for (int ib = 0; ib < d; ib += kWave) {
+    const int i = ib + l;
+    const uint64_t wi = i < d ? dbits(mw[i]) : ~0ull;
+    const int32_t ui = i < d ? mu[i] : 0x7fffffff;
+    int rank = 0;
+    for (int jb = 0; jb < d; jb += 4 * kWave) {
+      uint64_t wj[4];
+      int32_t uj[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jb + r * kWave + l;
+        wj[r] = j < d ? dbits(mw[j]) : ~0ull;
+        uj[r] = j < d ? mu[j] : 0x7fffffff;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b0 = jb + r * kWave;
+        const int lim = d - b0 < kWave ? d - b0 : kWave;
+        for (int jj = 0; jj < lim; ++jj) {
+          const uint64_t ww = readlane_u64(wj[r], jj);
+          const int32_t uu = __builtin_amdgcn_readlane(uj[r], jj);
+          rank += less_wu(ww, uu, wi, ui) ? 1 : 0;
+        }
+      }
+    }
+    if (i < d) {
+      su[rank] = ui;
+      sw[rank] = bitsd(wi);
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // larger neighbourhoods: the same steps over wave-private scratch in HBM;
@@ -385,7 +453,7 @@ constexpr int kRankMax = 2048;  // above this the radix sort replaces ranking
 // ---------------------------------------------------------------------------
 template <class Sync>
 __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
-                            int levk, uint64_t deadline, int *h) {
+                            int levk, uint64_t deadline, int *h, double *coarse) {
   const int l = lane();
   const int64_t bytes = (((int64_t)g * 68) + 255) & ~(int64_t)255;
   if (bytes > wk.sc_size) {
@@ -413,6 +481,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   int32_t *mm = mu + g;
   int32_t *su = mm + g;
   // 1. gather
+#pragma unroll 4
   for (int i = l; i < g; i += kWave) {
     int32_t u, src;
     double w;
@@ -434,21 +503,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   uint64_t *keyS = keyB;   // sorted keys and weights end up here
   double *wS = wB;
   if (g <= kRankMax) {
-    // rank = number of smaller keys (keys are unique)
-    for (int ib = 0; ib < g; ib += kWave) {
-      const int i = ib + l;
-      const uint64_t ki = i < g ? keyA[i] : ~0ull;
-      int rank = 0;
-      for (int jb = 0; jb < g; jb += kWave) {
-        const uint64_t kj = (jb + l < g) ? keyA[jb + l] : ~0ull;
-        const int lim = g - jb < kWave ? g - jb : kWave;
-        for (int jj = 0; jj < lim; ++jj) rank += readlane_u64(kj, jj) < ki ? 1 : 0;
-      }
-      if (i < g) {
-        keyB[rank] = ki;
-        wB[rank] = wA[i];
-      }
-    }
+    rank_sort_key(keyA, wA, keyB, wB, g);
   } else {
     // radix passes over the bits a key can use: src + 1 in the low word,
     // u in the high word, both below 2^bits(ntot + 1)
@@ -475,56 +530,86 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       return false;
     }
   }
-  // merge runs of equal u (left fold in key order)
+  // merge runs of equal u (left fold in key order).  Chunks of 64 sorted
+  // entries are held one per lane: runs inside a chunk are folded in
+  // lockstep through shuffles, a run that reaches the end of a chunk is
+  // carried (label cu, partial sum cacc, length cm) into the next one.
   int d = 0;
+  int32_t cu = -1;
+  double cacc = 0.0;
+  int cm = 0;
+  auto emit_carry = [&]() {
+    if (l == 0) {
+      mu[d] = cu;
+      mw[d] = cacc;
+      mm[d] = cm;
+    }
+    ++d;
+    cu = -1;
+  };
+  uint64_t knext = l < g ? keyS[l] : ~0ull;
+  double wnext = l < g ? wS[l] : 0.0;
   for (int ib = 0; ib < g; ib += kWave) {
     const int i = ib + l;
+    const int n = g - ib < kWave ? g - ib : kWave;
     const bool valid = i < g;
-    const int32_t u = valid ? (int32_t)(keyS[i] >> 32) : -1;
-    const int32_t up = (valid && i > 0) ? (int32_t)(keyS[i - 1] >> 32) : -1;
-    const bool head = valid && (i == 0 || up != u);
-    double acc = 0.0;
-    int m = 0;
-    if (head) {
-      acc = wS[i];
-      m = 1;
-      for (int jx = i + 1; jx < g && (int32_t)(keyS[jx] >> 32) == u; ++jx) {
-        acc = acc + wS[jx];
+    const int32_t u = valid ? (int32_t)(knext >> 32) : -1;
+    const double w = wnext;
+    if (i + kWave < g) {
+      knext = keyS[i + kWave];
+      wnext = wS[i + kWave];
+    }
+    // lanes continuing the carried run form a prefix [0, c)
+    int c = 0;
+    if (cu >= 0) {
+      const uint64_t cont = __ballot(valid && u == cu);
+      c = ~cont == 0 ? kWave : __builtin_ctzll(~cont);
+      for (int j = 0; j < c; ++j) cacc = cacc + shfl_f64(w, j);
+      cm += c;
+      if (c < n) emit_carry();
+      if (c == n) continue;  // the whole chunk continues the carried run
+    }
+    const int32_t uprev = shfl(u, l > 0 ? l - 1 : 0);
+    const bool head = valid && l >= c && (l == c || uprev != u);
+    double acc = head ? w : 0.0;
+    int m = head ? 1 : 0;
+    bool active = head;
+    for (int step = 1; step < kWave; ++step) {
+      const int sl = l + step < kWave ? l + step : kWave - 1;
+      const double ws = shfl_f64(w, sl);
+      const int32_t us = shfl(u, sl);
+      const bool cont2 = active && (l + step < n) && us == u;
+      if (cont2) {
+        acc = acc + ws;
         ++m;
       }
+      active = cont2;
+      if (!__any(active)) break;
     }
     const uint64_t hm = __ballot(head);
-    const int pos = d + __popcll(hm & lanemask_lt());
-    if (head) {
+    uint64_t em = hm;
+    if (hm && n == kWave && ib + kWave < g) {
+      const int hl = 63 - __clzll(hm);  // the chunk's last run reaches lane 63?
+      if (shfl(u, kWave - 1) == shfl(u, hl)) {
+        em &= ~(1ull << hl);
+        cu = shfl(u, hl);
+        cacc = shfl_f64(acc, hl);
+        cm = shfl(m, hl);
+      }
+    }
+    if ((em >> l) & 1) {
+      const int pos = d + __popcll(em & lanemask_lt());
       mu[pos] = u;
       mw[pos] = acc;
       mm[pos] = m;
     }
-    d += __popcll(hm);
+    d += __popcll(em);
   }
+  if (cu >= 0) emit_carry();
   fence_wave_local();
   // 3. sampling order (w asc, u asc)
   if (d <= kRankMax) {
-    for (int ib = 0; ib < d; ib += kWave) {
-      const int i = ib + l;
-      const uint64_t wi = i < d ? dbits(mw[i]) : ~0ull;
-      const int32_t ui = i < d ? mu[i] : 0x7fffffff;
-      int rank = 0;
-      for (int jb = 0; jb < d; jb += kWave) {
-        const uint64_t wj = (jb + l < d) ? dbits(mw[jb + l]) : ~0ull;
-        const int32_t uj = (jb + l < d) ? mu[jb + l] : 0x7fffffff;
-        const int lim = d - jb < kWave ? d - jb : kWave;
-        for (int jj = 0; jj < lim; ++jj) {
-          uint64_t ww = readlane_u64(wj, jj);
-          int32_t uu = __builtin_amdgcn_readlane(uj, jj);
-          rank += less_wu(ww, uu, wi, ui) ? 1 : 0;
-        }
-      }
-      if (i < d) {
-        su[rank] = ui;
-        sw[rank] = mw[i];
-      }
-    }
+    rank_sort_wu(mw, mu, sw, su, d);
   } else {
     // the merged list is in ascending u, so a stable sort on the bits of w
     // alone yields the (w, u) order
@@ -545,12 +630,19 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   }
   fence_wave_local();
   // suffix sums: 64-wide tiles, Hillis-Steele inside, carries right to left
+  // (the next tile's values are loaded while the current one is summed)
   const int ntile = (d + kWave - 1) / kWave;
   double carry = 0.0;
+  double vnext = 0.0;
+  {
+    const int t0 = (ntile - 1) * kWave;
+    vnext = t0 + l < d ? sw[t0 + l] : 0.0;
+  }
   for (int tt = ntile - 1; tt >= 0; --tt) {
     const int t0 = tt * kWave;
     const int len = d - t0 < kWave ? d - t0 : kWave;
-    double v = l < len ? sw[t0 + l] : 0.0;
+    double v = vnext;
+    if (tt > 0) vnext = sw[t0 - kWave + l];
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
@@ -564,10 +656,15 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   fence_wave_local();
   // suffix maximum (exact): S non-increasing
   double runmax = 0.0;
+  {
+    const int t0 = (ntile - 1) * kWave;
+    vnext = t0 + l < d ? S[t0 + l] : 0.0;
+  }
   for (int tt = ntile - 1; tt >= 0; --tt) {
     const int t0 = tt * kWave;
     const int len = d - t0 < kWave ? d - t0 : kWave;
-    double v = l < len ? S[t0 + l] : 0.0;
+    double v = vnext;
+    if (tt > 0) vnext = S[t0 - kWave + l];
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
@@ -579,28 +676,79 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   }
   fence_wave_local();
   const double Dk = S[0];
-  // 4. sampled edges
-  for (int ib = 0; ib < d - 1; ib += kWave) {
-    const int s = ib + l;
-    const bool ins = s < d - 1;
-    int32_t tgt = 0, oth = 0;
-    double c = 0.0;
-    if (ins) {
-      const double Sp1 = S[s + 1];
-      const double t = draw_unit(a.seed, (uint32_t)k, (uint32_t)s) * Sp1;
-      int lo = s + 1, hi = d - 1;
-      while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        double sn = (mid + 1 < d) ? S[mid + 1] : 0.0;
-        if (sn <= t) hi = mid;
-        else lo = mid + 1;
-      }
-      const int32_t ua = su[s], ub = su[lo];
-      c = (Sp1 * sw[s]) / Dk;
-      tgt = ua < ub ? ua : ub;
-      oth = ua < ub ? ub : ua;
+  // 4. sampled edges.  The partner of slot s is the first m > s with
+  // S[m+1] <= t (S non-increasing, S[d] = 0).  A coarse copy of S in the
+  // wave's LDS (every st-th entry) narrows the search to st entries, and the
+  // searches of four rounds of 64 slots run interleaved.
+  const int st = (d + kCoarse - 1) / kCoarse;
+  const int nco = (d + st - 1) / st;  // coarse points m_j = j st, j < nco
+  for (int j = l; j < nco; j += kWave) {
+    const int m = j * st;
+    coarse[j] = m + 1 < d ? S[m + 1] : 0.0;
+  }
+  fence_wave_local();
+  constexpr int R = 4;
+  for (int ib = 0; ib < d - 1; ib += R * kWave) {
+    int lo[R], hi[R];
+    double t[R], Sp1[R];
+    bool ins[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = ib + r * kWave + l;
+      ins[r] = sl < d - 1;
+      Sp1[r] = ins[r] ? S[sl + 1] : 0.0;
     }
-    if (!insert_records(a, wk, ins, tgt, oth, k, c, deadline)) return false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = ib + r * kWave + l;
+      lo[r] = sl + 1;
+      hi[r] = d - 1;
+      if (!ins[r]) {
+        lo[r] = hi[r] = 0;
+        continue;
+      }
+      t[r] = draw_unit(a.seed, (uint32_t)k, (uint32_t)sl) * Sp1[r];
+      // coarse: smallest j with m_j >= lo and coarse[j] <= t (exists unless
+      // the answer lies beyond the last coarse point)
+      int jl = (lo[r] + st - 1) / st, jh = nco;
+      while (jl < jh) {
+        const int mid = (jl + jh) >> 1;
+        if (coarse[mid] <= t[r]) jh = mid;
+        else jl = mid + 1;
+      }
+      if (jl < nco) hi[r] = jl * st;
+      const int lo2 = (jl - 1) * st + 1;
+      if (jl > 0 && lo2 > lo[r]) lo[r] = lo2;
+    }
+    // fine search in global memory, the four rounds' loads overlapping
+    for (;;) {
+      bool any = false;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (lo[r] < hi[r]) {
+          const int mid = (lo[r] + hi[r]) >> 1;
+          const double sn = mid + 1 < d ? S[mid + 1] : 0.0;
+          if (sn <= t[r]) hi[r] = mid;
+          else lo[r] = mid + 1;
+          any = true;
+        }
+      }
+      if (!__any(any)) break;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (ib + r * kWave >= d - 1) break;  // uniform
+      const int sl = ib + r * kWave + l;
+      int32_t tgt = 0, oth = 0;
+      double c = 0.0;
+      if (ins[r]) {
+        const int32_t ua = su[sl], ub = su[lo[r]];
+        c = (Sp1[r] * sw[sl]) / Dk;
+        tgt = ua < ub ? ua : ub;
+        oth = ua < ub ? ub : ua;
+      }
+      if (!insert_records(a, wk, ins[r], tgt, oth, k, c, deadline)) return false;
+    }
   }
   // 5. column k of F
   int64_t fbase;
@@ -628,7 +776,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
 
 template <class Sync>
 __device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
-                                int *h) {
+                                int *h, double *coarse) {
   const int64_t u0 = a.uptr[k];
   const int nU = (int)(a.uptr[k + 1] - u0);
   const int nF = ld_acq_relaxed(&a.fill_cnt[k]);
@@ -643,7 +791,7 @@ __device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64
   }
   const int levk = ld_acq_relaxed(&a.lev[k]);
   if (g <= kWave) return small_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline);
-  return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h);
+  return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h, coarse);
 }
 
 // After a slot has delivered label k: read k's counter (agent scope).  Zero
@@ -671,8 +819,9 @@ __device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
   return t;
 }
 
-__global__ __launch_bounds__(256) void k_eliminate(ElimArgs a) {
-  __shared__ int hist[4][256];  // radix-sort histogram of each wave
+__global__ __launch_bounds__(256, 3) void k_eliminate(ElimArgs a) {
+  __shared__ int hist[4][256];          // radix-sort histogram of each wave
+  __shared__ double coarse[4][kCoarse];  // coarse suffix sums of each wave
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wid >= a.nworkers || a.stop_at <= 0) return;
   const uint64_t deadline = now_ticks() + a.timeout_ticks;
@@ -717,7 +866,9 @@ __global__ __launch_bounds__(256) void k_eliminate(ElimArgs a) {
     if (!sync_with_producers<WideSync>(a, k)) return;
     if (lane() == 0) next = atomicAdd(head, 1);
     next = __shfl(next, 0, kWave);
-    if (!eliminate_pivot<WideSync>(a, wk, k, deadline, hist[threadIdx.x >> 6])) return;
+    if (!eliminate_pivot<WideSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
+                                   coarse[threadIdx.x >> 6]))
+      return;
     if (lane() == 0) atomicAdd(&a.done[x * kTailStride], 1);
   }
 }
@@ -741,7 +892,8 @@ __global__ void k_tail_seed(ElimArgs a) {
 // One workgroup (16 waves, one CU) eliminates the remaining pivots; the same
 // pivot code with workgroup-scope fences and its own in-order queue.
 __global__ __launch_bounds__(1024) void k_eliminate_tail(ElimArgs a) {
-  __shared__ int hist[16][256];  // radix-sort histogram of each wave
+  __shared__ int hist[16][256];          // radix-sort histogram of each wave
+  __shared__ double coarse[16][kCoarse];  // coarse suffix sums of each wave
   const int total = *a.tq_count;
   if (total == 0) return;
   const uint64_t deadline = now_ticks() + a.timeout_ticks;
@@ -764,7 +916,9 @@ __global__ __launch_bounds__(1024) void k_eliminate_tail(ElimArgs a) {
     if (!sync_with_producers<TailSync>(a, k)) return;
     if (lane() == 0) next = __hip_atomic_fetch_add(a.tq_head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     next = __shfl(next, 0, kWave);
-    if (!eliminate_pivot<TailSync>(a, wk, k, deadline, hist[threadIdx.x >> 6])) return;
+    if (!eliminate_pivot<TailSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
+                                   coarse[threadIdx.x >> 6]))
+      return;
   }
 }
 
