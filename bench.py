@@ -67,8 +67,8 @@ def roofline(info, apply_ms, n_applies, ms_elim, elem):
     if ms_elim >= apply_ms * n_applies:
         unit, nbytes, ms = "k_eliminate (one factorisation, one persistent launch)", eb, ms_elim
     else:
-        unit, nbytes, ms = ("preconditioner apply (one k_stail workgroup per system plus one "
-                            "k_slevel launch per wide level, forward and backward)"), ab, apply_ms
+        unit, nbytes, ms = ("preconditioner apply (k_ready forward and backward sweeps, one "
+                            "launch each)"), ab, apply_ms
     achieved = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": unit,

@@ -133,23 +133,24 @@ parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
 /* z = M^+ r with M = P^T F D F^T P (SDDM: ground row/column dropped, §V).
  *   r, z       device pointers, original vertex order, n x nrhs row-major
  *   precision  PARAC_PREC_FP64, or PARAC_PREC_MIXED (needs keep_fp32)
- * The forward solve F y = P r and the backward solve F^T x = D^+ y run level
- * by level (rows of one elimination level are independent).  With nrhs > 1
- * the columns are solved together in chunks of 64 (factor read once per
- * chunk); every column equals, bit for bit, the apply of that column alone.
- * The call returns after the result is complete.  Errors: EINVAL. */
+ * The forward solve F y = P r and the backward solve F^T x = D^+ y follow
+ * the elimination levels (a row depends only on rows of earlier levels).
+ * One column: two sweeps, each a single launch in which every row starts as
+ * soon as the rows it reads are solved.  nrhs > 1: the columns are solved
+ * together in chunks of 64 (factor read once per chunk), level by level.
+ * Every column equals, bit for bit, the apply of that column alone.
+ * The call returns after the result is complete.  Errors: EINVAL, ETIMEOUT
+ * (a sweep's watchdog expired; the factor stays usable). */
 parac_status parac_apply(parac_factor_t f, const double *r, double *z,
                          int64_t nrhs, int32_t precision, void *stream);
 
-/* Launch shape of the apply for chunks of `cols` columns (1..64) in one
- * precision.  Results do not depend on it, only speed.
- *   cpl        columns per lane: 1, 2 or 4 (ignored for cols = 1)
+/* Launch shape of the block apply for chunks of `cols` columns (2..64) in
+ * one precision.  Results do not depend on it, only speed.
+ *   cpl        columns per lane: 1, 2 or 4
  *   tail_rows  levels at most this wide, and all levels after them, are
- *              solved by a single workgroup (the rest one launch per level);
- *              for cols = 1 at most 1024
- * Unless set, the first block apply (cols > 1) of a factor times the
- * candidate shapes on its own input and keeps the fastest; the
- * single-vector apply (cols = 1) uses the factor's default threshold. */
+ *              solved by a single workgroup (the rest one launch per level)
+ * Unless set, the first block apply of a factor times the candidate shapes
+ * on its own input and keeps the fastest. */
 typedef struct {
   int32_t cpl;
   int64_t tail_rows;

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libparac.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["setup.hip", "eliminate.hip", "finalize.hip", "solve.hip", "block.hip", "serve.hip", "api.hip"]
+SOURCES = ["setup.hip", "eliminate.hip", "finalize.hip", "solve.hip", "block.hip", "serve.hip", "ready.hip", "api.hip"]
 ARCH = os.environ.get("PARAC_ARCH", "gfx950")
 
 

@@ -127,6 +127,8 @@ int status_from(Err &e) {
 // first level of the single-workgroup tail for a width threshold: every
 // level from it on has at most `rows` rows and at most kTailEntries entries
 // in each direction
+constexpr double kSweepTimeoutS = 20.0;  // watchdog of one triangular sweep
+
 static int64_t tail_start(parac_factor_t f, int64_t rows) {
   int64_t L0 = f->depth;
   while (L0 > 0) {
@@ -490,54 +492,66 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
                           F->val, F->lf_ptr, F->lb_ptr, F->lf_idx, F->lf_val, F->lb_idx,
                           F->lb_val, s),
         "level_copy");
-    F->lqf = tmp.alloc<int64_t>(depth + 1, "lqf");
-    F->lqb = tmp.alloc<int64_t>(depth + 1, "lqb");
-    chk(launch_level_offsets(depth, F->lptr, F->lf_ptr, F->lb_ptr, F->lqf, F->lqb, s),
+    int64_t *lqf = tmp.alloc<int64_t>(depth + 1, "lqf");
+    int64_t *lqb = tmp.alloc<int64_t>(depth + 1, "lqb");
+    chk(launch_level_offsets(depth, F->lptr, F->lf_ptr, F->lb_ptr, lqf, lqb, s),
         "level offsets");
     F->hlqf.resize(depth + 1);
     F->hlqb.resize(depth + 1);
-    chk(hipMemcpyAsync(F->hlqf.data(), F->lqf, (depth + 1) * sizeof(int64_t),
+    chk(hipMemcpyAsync(F->hlqf.data(), lqf, (depth + 1) * sizeof(int64_t),
                        hipMemcpyDeviceToHost, s),
         "read");
-    chk(hipMemcpyAsync(F->hlqb.data(), F->lqb, (depth + 1) * sizeof(int64_t),
+    chk(hipMemcpyAsync(F->hlqb.data(), lqb, (depth + 1) * sizeof(int64_t),
                        hipMemcpyDeviceToHost, s),
         "read");
-    // row classes of the wide levels, per direction: positions of each level
-    // ordered [thread rows | wave rows | workgroup rows]
-    int32_t *ccount = tmp.alloc<int32_t>(3 * depth, "class counts");
-    int64_t *cbase = tmp.alloc<int64_t>(3 * depth, "class bases");
-    std::vector<int32_t> hcc(3 * depth);
-    std::vector<int64_t> hcb(3 * depth);
+    // per direction: the positions of each level listed by row class, then
+    // the units of the dependency-driven sweep cut from these lists
+    const int64_t ncl = (int64_t)kRowClasses * depth;
+    int32_t *ccount = tmp.alloc<int32_t>(ncl, "class counts");
+    int64_t *cbase = tmp.alloc<int64_t>(ncl, "class bases");
+    int32_t *ucount = tmp.alloc<int32_t>(n, "unit counts");
+    int32_t *ccnt = tmp.alloc<int32_t>(n, "chunk counts");
+    int64_t *uoff = tmp.alloc<int64_t>(n + 1, "unit offsets");
+    int64_t *coff = tmp.alloc<int64_t>(n + 1, "chunk offsets");
+    std::vector<int32_t> hcc(ncl);
+    std::vector<int64_t> hcb(ncl);
     for (int dir = 0; dir < 2; ++dir) {
       const int64_t *ptr = dir == 0 ? F->lf_ptr : F->lb_ptr;
       int32_t *&list = dir == 0 ? F->flist : F->blist;
-      int32_t *&cnt = dir == 0 ? F->fcnt : F->bcnt;
-      std::vector<int32_t> &hcnt = dir == 0 ? F->hfcnt : F->hbcnt;
-      chk(hipMemsetAsync(ccount, 0, 3 * depth * sizeof(int32_t), s), "memset");
+      chk(hipMemsetAsync(ccount, 0, ncl * sizeof(int32_t), s), "memset");
       chk(launch_class_count(n, F->order, F->lev, ptr, ccount, s), "class count");
-      chk(hipMemcpyAsync(hcc.data(), ccount, 3 * depth * sizeof(int32_t), hipMemcpyDeviceToHost,
-                         s),
+      chk(hipMemcpyAsync(hcc.data(), ccount, ncl * sizeof(int32_t), hipMemcpyDeviceToHost, s),
           "read");
       chk(hipStreamSynchronize(s), "sync");
-      hcnt.resize(2 * depth);
       for (int64_t L = 0; L < depth; ++L) {
-        hcnt[2 * L] = hcc[3 * L];
-        hcnt[2 * L + 1] = hcc[3 * L + 1];
-        hcb[3 * L] = F->hlptr[L];
-        hcb[3 * L + 1] = F->hlptr[L] + hcc[3 * L];
-        hcb[3 * L + 2] = F->hlptr[L] + hcc[3 * L] + hcc[3 * L + 1];
+        int64_t b = F->hlptr[L];
+        for (int c = 0; c < kRowClasses; ++c) {
+          hcb[kRowClasses * L + c] = b;
+          b += hcc[kRowClasses * L + c];
+        }
       }
       list = tmp.alloc<int32_t>(n, "class list");
-      cnt = tmp.alloc<int32_t>(2 * depth, "class counts");
-      chk(hipMemcpyAsync(cnt, hcnt.data(), 2 * depth * sizeof(int32_t), hipMemcpyHostToDevice, s),
+      chk(hipMemcpyAsync(cbase, hcb.data(), ncl * sizeof(int64_t), hipMemcpyHostToDevice, s),
           "upload");
-      chk(hipMemcpyAsync(cbase, hcb.data(), 3 * depth * sizeof(int64_t), hipMemcpyHostToDevice, s),
-          "upload");
-      chk(hipMemsetAsync(ccount, 0, 3 * depth * sizeof(int32_t), s), "memset");
+      chk(hipMemsetAsync(ccount, 0, ncl * sizeof(int32_t), s), "memset");
       chk(launch_class_place(n, F->order, F->lev, ptr, cbase, ccount, list, s), "class place");
+      // units of the dependency-driven sweep of this direction
+      chk(launch_unit_count(n, depth, F->lptr, cbase, list, ptr, ucount, ccnt, dir == 1, s),
+          "unit count");
+      chk(scan_counts(ucount, uoff, n, scan_tmp, scan_bytes, s), "scan");
+      chk(scan_counts(ccnt, coff, n, scan_tmp, scan_bytes, s), "scan");
+      const int64_t nu = read1(uoff + n, s), nch = read1(coff + n, s);
+      if (nu > INT32_MAX || nch > INT32_MAX)
+        throw Err{PARAC_EINVAL, "factor too large for the sweep's 32-bit unit tables"};
+      int4 *units = tmp.alloc<int4>(nu, "sweep units");
+      chk(launch_unit_write(n, depth, F->lptr, cbase, list, ptr, uoff, coff, units, dir == 1,
+                            s),
+          "unit write");
+      (dir == 0 ? F->task_f : F->task_b) = units;
+      (dir == 0 ? F->ntask_f : F->ntask_b) = (int32_t)nu;
+      F->ncs = std::max(F->ncs, nch);
       chk(hipStreamSynchronize(s), "sync");  // host tables reused by the next direction
     }
-    F->L0 = tail_start(F, kTailDefault);
     if (opt.keep_fp32) {
       F->lf_val32 = tmp.alloc<float>(nf, "lf_val32");
       F->lb_val32 = tmp.alloc<float>(nbk, "lb_val32");
@@ -548,6 +562,10 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   if (!F->Dinv) F->Dinv = tmp.alloc<double>(1, "Dinv");  // n = 0
   F->zero = tmp.alloc<int>(1, "zero flag");
   chk(hipMemsetAsync(F->zero, 0, sizeof(int), s), "memset");
+  F->ctr = tmp.alloc<int32_t>(2, "sweep counters");
+  F->serr = tmp.alloc<int>(1, "sweep error");
+  chk(hipMemsetAsync(F->ctr, 0, 2 * sizeof(int32_t), s), "memset");
+  chk(hipMemsetAsync(F->serr, 0, sizeof(int), s), "memset");
   if (opt.keep_fp32 && !F->Dinv32) F->Dinv32 = tmp.alloc<float>(1, "Dinv32");
   // component roots (last label of each component) by pointer jumping
   F->root = tmp.alloc<int32_t>(ntot, "root");
@@ -592,8 +610,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   for (void *p : {(void *)F->perm, (void *)F->iperm, (void *)F->colptr, (void *)F->rowind,
                   (void *)F->val, (void *)F->D, (void *)F->Dinv, (void *)F->Dinv32,
                   (void *)F->lev, (void *)F->order, (void *)F->root, (void *)F->lptr,
-                  (void *)F->src, (void *)F->lqf, (void *)F->lqb, (void *)F->flist,
-                  (void *)F->blist, (void *)F->fcnt, (void *)F->bcnt, (void *)F->zero,
+                  (void *)F->src, (void *)F->flist, (void *)F->blist, (void *)F->zero,
+                  (void *)F->task_f, (void *)F->task_b, (void *)F->ctr, (void *)F->serr,
                   (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
                   (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
     if (p) F->bytes += tmp.keep(p, F->owned);
@@ -607,23 +625,11 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
 static int prec_slot(int prec) { return prec == PARAC_PREC_MIXED ? 1 : 0; }
 
 
-// the single-vector apply's tail threshold (at most the tail kernel's one
-// row per thread): fixed through the shape calls with one column, else the
-// factor's default
-static int64_t single_tail_start(parac_factor_t f, int prec) {
-  auto it = f->shapes.find(std::make_pair(1, prec_slot(prec)));
-  if (it == f->shapes.end()) return f->L0;
-  return tail_start(f, std::min<int64_t>(it->second.tail_rows, kTailWidth));
-}
-
-static SolveArgs solve_args(parac_factor_t f, const int *skip, int prec) {
+static SolveArgs solve_args(parac_factor_t f, const int *skip) {
   SolveArgs a{};
   a.n = f->n;
   a.lptr = f->lptr;
-  a.lqf = f->lqf;
-  a.lqb = f->lqb;
   a.depth = f->depth;
-  a.L0 = single_tail_start(f, prec);
   a.lf_ptr = f->lf_ptr;
   a.lf_idx = f->lf_idx;
   a.lf_val = f->lf_val;
@@ -637,26 +643,60 @@ static SolveArgs solve_args(parac_factor_t f, const int *skip, int prec) {
   a.src = f->src;
   a.flist = f->flist;
   a.blist = f->blist;
-  a.fcnt = f->fcnt;
-  a.bcnt = f->bcnt;
   a.skip = skip;
+  a.task_f = f->task_f;
+  a.task_b = f->task_b;
+  a.ntask_f = f->ntask_f;
+  a.ntask_b = f->ntask_b;
+  a.err = f->serr;
+  a.timeout_ticks = (uint64_t)(kSweepTimeoutS * 1000.0 * (double)wall_khz());
   return a;
 }
 
 // label-space work vectors of the two triangular solves
-static void ensure_work(parac_factor_t f, int prec) {
-  void **py = prec == PARAC_PREC_MIXED ? &f->wy32 : &f->wy64;
-  void **px = prec == PARAC_PREC_MIXED ? &f->wx32 : &f->wx64;
+// every entry of the sweep vectors and chunk sums pending, counters and
+// error word cleared: the state each sweep pair starts from and leaves
+static void reset_work(parac_factor_t f, int prec, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(f->ntot, 1), c = std::max<int64_t>(f->ncs, 1);
+  if (prec == PARAC_PREC_MIXED) {
+    for (void *p : {f->wy32, f->wx32})
+      chk(launch_fill_u32((uint32_t *)p, kPending32, m, s), "fill");
+    chk(launch_fill_u32((uint32_t *)f->cs32, kPending32, c, s), "fill");
+  } else {
+    for (void *p : {f->wy64, f->wx64})
+      chk(launch_fill_u64((uint64_t *)p, kPending64, m, s), "fill");
+    chk(launch_fill_u64((uint64_t *)f->cs64, kPending64, c, s), "fill");
+  }
+  chk(hipMemsetAsync(f->ctr, 0, 2 * sizeof(int32_t), s), "memset");
+  chk(hipMemsetAsync(f->serr, 0, sizeof(int), s), "memset");
+}
+
+static void ensure_work(parac_factor_t f, int prec, hipStream_t s) {
+  const bool mixed = prec == PARAC_PREC_MIXED;
+  void **py = mixed ? &f->wy32 : &f->wy64;
+  void **px = mixed ? &f->wx32 : &f->wx64;
+  void **pc = mixed ? &f->cs32 : &f->cs64;
   if (*py) return;
-  const size_t el = prec == PARAC_PREC_MIXED ? 4 : 8;
-  const int64_t m = std::max<int64_t>(f->ntot, 1);
+  const size_t el = mixed ? 4 : 8;
+  const int64_t m = std::max<int64_t>(f->ntot, 1), c = std::max<int64_t>(f->ncs, 1);
   chk(hipMalloc(py, m * el), "work vector");
   f->owned.push_back(*py);
   chk(hipMalloc(px, m * el), "work vector");
   f->owned.push_back(*px);
-  f->bytes += 2 * (int64_t)(m * el);
+  chk(hipMalloc(pc, c * el), "chunk sums");
+  f->owned.push_back(*pc);
+  f->bytes += (int64_t)((2 * m + c) * el);
+  reset_work(f, prec, s);
 }
 
+// after sweeps have run: a watchdog error leaves the sweep state
+// inconsistent, so it is reset before the error is reported
+static void check_sweeps(parac_factor_t f, int prec, hipStream_t s) {
+  if (read1(f->serr, s) == 0) return;
+  reset_work(f, prec, s);
+  chk(hipStreamSynchronize(s), "sync");
+  throw Err{PARAC_ETIMEOUT, "triangular sweep watchdog expired"};
+}
 
 // ---------------------------------------------------------------------------
 // block apply (several right-hand sides, chunks of at most kBlockCols)
@@ -687,7 +727,7 @@ static void apply_block(parac_factor_t f, const parac_block_shape &shp, int nc, 
                         hipStream_t s) {
   if (f->n == 0) return;
   ensure_bwork(f, prec, nc);
-  SolveArgs a = solve_args(f, skip, prec);
+  SolveArgs a = solve_args(f, skip);
   BlockShape sh{shp.cpl, tail_start(f, shp.tail_rows)};
   const int k = prec_slot(prec);
   chk(launch_block_apply(a, f->hlptr.data(), sh, nc, r, ldr, f->bwy[k], f->bwx[k], z, ldz, prec,
@@ -757,8 +797,6 @@ static void check_consistent(parac_factor_t f, const double *b, hipStream_t s) {
 struct Batch {
   Scratch mem;
   SlotBatch B;
-  std::vector<int32_t> htot_f, htot_b;
-  std::vector<uint8_t> hmix_f, hmix_b;
 };
 
 struct SlotView {
@@ -766,87 +804,35 @@ struct SlotView {
   parac_factor_t f;
 };
 
-// workgroups of one wide level of one system: with the lean kernel (thread
-// rows only) and with the mixed one (thread rows, wave rows four to a
-// workgroup, one workgroup per group row); mixed = the level has long rows
-static void level_groups(const std::vector<int64_t> &hlptr, const std::vector<int32_t> &cnt,
-                         int64_t L, int32_t &lean, int32_t &mixed, bool &has_long) {
-  const int64_t rows = hlptr[L + 1] - hlptr[L];
-  const int64_t nthr = cnt[2 * L], nwave = cnt[2 * L + 1];
-  lean = (int32_t)((nthr + kThrThreadsHost - 1) / kThrThreadsHost);
-  mixed = lean + (int32_t)((nwave + kWavesPerGroupHost - 1) / kWavesPerGroupHost +
-                           (rows - nthr - nwave));
-  has_long = rows > nthr;
-}
-
-// the apply tables of a batch (apply slots, wide-level workgroup prefixes per
-// direction, slots with a tail); uploads into bt.mem
+// the apply tables of a batch: its apply slots and the workgroups of the
+// sweeps, each system's dealt out round-robin so that every system starts
+// at once.  Uploads into bt.mem.
 static void build_apply_tables(Batch &bt, const std::vector<ApplySlot> &as,
                                const std::vector<parac_factor_t> &fs, hipStream_t s) {
   const int ns = (int)as.size();
-  int64_t maxL0 = 0;
-  std::vector<int32_t> tsl;
+  std::vector<int32_t> g(ns);
+  int32_t gmax = 0;
   for (int k = 0; k < ns; ++k) {
-    maxL0 = std::max(maxL0, as[k].a.L0);
-    if (as[k].a.L0 < fs[k]->depth) tsl.push_back(k);
+    const int64_t nt = std::max(fs[k]->ntask_f, fs[k]->ntask_b);
+    const int64_t waves = kReadyThreads / 64;
+    g[k] = (int32_t)std::min<int64_t>((nt + waves - 1) / waves, kReadyGroupsMax);
+    gmax = std::max(gmax, g[k]);
   }
-  const size_t w = (size_t)(ns + 1);
-  const size_t nl = (size_t)std::max<int64_t>(maxL0, 1);
-  std::vector<int32_t> pf(nl * w, 0), pb(nl * w, 0);
-  bt.htot_f.assign(nl, 0);
-  bt.htot_b.assign(nl, 0);
-  bt.hmix_f.assign(nl, 0);
-  bt.hmix_b.assign(nl, 0);
-  std::vector<int32_t> lf(ns), mf(ns), lbk(ns), mb(ns);
-  for (int64_t L = 0; L < maxL0; ++L) {
-    bool anyf = false, anyb = false;
-    for (int k = 0; k < ns; ++k) {
-      lf[k] = mf[k] = lbk[k] = mb[k] = 0;
-      if (L >= as[k].a.L0) continue;
-      bool hl;
-      level_groups(fs[k]->hlptr, fs[k]->hfcnt, L, lf[k], mf[k], hl);
-      anyf |= hl;
-      level_groups(fs[k]->hlptr, fs[k]->hbcnt, L, lbk[k], mb[k], hl);
-      anyb |= hl;
-    }
-    int32_t af = 0, ab = 0;
-    for (int k = 0; k < ns; ++k) {
-      pf[L * w + k] = af;
-      pb[L * w + k] = ab;
-      af += anyf ? mf[k] : lf[k];
-      ab += anyb ? mb[k] : lbk[k];
-    }
-    pf[L * w + ns] = af;
-    pb[L * w + ns] = ab;
-    bt.htot_f[L] = af;
-    bt.htot_b[L] = ab;
-    bt.hmix_f[L] = anyf;
-    bt.hmix_b[L] = anyb;
-  }
+  std::vector<int32_t> map;
+  for (int32_t r = 0; r < gmax; ++r)
+    for (int k = 0; k < ns; ++k)
+      if (r < g[k]) map.push_back(k);
   ApplySlot *das = bt.mem.alloc<ApplySlot>(ns, "batch apply slots");
-  int32_t *dpf = bt.mem.alloc<int32_t>((int64_t)pf.size(), "batch level table");
-  int32_t *dpb = bt.mem.alloc<int32_t>((int64_t)pb.size(), "batch level table");
-  int32_t *dts = bt.mem.alloc<int32_t>((int64_t)tsl.size(), "batch tail slots");
+  int32_t *dmap = bt.mem.alloc<int32_t>(std::max<int64_t>((int64_t)map.size(), 1), "sweep map");
   chk(hipMemcpyAsync(das, as.data(), ns * sizeof(ApplySlot), hipMemcpyHostToDevice, s), "upload");
-  chk(hipMemcpyAsync(dpf, pf.data(), pf.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
-      "upload");
-  chk(hipMemcpyAsync(dpb, pb.data(), pb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
-      "upload");
-  if (!tsl.empty())
-    chk(hipMemcpyAsync(dts, tsl.data(), tsl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+  if (!map.empty())
+    chk(hipMemcpyAsync(dmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
         "upload");
   chk(hipStreamSynchronize(s), "sync");  // the host tables above go out of scope
   SlotBatch &B = bt.B;
   B.aslots = das;
-  B.maxL0 = maxL0;
-  B.pre_f = dpf;
-  B.pre_b = dpb;
-  B.htot_f = bt.htot_f.data();
-  B.htot_b = bt.htot_b.data();
-  B.hmix_f = bt.hmix_f.data();
-  B.hmix_b = bt.hmix_b.data();
-  B.ntail = (int)tsl.size();
-  B.tslot = dts;
+  B.wgmap = dmap;
+  B.nwg = (int)map.size();
 }
 
 // lay out the workgroups of a batch and upload its tables; partial must
@@ -868,11 +854,13 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     blk += ps[k].nblk;
     parac_factor_t f = v[k].f;
     fs[k] = f;
-    ensure_work(f, prec);
-    as[k].a = solve_args(f, ps[k].ist + 1, prec);
+    ensure_work(f, prec, s);
+    as[k].a = solve_args(f, ps[k].ist + 1);
     as[k].r = ps[k].r;
     as[k].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
     as[k].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
+    as[k].cs = prec == PARAC_PREC_MIXED ? f->cs32 : f->cs64;
+    as[k].ctr = f->ctr;
     as[k].z = ps[k].z;
   }
   PcgSlot *dps = bt.mem.alloc<PcgSlot>(ns, "batch slots");
@@ -892,18 +880,21 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
 // z = M^+ r for one vector: the batched apply with a batch of one
 static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hipStream_t s) {
   if (f->n == 0) return;
-  ensure_work(f, prec);
+  ensure_work(f, prec, s);
   std::vector<ApplySlot> as(1);
-  as[0].a = solve_args(f, f->zero, prec);
+  as[0].a = solve_args(f, f->zero);
   as[0].r = r;
   as[0].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
   as[0].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
+  as[0].cs = prec == PARAC_PREC_MIXED ? f->cs32 : f->cs64;
+  as[0].ctr = f->ctr;
   as[0].z = z;
   Batch bt;
   build_apply_tables(bt, as, {f}, s);
   bt.B.nslots = 1;
   chk(slots_apply(bt.B, prec, s), "apply");
   chk(hipStreamSynchronize(s), "sync");
+  check_sweeps(f, prec, s);
 }
 
 // one system as a batch of one: the same launches, hence the same bits, as
@@ -972,6 +963,7 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
   }
   chk(slots_true_res(B, s), "true residual");
   mark(true);  // last: end
+  check_sweeps(f, o.precision, s);
   double hst[8];
   chk(hipMemcpyAsync(hst, dst, sizeof(hst), hipMemcpyDeviceToHost, s), "read");
   chk(hipMemcpyAsync(hist, ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read");
@@ -1208,7 +1200,7 @@ void serve_setup(ServeSlot &sl, const parac_request &rq, int prec, int maxit, do
   sl.z = M.alloc<double>(n, "z");
   sl.p = M.alloc<double>(n, "p");
   sl.q = M.alloc<double>(n, "q");
-  ensure_work(sl.f, prec);
+  ensure_work(sl.f, prec, s);
   const double rtol = rq.rtol >= 0 ? rq.rtol : 1e-6;
   const double hst0[8] = {0, 0, 0, 0, 0, 0, rtol, 0};
   const int hist0[4] = {0, 0, maxit, 0};
@@ -1458,7 +1450,9 @@ static int serve_impl(const parac_request *reqs, int64_t nreq, const parac_serve
       parac_result &r = out[sl->req];
       r.iterations = hflags[4 * id];
       r.true_relres = bn > 0 ? sqrt(hst[8 * id + 7]) / bn : 0.0;
-      retire(*sl, hflags[4 * id + 1] == 1 ? PARAC_OK : PARAC_ENOCONV);
+      int stat = hflags[4 * id + 1] == 1 ? PARAC_OK : PARAC_ENOCONV;
+      if (sl->f && read1(sl->f->serr, cs) != 0) stat = PARAC_ETIMEOUT;
+      retire(*sl, stat);
     }
   }
   return PARAC_OK;
@@ -1584,7 +1578,7 @@ parac_status parac_pcg(const parac_csr *A, parac_factor_t f, const double *b, do
 
 parac_status parac_block_shape_set(parac_factor_t f, int32_t cols, int32_t precision,
                                    const parac_block_shape *shape) {
-  if (!f || cols < 1 || cols > kBlockCols ||
+  if (!f || cols < 2 || cols > kBlockCols ||
       (precision != PARAC_PREC_FP64 && precision != PARAC_PREC_MIXED) ||
       (shape && !shape_ok(*shape))) {
     g_last_error = "bad block shape arguments";

@@ -13,7 +13,6 @@
 // the columns are independent (their own alpha, beta and stopping test).
 #include "device.hpp"
 #include "internal.hpp"
-#include "rows.hpp"
 
 namespace parac {
 

@@ -126,26 +126,68 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 struct SolveArgs {
   int64_t n;             // solved rows (labels 0..n-1)
   const int64_t *lptr;   // position prefix over levels [depth+1]
-  const int64_t *lqf, *lqb;  // entry offset of each level's first position
-                             // in the forward / backward copy [depth+1]
   int64_t depth;
-  int64_t L0;            // first level of the thin tail (solved by one workgroup)
   // level-ordered copies of F: forward rows, backward columns (no ground)
   const int64_t *lf_ptr; const int32_t *lf_idx; const double *lf_val; const float *lf_val32;
   const int64_t *lb_ptr; const int32_t *lb_idx; const double *lb_val; const float *lb_val32;
   const double *Dinv; const float *Dinv32;  // D^+ by position
   const int32_t *src;    // position -> vertex of the original ordering
-  // wide levels: positions of each level ordered by row class (thread, wave,
-  // workgroup rows) per direction; cnt[2L], cnt[2L+1] = thread / wave rows
+  // positions of each level ordered by row class, per direction
   const int32_t *flist, *blist;
-  const int32_t *fcnt, *bcnt;
   const int *skip;       // device flag: nonzero => return immediately
+  // dependency-driven sweeps: units of work per direction in level order
+  const int4 *task_f, *task_b;
+  int32_t ntask_f, ntask_b;
+  int *err;                // error word of the sweeps (watchdog)
+  uint64_t timeout_ticks;  // watchdog of one sweep, wall-clock ticks
 };
+// the factor values of an apply precision
+template <typename T> struct FactorVals;
+template <> struct FactorVals<double> {
+  static __device__ __forceinline__ const double *fwd(const SolveArgs &a) { return a.lf_val; }
+  static __device__ __forceinline__ const double *bwd(const SolveArgs &a) { return a.lb_val; }
+  static __device__ __forceinline__ const double *dinv(const SolveArgs &a) { return a.Dinv; }
+};
+template <> struct FactorVals<float> {
+  static __device__ __forceinline__ const float *fwd(const SolveArgs &a) { return a.lf_val32; }
+  static __device__ __forceinline__ const float *bwd(const SolveArgs &a) { return a.lb_val32; }
+  static __device__ __forceinline__ const float *dinv(const SolveArgs &a) { return a.Dinv32; }
+};
+// A row sum is taken in chunks of kChunk products.  Row classes by entries
+// (per direction): at most 16, 64, 256, 1024, more; a row of class c < 4 is
+// solved by a group of 4^c lanes (16 entries per lane), 64 / 4^c rows to a
+// wave; a longer row in blocks of kBlockChunks chunks and a fold.
+constexpr int kChunk = 64;
+constexpr int kRowClasses = 5;
+__host__ __device__ __forceinline__ int row_class(int64_t m) {
+  return m <= 16 ? 0 : m <= 64 ? 1 : m <= 256 ? 2 : m <= 1024 ? 3 : 4;
+}
+// units of a sweep (x = kind): group of 4^kind lanes per row (y = first
+// class-list index, z = rows), block (y = position, z = first chunk,
+// w = chunk-sum offset), fold (y = position, z = chunks, w = chunk-sum
+// offset)
+constexpr int kUnitGroup1 = 0, kUnitGroup4 = 1, kUnitGroup16 = 2, kUnitGroup64 = 3;
+constexpr int kUnitBlock = 4, kUnitFold = 5;
+constexpr int kBlockChunks = 16;                // chunks of one block unit
+constexpr int kReadyThreads = 256;              // four independent waves
+constexpr int kReadyGroupsMax = 1024;           // workgroups of one system's sweep
+// a work-vector entry whose row is not solved yet (signalling NaNs)
+constexpr unsigned long long kPending64 = 0x7FF4DEADBEEF0001ull;
+constexpr unsigned int kPending32 = 0x7FA0BEEFu;
+// units of each direction (rev: levels in descending order, the backward
+// sweep) from the class lists and the class bases cls[kRowClasses L + c]:
+// counts per class-list entry in sweep order, then the units
+hipError_t launch_unit_count(int64_t n, int64_t depth, const int64_t *lptr, const int64_t *cls,
+                             const int32_t *list, const int64_t *ptr, int32_t *ucnt,
+                             int32_t *ccnt, bool rev, hipStream_t s);
+hipError_t launch_unit_write(int64_t n, int64_t depth, const int64_t *lptr, const int64_t *cls,
+                             const int32_t *list, const int64_t *ptr, const int64_t *uoff,
+                             const int64_t *coff, int4 *units, bool rev, hipStream_t s);
 hipError_t launch_level_layout(int64_t n, const int32_t *order, const int64_t *rowptr_f,
                                const int64_t *colptr, const int32_t *rowind, int32_t *flen,
                                int32_t *blen, hipStream_t s);
-// row classes of the wide levels (by entries: at most 64, at most 4096,
-// more); counts per (level, class), then placement into per-level lists
+// row classes (row_class); counts per (level, class), then placement into
+// per-level lists
 hipError_t launch_class_count(int64_t n, const int32_t *order, const int32_t *lev,
                               const int64_t *ptr, int32_t *ccount, hipStream_t s);
 hipError_t launch_class_place(int64_t n, const int32_t *order, const int32_t *lev,
@@ -162,11 +204,11 @@ hipError_t launch_level_copy(int64_t n, const int32_t *order, const int32_t *pos
                              const double *val, const int64_t *lf_ptr, const int64_t *lb_ptr,
                              int32_t *lf_idx, double *lf_val, int32_t *lb_idx, double *lb_val,
                              hipStream_t s);
-constexpr int kTailWidth = 1024;   // widest level the single-workgroup tail can take
-constexpr int kTailDefault = 256;  // default: levels this narrow (and all above) form the tail
-constexpr int kTailEntries = 16384;  // most entries of a tail level (per direction)
-constexpr int kThrThreadsHost = 256;     // workgroup of a wide-level launch
-constexpr int kWavesPerGroupHost = 4;    // wave rows per workgroup
+// block apply: levels from the first one after which every level has at
+// most tail_rows rows and kTailEntries entries per direction go to the
+// single-workgroup tail (kTailDefault: the default threshold)
+constexpr int kTailDefault = 256;
+constexpr int kTailEntries = 16384;
 hipError_t launch_comp_init(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
                             int32_t *parent, hipStream_t s);
 hipError_t launch_comp_jump(int64_t ntot, const int32_t *src, int32_t *dst, int *changed,
@@ -216,7 +258,9 @@ struct PcgSlot {
 struct ApplySlot {
   SolveArgs a;  // a.skip points at the system's done flag
   const double *r;
-  void *y, *x;  // label-space work vectors (precision of the apply)
+  void *y, *x;  // position-space work vectors (precision of the apply), all pending
+  void *cs;     // chunk sums of long rows (precision of the apply), all pending
+  int32_t *ctr;  // ticket counters of the forward and backward sweeps
   double *z;
 };
 struct SlotBatch {
@@ -225,15 +269,9 @@ struct SlotBatch {
   const int32_t *bslot = nullptr;   // device [nblocks]: slot of each workgroup
   double *partial = nullptr;        // device [nblocks]
   const ApplySlot *aslots = nullptr;  // device [nslots]
-  int64_t maxL0 = 0;
-  // per direction, one launch per wide level L: workgroup prefix of the
-  // slots, total workgroups, and whether any slot has wave or group rows
-  // there (the mixed kernel)
-  const int32_t *pre_f = nullptr, *pre_b = nullptr;  // device [maxL0 (nslots + 1)]
-  const int32_t *htot_f = nullptr, *htot_b = nullptr;  // host [maxL0]
-  const uint8_t *hmix_f = nullptr, *hmix_b = nullptr;  // host [maxL0]
-  int ntail = 0;
-  const int32_t *tslot = nullptr;   // device [ntail]: slots with a thin tail
+  // sweeps: one launch per direction; workgroup b serves slot wgmap[b]
+  const int32_t *wgmap = nullptr;  // device [nwg]
+  int nwg = 0;
 };
 int slot_blocks(int64_t n);
 hipError_t slots_init(const SlotBatch &B, hipStream_t s);
@@ -241,6 +279,8 @@ hipError_t slots_rz(const SlotBatch &B, int first, hipStream_t s);
 hipError_t slots_step(const SlotBatch &B, hipStream_t s);
 hipError_t slots_true_res(const SlotBatch &B, hipStream_t s);
 hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s);
+// --- ready.hip ---
+hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s);
 
 }  // namespace parac
 
@@ -248,7 +288,7 @@ hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s);
 struct parac_factor_s {
   int64_t n = 0, ntot = 0;
   int32_t mode = 0;
-  int64_t nnz_off = 0, depth = 0, L0 = 0;
+  int64_t nnz_off = 0, depth = 0;
   parac_factor_stats stats{};
   // device arrays
   int32_t *perm = nullptr, *iperm = nullptr;
@@ -258,18 +298,24 @@ struct parac_factor_s {
   double *D = nullptr, *Dinv = nullptr;
   float *Dinv32 = nullptr;
   int32_t *lev = nullptr, *order = nullptr, *root = nullptr, *src = nullptr;
-  int32_t *flist = nullptr, *blist = nullptr, *fcnt = nullptr, *bcnt = nullptr;
+  int32_t *flist = nullptr, *blist = nullptr;
   int *zero = nullptr;  // device flag that stays 0 (apply without a skip flag)
-  int64_t *lptr = nullptr, *lqf = nullptr, *lqb = nullptr;
+  int64_t *lptr = nullptr;
   int64_t *lf_ptr = nullptr, *lb_ptr = nullptr;
   int32_t *lf_idx = nullptr, *lb_idx = nullptr;
   double *lf_val = nullptr, *lb_val = nullptr;
   float *lf_val32 = nullptr, *lb_val32 = nullptr;
   std::vector<int64_t> hlptr;  // host copy of lptr
   std::vector<int64_t> hlqf, hlqb;  // host copies of the level entry offsets
-  std::vector<int32_t> hfcnt, hbcnt;  // host copies of the class counts
-  // solve work vectors (label space)
+  // sweep units per direction, chunk-sum entries they need (the larger)
+  int4 *task_f = nullptr, *task_b = nullptr;
+  int32_t ntask_f = 0, ntask_b = 0;
+  int64_t ncs = 0;
+  int32_t *ctr = nullptr;  // sweep ticket counters [2]
+  int *serr = nullptr;     // sweep error word
+  // solve work vectors (position space) and chunk sums per precision
   void *wy64 = nullptr, *wx64 = nullptr, *wy32 = nullptr, *wx32 = nullptr;
+  void *cs64 = nullptr, *cs32 = nullptr;
   // block work vectors (ntot x bcols) per precision, launch shape per
   // (columns, precision): set by the caller or picked by timing
   void *bwy[2] = {nullptr, nullptr}, *bwx[2] = {nullptr, nullptr};

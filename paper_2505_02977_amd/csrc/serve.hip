@@ -9,16 +9,12 @@
 // same bits alone (a batch of one, which is how single-system PCG runs) and
 // in any mix.
 //
-// The apply of a batch: for each wide level L, one launch over the rows of
-// level L of every slot that has it (a per-level table gives each slot its
-// workgroups: thread rows, wave rows and workgroup rows, see rows.hpp); then
-// one workgroup per slot walks that slot's thin tail, forward and backward;
-// then the wide levels backward.  A single system is a batch of one.
+// The apply of a batch is one forward and one backward sweep launch over
+// every slot (ready.hip); a single system is a batch of one.
 #include <float.h>
 
 #include "device.hpp"
 #include "internal.hpp"
-#include "rows.hpp"
 
 namespace parac {
 
@@ -220,87 +216,8 @@ hipError_t slots_true_res(const SlotBatch &B, hipStream_t s) {
   return hipGetLastError();
 }
 
-// --------------------------------------------------------------------------
-// batched apply
-// --------------------------------------------------------------------------
-// the slot owning workgroup b of a level launch: pre[0..ns] prefix of the
-// slots' workgroup counts (binary search)
-__device__ __forceinline__ int slot_of(const int32_t *pre, int ns, int b) {
-  int lo = 0, hi = ns;  // pre[lo] <= b < pre[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= b) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-template <typename T, bool MIXED>
-__global__ __launch_bounds__(kThrThreads) void k_slevel_fwd(const ApplySlot *AS,
-                                                            const int32_t *pre, int ns,
-                                                            int64_t L) {
-  __shared__ T cs[MIXED ? kThrThreads : 1];
-  const int k = slot_of(pre, ns, blockIdx.x);
-  const ApplySlot q = AS[k];
-  if (*q.a.skip) return;
-  fwd_level<T, MIXED>(q.a, L, (int)(blockIdx.x - pre[k]), q.r, (T *)q.y, cs);
-}
-
-template <typename T, bool MIXED>
-__global__ __launch_bounds__(kThrThreads) void k_slevel_bwd(const ApplySlot *AS,
-                                                            const int32_t *pre, int ns,
-                                                            int64_t L) {
-  __shared__ T cs[MIXED ? kThrThreads : 1];
-  const int k = slot_of(pre, ns, blockIdx.x);
-  const ApplySlot q = AS[k];
-  if (*q.a.skip) return;
-  bwd_level<T, MIXED>(q.a, L, (int)(blockIdx.x - pre[k]), (const T *)q.y, (T *)q.x, q.z, cs);
-}
-
-// one workgroup per slot with a tail: forward tail, then backward tail
-template <typename T>
-__global__ __launch_bounds__(kTThreads) void k_stail(const ApplySlot *AS, const int32_t *tslot) {
-  __shared__ TailShared<T> S;
-  const ApplySlot q = AS[tslot[blockIdx.x]];
-  if (*q.a.skip) return;
-  tail_fwd<T>(q.a, q.r, (T *)q.y, S);
-  __syncthreads();
-  tail_bwd<T>(q.a, (const T *)q.y, (T *)q.x, q.z, S);
-}
-
-template <typename T>
-static void sapply_t(const SlotBatch &B, hipStream_t s) {
-  const int64_t w = B.nslots + 1;
-  for (int64_t L = 0; L < B.maxL0; ++L) {
-    const int tot = B.htot_f[L];
-    if (tot == 0) continue;
-    if (B.hmix_f[L])
-      hipLaunchKernelGGL((k_slevel_fwd<T, true>), dim3(tot), dim3(kThrThreads), 0, s, B.aslots,
-                         B.pre_f + L * w, B.nslots, L);
-    else
-      hipLaunchKernelGGL((k_slevel_fwd<T, false>), dim3(tot), dim3(kThrThreads), 0, s, B.aslots,
-                         B.pre_f + L * w, B.nslots, L);
-  }
-  if (B.ntail > 0)
-    hipLaunchKernelGGL(k_stail<T>, dim3(B.ntail), dim3(kTThreads), 0, s, B.aslots, B.tslot);
-  for (int64_t L = B.maxL0 - 1; L >= 0; --L) {
-    const int tot = B.htot_b[L];
-    if (tot == 0) continue;
-    if (B.hmix_b[L])
-      hipLaunchKernelGGL((k_slevel_bwd<T, true>), dim3(tot), dim3(kThrThreads), 0, s, B.aslots,
-                         B.pre_b + L * w, B.nslots, L);
-    else
-      hipLaunchKernelGGL((k_slevel_bwd<T, false>), dim3(tot), dim3(kThrThreads), 0, s, B.aslots,
-                         B.pre_b + L * w, B.nslots, L);
-  }
-}
-
 hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s) {
-  if (prec == PARAC_PREC_MIXED)
-    sapply_t<float>(B, s);
-  else
-    sapply_t<double>(B, s);
-  return hipGetLastError();
+  return ready_apply(B, prec, s);
 }
 
 }  // namespace parac

@@ -8,29 +8,23 @@
 
 #include "device.hpp"
 #include "internal.hpp"
-#include "rows.hpp"
 
 namespace parac {
 
 // ---------------------------------------------------------------------------
 // Layout of the preconditioner apply.  The factor is stored twice in level
-// order: the rows of F for the forward solve and its columns (without the
-// ground row) for the backward solve; position p of either copy is the row
-// order[p].  Rows of one level are independent.  The apply kernels are in
-// serve.hip (one launch per wide level for every system of a batch, one
-// workgroup per system for the thin tail), the row arithmetic in rows.hpp.
+// order: the rows of F for the forward sweep and its columns (without the
+// ground row) for the backward sweep; position p of either copy is the row
+// order[p].  Rows of one level are independent.  Per direction, the
+// positions of each level are listed by row class, and the sweep's units
+// (ready.hip) are cut from these lists.
 // ---------------------------------------------------------------------------
-// row class of a wide-level row by its number of entries
-__device__ __forceinline__ int row_class(int64_t m) {
-  return m < kWaveRowMin ? 0 : (m < kGroupRowMin ? 1 : 2);
-}
-
 __global__ void k_class_count(int64_t n, const int32_t *__restrict__ order,
                               const int32_t *__restrict__ lev, const int64_t *__restrict__ ptr,
                               int32_t *ccount) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = p < n;
-  const int key = valid ? lev[order[p]] * 3 + row_class(ptr[p + 1] - ptr[p]) : 0;
+  const int key = valid ? lev[order[p]] * kRowClasses + row_class(ptr[p + 1] - ptr[p]) : 0;
   // one atomic per distinct key of the wave
   uint64_t act = __ballot(valid);
   while (act) {
@@ -47,7 +41,7 @@ __global__ void k_class_place(int64_t n, const int32_t *__restrict__ order,
                               const int64_t *__restrict__ cbase, int32_t *ccursor, int32_t *list) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = p < n;
-  const int key = valid ? lev[order[p]] * 3 + row_class(ptr[p + 1] - ptr[p]) : 0;
+  const int key = valid ? lev[order[p]] * kRowClasses + row_class(ptr[p + 1] - ptr[p]) : 0;
   uint64_t act = __ballot(valid);
   while (act) {
     const int leader = __ffsll((long long)act) - 1;
@@ -76,6 +70,107 @@ hipError_t launch_class_place(int64_t n, const int32_t *order, const int32_t *le
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_class_place, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order,
                      lev, ptr, cbase, ccursor, list);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Units of the dependency-driven sweeps (ready.hip), per direction, from the
+// class lists (level-major, each level ordered by row class): a group unit
+// per 64 / 4^c rows of class c < 4 of a level, and for a longer row one
+// block unit per kBlockChunks chunks followed by its fold unit.  Units come
+// out level by level in the order the sweep solves the levels (ascending
+// forward, descending backward: rev), in class-list order within a level,
+// and a fold follows its blocks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t level_of(const int64_t *lptr, int64_t depth, int64_t i) {
+  int64_t lo = 0, hi = depth;  // lptr[lo] <= i < lptr[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (lptr[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+struct UnitShape {
+  int units;    // units that start at this class-list index
+  int kind;     // group units: their kind
+  int rows;     // group units: rows
+  int64_t nch;  // chunk sums it needs (longer rows)
+  int64_t j;    // index of the class-list entry in sweep order
+};
+
+__device__ __forceinline__ UnitShape unit_shape(int64_t n, int64_t depth, const int64_t *lptr,
+                                                const int64_t *cls, const int32_t *list,
+                                                const int64_t *ptr, int64_t i, bool rev) {
+  UnitShape u{0, 0, 0, 0, i};
+  const int64_t pos = list[i];
+  const int64_t m = ptr[pos + 1] - ptr[pos];
+  const int64_t L = level_of(lptr, depth, i);
+  if (rev) u.j = (n - lptr[L + 1]) + (i - lptr[L]);
+  const int c = row_class(m);
+  if (c < kRowClasses - 1) {
+    const int per = kWave >> (2 * c);  // rows of one group unit
+    const int64_t b0 = cls[kRowClasses * L + c], b1 = cls[kRowClasses * L + c + 1];
+    const int64_t k = i - b0;
+    if (k % per == 0) {
+      u.units = 1;
+      u.kind = kUnitGroup1 + c;
+      u.rows = (int)(b1 - i < per ? b1 - i : per);
+    }
+  } else {
+    u.nch = (m + kChunk - 1) / kChunk;
+    u.units = (int)((u.nch + kBlockChunks - 1) / kBlockChunks) + 1;
+  }
+  return u;
+}
+
+__global__ void k_unit_count(int64_t n, int64_t depth, const int64_t *__restrict__ lptr,
+                             const int64_t *__restrict__ cls, const int32_t *__restrict__ list,
+                             const int64_t *__restrict__ ptr, int32_t *ucnt, int32_t *ccnt,
+                             bool rev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const UnitShape u = unit_shape(n, depth, lptr, cls, list, ptr, i, rev);
+  ucnt[u.j] = u.units;
+  ccnt[u.j] = (int32_t)u.nch;
+}
+
+__global__ void k_unit_write(int64_t n, int64_t depth, const int64_t *__restrict__ lptr,
+                             const int64_t *__restrict__ cls, const int32_t *__restrict__ list,
+                             const int64_t *__restrict__ ptr, const int64_t *__restrict__ uoff,
+                             const int64_t *__restrict__ coff, int4 *units, bool rev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const UnitShape u = unit_shape(n, depth, lptr, cls, list, ptr, i, rev);
+  if (u.units == 0) return;
+  const int64_t o = uoff[u.j];
+  const int pos = list[i];
+  if (u.nch == 0) {
+    units[o] = make_int4(u.kind, (int)i, u.rows, 0);
+  } else {
+    const int c = (int)coff[u.j];
+    const int nb = u.units - 1;
+    for (int j = 0; j < nb; ++j) units[o + j] = make_int4(kUnitBlock, pos, j * kBlockChunks, c);
+    units[o + nb] = make_int4(kUnitFold, pos, (int)u.nch, c);
+  }
+}
+
+hipError_t launch_unit_count(int64_t n, int64_t depth, const int64_t *lptr, const int64_t *cls,
+                             const int32_t *list, const int64_t *ptr, int32_t *ucnt,
+                             int32_t *ccnt, bool rev, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, depth,
+                     lptr, cls, list, ptr, ucnt, ccnt, rev);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_write(int64_t n, int64_t depth, const int64_t *lptr, const int64_t *cls,
+                             const int32_t *list, const int64_t *ptr, const int64_t *uoff,
+                             const int64_t *coff, int4 *units, bool rev, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_write, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, depth,
+                     lptr, cls, list, ptr, uoff, coff, units, rev);
   return hipGetLastError();
 }
 
