@@ -96,6 +96,38 @@ __device__ __forceinline__ float readlane_t(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// DPP lane moves within rows of 16 lanes: row_shr:1 (lane l gets lane l-1;
+// the first lane of a row keeps 0) and quad_perm [3,3,3,3] (every lane gets
+// lane 3 of its group of four)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL>((int)(unsigned)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppQuad3 = 0xFF;
+
+// short back-off between polls of one address: 64, 128, 256 cycles
+struct PollBackoff {
+  int step = 0;
+  __device__ __forceinline__ void pause() {
+    if (step == 0) __builtin_amdgcn_s_sleep(1);
+    else if (step == 1) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(4);
+    if (step < 2) ++step;
+  }
+};
+
 // the watchdog of one wave: deadline, and the sweep's error word (another
 // wave's timeout stops this one too)
 struct Watch {
@@ -113,31 +145,47 @@ struct Watch {
   }
 };
 
-// wait until every lane's v[0..m) (those with in[u]) is no longer pending;
-// reloads only what is still pending
-template <typename T, int M>
+// Wait until every lane's entries v[u] (those with in[u]) are solved.  The
+// wave polls one address at a time: of its pending entries the one solved
+// last in sweep order (positions follow the levels: the highest position
+// forward, DESC: the lowest backward), then reloads the others, which are
+// usually solved by then.  A single polled address per wave leaves the
+// memory system to the loads and stores of the rows being solved.
+template <typename T, int M, bool DESC>
 __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
                                            const bool (&in)[M], typename Bits<T>::U (&v)[M],
                                            Watch &w) {
   using B = Bits<T>;
-  auto any_pending = [&]() {
-    bool p = false;
-#pragma unroll
-    for (int u = 0; u < M; ++u) p |= in[u] && v[u] == B::kPending;
-    return p;
-  };
-  Backoff bo;
-  while (__ballot(any_pending())) {
-    if (w.expired()) {
-#pragma unroll
-      for (int u = 0; u < M; ++u)
-        if (v[u] == B::kPending) v[u] = B::kQuietNaN;
-      return;
-    }
-    bo.pause();
+  auto reload = [&]() {
 #pragma unroll
     for (int u = 0; u < M; ++u)
       if (in[u] && v[u] == B::kPending) v[u] = load_bits(vec + ci[u]);
+  };
+  for (;;) {
+    int key = INT32_MIN;
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int k = DESC ? -ci[u] : ci[u];
+      if (in[u] && v[u] == B::kPending && k > key) key = k;
+    }
+    if (!__ballot(key != INT32_MIN)) return;
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+      const int y = __shfl_xor(key, o, kWave);
+      key = y > key ? y : key;
+    }
+    const int32_t at = __builtin_amdgcn_readfirstlane(DESC ? -key : key);
+    PollBackoff bo;
+    while (load_bits(vec + at) == B::kPending) {
+      if (__ballot(w.expired())) {
+#pragma unroll
+        for (int u = 0; u < M; ++u)
+          if (v[u] == B::kPending) v[u] = B::kQuietNaN;
+        return;
+      }
+      bo.pause();
+    }
+    reload();
   }
 }
 
@@ -147,7 +195,7 @@ __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
 // fourth lane, and in every lane when G == 1 (one lane, at most 16
 // products).  Chunks are left folds from their first product: the first
 // lane of a chunk starts the fold, the next three continue it in turn.
-template <typename T, int G>
+template <typename T, int G, bool DESC>
 __device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool valid,
                                           const int32_t *__restrict__ idx,
                                           const T *__restrict__ fv, const T *vec, Watch &w) {
@@ -165,7 +213,7 @@ __device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool val
   }
 #pragma unroll
   for (int u = 0; u < 16; ++u) v[u] = in[u] ? load_bits(vec + ci[u]) : (typename B::U)0;
-  wait_ready<T, 16>(vec, ci, in, v, w);
+  wait_ready<T, 16, DESC>(vec, ci, in, v, w);
   // the lane's own products, folded from its first; a lane without entries
   // passes the running sum on
   auto fold = [&](T t, bool first) {
@@ -181,11 +229,13 @@ __device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool val
   if constexpr (G == 1) {
     return fold((T)0, true);
   } else {
+    // the four lanes of a chunk lie in one DPP row: lane l takes the running
+    // sum of lane l-1
     const int st = q & 3;
     T s = (T)0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const T prev = shfl_t(s, lane() - 1 < 0 ? 0 : lane() - 1);
+      const T prev = dpp_t<kDppRowShr1>(s);
       if (st == k) s = k == 0 ? fold((T)0, true) : fold(prev, false);
     }
     return s;
@@ -236,17 +286,26 @@ __device__ __forceinline__ void group_unit(const Sweep<T, BWD> &S, const int4 &u
   const int64_t pos = valid ? (BWD ? S.q.a.blist : S.q.a.flist)[u.y + r] : 0;
   const int64_t e0 = valid ? S.ptr[pos] : 0, e1 = valid ? S.ptr[pos + 1] : 0;
   T acc = valid && q == 0 ? S.start(pos) : (T)0;  // issued before the wait
-  const T c = group_chunks<T, G>(e0, e1, q, valid, S.idx, S.fv, S.in, w);
+  const T c = group_chunks<T, G, BWD>(e0, e1, q, valid, S.idx, S.fv, S.in, w);
   // the row value: start minus its chunk sums in chunk order (each in the
   // fourth lane of its chunk); the group's first lane publishes it
   if constexpr (G == 1) {
     if (e1 > e0) acc = acc - c;
-  } else {
+  } else if constexpr (G == 4) {
+    const T c0 = dpp_t<kDppQuad3>(c);
+    if (e1 > e0) acc = acc - c0;
+  } else if constexpr (G == 16) {
     const int base = r * G;
 #pragma unroll
     for (int k = 0; k < G / 4; ++k) {
       const T ck = shfl_t(c, base + 4 * k + 3);
-      if (q == 0 && e0 + 64 * (int64_t)k < e1) acc = acc - ck;
+      if (e0 + kChunk * (int64_t)k < e1) acc = acc - ck;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < G / 4; ++k) {
+      const T ck = readlane_t(c, 4 * k + 3);
+      if (e0 + kChunk * (int64_t)k < e1) acc = acc - ck;
     }
   }
   if (valid && q == 0) S.finish(pos, acc);
@@ -287,7 +346,7 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
       const int64_t pos = first_lane_i32(u.y);
       const int64_t e0 = S.ptr[pos], e1 = S.ptr[pos + 1];
       const int64_t c0 = u.z;
-      const T c = group_chunks<T, 64>(e0 + kChunk * c0, e1, l, true, S.idx, S.fv, S.in, w);
+      const T c = group_chunks<T, 64, BWD>(e0 + kChunk * c0, e1, l, true, S.idx, S.fv, S.in, w);
       const int64_t ck = c0 + l / 4;
       if ((l & 3) == 3 && e0 + kChunk * ck < e1) publish(cs + u.w + ck, c);
     } else {  // fold
@@ -299,7 +358,7 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
         int32_t ci[1] = {u.w + base + l};
         bool in[1] = {l < m};
         typename Bits<T>::U v[1] = {in[0] ? load_bits(cs + ci[0]) : (typename Bits<T>::U)0};
-        wait_ready<T, 1>(cs, ci, in, v, w);
+        wait_ready<T, 1, false>(cs, ci, in, v, w);
         if (in[0]) reset(cs + ci[0]);
         const T c = Bits<T>::val(v[0]);
         for (int k = 0; k < m; ++k) acc = acc - readlane_t(c, k);
