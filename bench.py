@@ -269,6 +269,7 @@ def main():
         sys.exit(2)
 
     from paper_2505_02977_amd import inputs, parac
+    inputs.PROGRESS = log  # the large generators report their stages
     name = args.workload
     W = None
     if name == "serve_200":

@@ -184,11 +184,21 @@ __device__ __forceinline__ int bitonic_partner(int l, int p, int j, bool first) 
 // between two buffers: 8-bit digits at the given shifts, a 256-bucket
 // histogram in the wave's LDS slice h, in-wave ranks by matching digits with
 // ballots.  Returns true when the sorted data ends in the first buffer.
+// Every lane issues the same global loads and stores in every chunk (lanes
+// past the end read the last element and store to a sink), so the wait for
+// the next chunk's prefetched loads does not also wait for this chunk's
+// stores.
 // ---------------------------------------------------------------------------
+static __device__ uint64_t g_radix_sink[2];
+
 template <typename K, typename V>
 __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *shifts, int npass,
                                 int *h) {
+  static_assert(sizeof(K) <= 8 && sizeof(V) <= 8, "sink holds 8-byte values");
+  if (n <= 0) return true;
   const int l = lane();
+  K *const sink_k = (K *)&g_radix_sink[0];
+  V *const sink_v = (V *)&g_radix_sink[1];
   bool in_a = true;
   for (int pass = 0; pass < npass; ++pass) {
     const int sh = shifts[pass];
@@ -201,7 +211,8 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
 #pragma unroll 4
     for (int base = 0; base < n; base += kWave) {
       const int i = base + l;
-      if (i < n) atomicAdd(&h[(int)(((uint64_t)ks[i] >> sh) & 255)], 1);
+      const K k = ks[i < n ? i : n - 1];
+      if (i < n) atomicAdd(&h[(int)(((uint64_t)k >> sh) & 255)], 1);
     }
     fence_wave_local();
     // exclusive scan of the 256 buckets, four per lane
@@ -222,17 +233,16 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
     fence_wave_local();
     // stable scatter, 64 elements at a time in index order (the next
     // chunk's elements are loaded while the current one is placed)
-    K knext = l < n ? ks[l] : (K)0;
-    V vnext = l < n ? vs[l] : (V)0;
+    K knext = ks[l < n ? l : n - 1];
+    V vnext = vs[l < n ? l : n - 1];
     for (int base = 0; base < n; base += kWave) {
       const int i = base + l;
       const bool valid = i < n;
       const K k = knext;
       const V v = vnext;
-      if (i + kWave < n) {
-        knext = ks[i + kWave];
-        vnext = vs[i + kWave];
-      }
+      const int inext = i + kWave < n ? i + kWave : n - 1;
+      knext = ks[inext];
+      vnext = vs[inext];
       const int d = (int)(((uint64_t)k >> sh) & 255);
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -242,12 +252,12 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
       }
       const int off = valid ? h[d] : 0;
       fence_wave_local();
-      if (valid) {
-        const int rank = __popcll(peers & lanemask_lt());
-        kd[off + rank] = k;
-        vd[off + rank] = v;
-        if (rank == 0) h[d] = off + __popcll(peers);
-      }
+      const int rank = __popcll(peers & lanemask_lt());
+      K *pk = valid ? kd + off + rank : sink_k;
+      V *pv = valid ? vd + off + rank : sink_v;
+      *pk = k;
+      *pv = v;
+      if (valid && rank == 0) h[d] = off + __popcll(peers);
       fence_wave_local();
     }
     fence_wave_local();

@@ -92,30 +92,49 @@ __device__ __forceinline__ bool timed_out(const ElimArgs &a, uint64_t deadline) 
   return ld_acq_relaxed(a.err) != 0;
 }
 
-// Append one sampled edge per active lane to the inbox of `tgt` and count it
-// on `oth` (insertion step of §III).  Returns false after setting an error.
-__device__ bool insert_records(const ElimArgs &a, Worker &wk, bool ins, int32_t tgt, int32_t oth,
-                               int32_t k, double c, uint64_t deadline) {
+// Append one sampled edge per active lane and round to the inbox of
+// tgt[q] and count it on oth[q] (insertion step of §III), for R rounds of
+// lanes at once: the record indices of all rounds are reserved first (one
+// round trip), then every page that one of them opens is allocated, and only
+// then does a lane wait for a page opened by another lane or wave.  Returns
+// false after setting an error.
+template <int R>
+__device__ bool insert_records(const ElimArgs &a, Worker &wk, const bool (&ins)[R],
+                               const int32_t (&tgt)[R], const int32_t (&oth)[R], int32_t k,
+                               const double (&c)[R], uint64_t deadline) {
   const int l = lane();
-  int r = ins ? fetch_add(&a.fill_cnt[tgt], 1) : 0;
-  int j = 0, off = 0;
-  if (ins) page_of(r, j, off);
-  if (__any(ins && j >= kPages)) {
+  int r[R], j[R], off[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) r[q] = ins[q] ? fetch_add(&a.fill_cnt[tgt[q]], 1) : 0;
+  bool over = false;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    j[q] = 0;
+    off[q] = 0;
+    if (ins[q]) page_of(r[q], j[q], off[q]);
+    over |= ins[q] && j[q] >= kPages;
+  }
+  if (__any(over)) {
     set_error(a.err, PARAC_EPOOL);
     return false;
   }
-  const bool alloc = ins && j > 0 && off == 0;
-  int32_t *pslot = (ins && j > 0) ? &a.ptab[(int64_t)tgt * (kPages - 1) + j - 1] : nullptr;
-  int need = alloc ? (kInline << j) : 0;
-  int incl = need;
+  // pages opened by this wave: reserve them together, publish their bases
+  int64_t pbase[R];
+  bool fail = false;
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    int y = __shfl_up(incl, o, kWave);
-    if (l >= o) incl += y;
-  }
-  const int total = shfl(incl, kWave - 1);
-  int64_t mybase = -1;
-  if (total > 0) {
+  for (int q = 0; q < R; ++q) {
+    const bool alloc = ins[q] && j[q] > 0 && off[q] == 0;
+    pbase[q] = -1;
+    if (!__any(alloc)) continue;
+    int32_t *pslot = alloc ? &a.ptab[(int64_t)tgt[q] * (kPages - 1) + j[q] - 1] : nullptr;
+    const int need = alloc ? (kInline << j[q]) : 0;
+    int incl = need;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      int y = __shfl_up(incl, o, kWave);
+      if (l >= o) incl += y;
+    }
+    const int total = shfl(incl, kWave - 1);
     if ((int64_t)total > wk.pg_left) {
       int64_t grab = total > a.pg_chunk ? total : a.pg_chunk;
       long long b = 0;
@@ -123,41 +142,56 @@ __device__ bool insert_records(const ElimArgs &a, Worker &wk, bool ins, int32_t 
       b = __shfl(b, 0, kWave);
       if (b + grab > a.pool_cap) {
         if (alloc) st_relaxed(pslot, (int32_t)-2);  // release waiters
-        set_error(a.err, PARAC_EPOOL);
-        return false;
+        fail = true;
+        continue;
       }
       wk.pg_base = b;
       wk.pg_left = grab;
     }
-    mybase = wk.pg_base + (incl - need);
+    const int64_t mybase = wk.pg_base + (incl - need);
     wk.pg_base += total;
     wk.pg_left -= total;
-    if (alloc) st_relaxed(pslot, (int32_t)mybase);
-  }
-  int64_t pbase = alloc ? mybase : -1;
-  bool wait = ins && j > 0 && !alloc;
-  Backoff bo;
-  for (int it = 0; __any(wait); ++it) {
-    if (wait) {
-      int32_t v = ld_acq_relaxed(pslot);
-      if (v != -1) {
-        pbase = v;
-        wait = false;
-      }
-    }
-    if (__any(wait)) {
-      bo.pause();
-      if ((it & 63) == 63 && timed_out(a, deadline)) return false;
+    if (alloc) {
+      st_relaxed(pslot, (int32_t)mybase);
+      pbase[q] = mybase;
     }
   }
-  if (__any(ins && j > 0 && pbase < 0)) {
+  if (fail) {
     set_error(a.err, PARAC_EPOOL);
     return false;
   }
-  if (ins) {
-    Rec *dst = (j == 0) ? a.inl + (int64_t)tgt * kInline + off : a.pool + pbase + off;
-    store_rec(dst, oth, k, c);
-    fetch_add(&a.dp[oth], 1);
+  // pages opened elsewhere: wait for their bases
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    bool wait = ins[q] && j[q] > 0 && pbase[q] < 0;
+    if (!__any(wait)) continue;
+    const int32_t *pslot = wait ? &a.ptab[(int64_t)tgt[q] * (kPages - 1) + j[q] - 1] : nullptr;
+    Backoff bo;
+    for (int it = 0; __any(wait); ++it) {
+      if (wait) {
+        int32_t v = ld_acq_relaxed(pslot);
+        if (v != -1) {
+          pbase[q] = v;
+          wait = false;
+        }
+      }
+      if (__any(wait)) {
+        bo.pause();
+        if ((it & 63) == 63 && timed_out(a, deadline)) return false;
+      }
+    }
+    if (__any(ins[q] && j[q] > 0 && pbase[q] < 0)) {
+      set_error(a.err, PARAC_EPOOL);
+      return false;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (ins[q]) {
+      Rec *dst = (j[q] == 0) ? a.inl + (int64_t)tgt[q] * kInline + off[q] : a.pool + pbase[q] + off[q];
+      store_rec(dst, oth[q], k, c[q]);
+      fetch_add(&a.dp[oth[q]], 1);
+    }
   }
   return true;
 }
@@ -236,6 +270,35 @@ __device__ __forceinline__ bool decrement(const ElimArgs &a, bool valid, int32_t
     if (__any(bad)) {
       set_error(a.err, PARAC_EINTERNAL);
       return false;
+    }
+  }
+  return true;
+}
+
+// decrement() for Q rounds of lanes: the counter updates of all rounds go
+// out together, then the labels that reached zero are enqueued
+template <class Sync, int Q>
+__device__ __forceinline__ bool decrement_batch(const ElimArgs &a, const bool (&valid)[Q],
+                                                const int32_t (&u)[Q], const int (&m)[Q]) {
+  int prior[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) prior[q] = valid[q] ? fetch_add(&a.dp[u[q]], -m[q]) : 0;
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) bad |= valid[q] && prior[q] < m[q];
+  if (__any(bad)) {
+    set_error(a.err, PARAC_EINTERNAL);
+    return false;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const bool enq = valid[q] && prior[q] == m[q];
+    if (__any(enq)) {
+      if (enq && !Sync::enqueue(a, u[q])) bad = true;
+      if (__any(bad)) {
+        set_error(a.err, PARAC_EINTERNAL);
+        return false;
+      }
     }
   }
   return true;
@@ -358,7 +421,12 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   const int32_t ub = shfl(su, lo < kWave ? lo : kWave - 1);
   const double c = (Sp1 * sw) / Dk;
   const int32_t tgt = su < ub ? su : ub, oth = su < ub ? ub : su;
-  if (!insert_records(a, wk, ins, tgt, oth, k, c, deadline)) return false;
+  {
+    const bool ins1[1] = {ins};
+    const int32_t tgt1[1] = {tgt}, oth1[1] = {oth};
+    const double c1[1] = {c};
+    if (!insert_records<1>(a, wk, ins1, tgt1, oth1, k, c1, deadline)) return false;
+  }
   // 5. column k of F (rows ascending) and D_k
   int64_t base;
   if (!alloc_column(a, wk, d, base)) return false;
@@ -630,9 +698,11 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   }
   fence_wave_local();
   // suffix sums: 64-wide tiles, Hillis-Steele inside, carries right to left
-  // (the next tile's values are loaded while the current one is summed)
+  // (the next tile's values are loaded while the current one is summed);
+  // the exact suffix maximum that makes S non-increasing is taken in the
+  // same right-to-left pass (a maximum does not depend on its order)
   const int ntile = (d + kWave - 1) / kWave;
-  double carry = 0.0;
+  double carry = 0.0, runmax = 0.0;
   double vnext = 0.0;
   {
     const int t0 = (ntile - 1) * kWave;
@@ -651,20 +721,6 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     const double total = shfl_f64(v, 0);
     if (tt != ntile - 1) v = v + carry;
     carry = (tt == ntile - 1) ? total : total + carry;
-    if (l < len) S[t0 + l] = v;
-  }
-  fence_wave_local();
-  // suffix maximum (exact): S non-increasing
-  double runmax = 0.0;
-  {
-    const int t0 = (ntile - 1) * kWave;
-    vnext = t0 + l < d ? S[t0 + l] : 0.0;
-  }
-  for (int tt = ntile - 1; tt >= 0; --tt) {
-    const int t0 = tt * kWave;
-    const int len = d - t0 < kWave ? d - t0 : kWave;
-    double v = vnext;
-    if (tt > 0) vnext = S[t0 - kWave + l];
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
@@ -735,20 +791,21 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       }
       if (!__any(any)) break;
     }
+    int32_t tgt[R], oth[R];
+    double c[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (ib + r * kWave >= d - 1) break;  // uniform
       const int sl = ib + r * kWave + l;
-      int32_t tgt = 0, oth = 0;
-      double c = 0.0;
+      tgt[r] = oth[r] = 0;
+      c[r] = 0.0;
       if (ins[r]) {
         const int32_t ua = su[sl], ub = su[lo[r]];
-        c = (Sp1[r] * sw[sl]) / Dk;
-        tgt = ua < ub ? ua : ub;
-        oth = ua < ub ? ub : ua;
+        c[r] = (Sp1[r] * sw[sl]) / Dk;
+        tgt[r] = ua < ub ? ua : ub;
+        oth[r] = ua < ub ? ub : ua;
       }
-      if (!insert_records(a, wk, ins[r], tgt, oth, k, c, deadline)) return false;
     }
+    if (!insert_records<R>(a, wk, ins, tgt, oth, k, c, deadline)) return false;
   }
   // 5. column k of F
   int64_t fbase;
@@ -764,12 +821,21 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     a.colstart[k] = fbase;
     a.colcnt[k] = d;
   }
-  // 6. publish, then delete the pivot's edges
+  // 6. publish, then delete the pivot's edges (four chunks of the column
+  // per round trip)
   Sync::release();
-  for (int ib = 0; ib < d; ib += kWave) {
-    const int i = ib + l;
-    const bool valid = i < d;
-    if (!decrement<Sync>(a, valid, valid ? mu[i] : 0, valid ? mm[i] : 0)) return false;
+  for (int ib = 0; ib < d; ib += 4 * kWave) {
+    bool valid[4];
+    int32_t uu[4];
+    int mmv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ib + q * kWave + l;
+      valid[q] = i < d;
+      uu[q] = valid[q] ? mu[i] : 0;
+      mmv[q] = valid[q] ? mm[i] : 0;
+    }
+    if (!decrement_batch<Sync, 4>(a, valid, uu, mmv)) return false;
   }
   return true;
 }
