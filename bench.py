@@ -33,6 +33,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "setup+solve s to 1e-6 rel. residual; factor nnz/s; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the apply measured with rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE), scaled by the same counters on a copy of known size; valid only
+# for the kernel sources it was taken from
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ready_traffic_grid3d_128.md")
+SWEEP_SOURCES = ["ready.hip", "internal.hpp", "device.hpp"]
+
+
+def sweep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2505_02977_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per apply from the committed counter summary, if it was taken
+    on this workload from the current sweep sources; else None."""
+    import re
+    if workload != "grid3d_128" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    m1 = re.search(r"sweep-sources-sha256:\s*([0-9a-f]{64})", text)
+    m2 = re.search(r"hbm-bytes-per-apply:\s*([0-9]+)", text)
+    if not (m1 and m2) or m1.group(1) != sweep_source_hash():
+        return None
+    return int(m2.group(1))
 
 
 def log(*a):
@@ -58,7 +86,7 @@ def apply_bytes(n_off, N, elem=8):
     return 2 * n_off * (4 + 2 * elem) + N * (8 + 4 + 8 + elem) + N * (8 + elem + elem + elem + 8 + 4)
 
 
-def roofline(info, apply_ms, n_applies, ms_elim, elem):
+def roofline(info, apply_ms, n_applies, ms_elim, elem, workload):
     """The dominant unit of a step (elimination or applies, by time) against
     the HBM peak."""
     N, n_off = info["n"], info["nnz_off"]
@@ -70,8 +98,9 @@ def roofline(info, apply_ms, n_applies, ms_elim, elem):
         unit, nbytes, ms = ("preconditioner apply (k_ready forward and backward sweeps, one "
                             "launch each)"), ab, apply_ms
     achieved = nbytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(workload) if unit.startswith("preconditioner") else None
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": unit,
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": unit,
             "algorithmic_bytes": int(nbytes), "avg_ms": round(ms, 4)}
 
 
@@ -90,6 +119,7 @@ def run_system(args, W, desc, precision, nrhs):
 
     def step(timing):
         f = parac.parac_factor(dA, perm=W.perm, seed=W.seed, keep_fp32=keep32)
+        log("  factor: %.1f ms" % f.info()["ms_total"])
         sts = parac.parac_pcg(dA, f, b, x, rtol=args.rtol, precision=precision, timing=timing)
         info = f.info()
         del f
@@ -122,7 +152,7 @@ def run_system(args, W, desc, precision, nrhs):
                               for s in stss]))
     N, n_off = info["n"], info["nnz_off"]
     elem = 4 if precision == parac.PREC_MIXED else 8
-    rl = roofline(info, ms_apply, applies, ms_elim, elem)
+    rl = roofline(info, ms_apply, applies, ms_elim, elem, args.workload)
     if nrhs > 1:
         rl["note"] = ("block apply: algorithmic bytes counted as for one column (factor read once), "
                       "the %d-column vector traffic comes on top" % nrhs)
@@ -262,7 +292,20 @@ def main():
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a copy of 2^27 doubles five times (read 1 GiB, write 1 GiB per "
+                         "launch): the reference for scaling HBM counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": x.numel() * 8,
+                          "calibrate_copy_bytes_written": y.numel() * 8, "launches": 5}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the single-system factorisation does not shard "
               "(the design notes say how it would); run with --gpus 1", file=sys.stderr)

@@ -135,9 +135,11 @@ parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
  *   precision  PARAC_PREC_FP64, or PARAC_PREC_MIXED (needs keep_fp32)
  * The forward solve F y = P r and the backward solve F^T x = D^+ y follow
  * the elimination levels (a row depends only on rows of earlier levels).
- * One column: two sweeps, each a single launch in which every row starts as
- * soon as the rows it reads are solved.  nrhs > 1: the columns are solved
- * together in chunks of 64 (factor read once per chunk), level by level.
+ * Two sweeps, each a single launch in which every row starts as soon as the
+ * rows it reads are solved; with nrhs > 1, chunks of up to 64 columns run as
+ * one sweep pair per column in the same two launches (or level by level,
+ * the factor read once per chunk, when a level-synchronous block shape is
+ * fixed, see parac_block_shape_set).
  * Every column equals, bit for bit, the apply of that column alone.
  * The call returns after the result is complete.  Errors: EINVAL, ETIMEOUT
  * (a sweep's watchdog expired; the factor stays usable). */
@@ -146,11 +148,13 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z,
 
 /* Launch shape of the block apply for chunks of `cols` columns (2..64) in
  * one precision.  Results do not depend on it, only speed.
- *   cpl        columns per lane: 1, 2 or 4
- *   tail_rows  levels at most this wide, and all levels after them, are
- *              solved by a single workgroup (the rest one launch per level)
- * Unless set, the first block apply of a factor times the candidate shapes
- * on its own input and keeps the fastest. */
+ *   cpl        0: one dependency-driven sweep pair per column, all columns
+ *              in the same two launches (the default);
+ *              1, 2 or 4: level-synchronous block launches with that many
+ *              columns per lane (the factor read once for all columns)
+ *   tail_rows  level-synchronous shapes: levels at most this wide, and all
+ *              levels after them, are solved by a single workgroup (the rest
+ *              one launch per level) */
 typedef struct {
   int32_t cpl;
   int64_t tail_rows;

@@ -722,10 +722,67 @@ static void ensure_bwork(parac_factor_t f, int prec, int nc) {
   f->bytes += 2 * (int64_t)(m * el);
 }
 
+// column sweeps: every column's work vectors and chunk sums pending, its
+// counters clear (the state each sweep pair starts from and leaves)
+static void reset_cwork(parac_factor_t f, int prec, hipStream_t s) {
+  const int k = prec_slot(prec);
+  const int64_t nc = f->ccols[k];
+  if (nc == 0) return;
+  const int64_t m = std::max<int64_t>(f->ntot, 1) * nc, c = std::max<int64_t>(f->ncs, 1) * nc;
+  if (k) {
+    for (void *p : {f->cy[k], f->cx[k]}) chk(launch_fill_u32((uint32_t *)p, kPending32, m, s), "fill");
+    chk(launch_fill_u32((uint32_t *)f->ccs[k], kPending32, c, s), "fill");
+  } else {
+    for (void *p : {f->cy[k], f->cx[k]}) chk(launch_fill_u64((uint64_t *)p, kPending64, m, s), "fill");
+    chk(launch_fill_u64((uint64_t *)f->ccs[k], kPending64, c, s), "fill");
+  }
+  chk(hipMemsetAsync(f->cctr[k], 0, 2 * nc * sizeof(int32_t), s), "memset");
+}
+
+static void ensure_cwork(parac_factor_t f, int prec, int nc, hipStream_t s) {
+  const int k = prec_slot(prec);
+  if (f->ccols[k] >= nc) return;
+  const size_t el = k ? 4 : 8;
+  const int64_t m0 = std::max<int64_t>(f->ntot, 1), c0 = std::max<int64_t>(f->ncs, 1);
+  for (void **pp : {&f->cy[k], &f->cx[k], &f->ccs[k], (void **)&f->cctr[k]}) {
+    if (!*pp) continue;
+    f->owned.erase(std::remove(f->owned.begin(), f->owned.end(), *pp), f->owned.end());
+    (void)hipFree(*pp);
+    *pp = nullptr;
+  }
+  f->bytes -= f->ccols[k] * (int64_t)((2 * m0 + c0) * el + 2 * sizeof(int32_t));
+  f->ccols[k] = 0;
+  chk(hipMalloc(&f->cy[k], (size_t)(m0 * nc) * el), "column work vector");
+  f->owned.push_back(f->cy[k]);
+  chk(hipMalloc(&f->cx[k], (size_t)(m0 * nc) * el), "column work vector");
+  f->owned.push_back(f->cx[k]);
+  chk(hipMalloc(&f->ccs[k], (size_t)(c0 * nc) * el), "column chunk sums");
+  f->owned.push_back(f->ccs[k]);
+  chk(hipMalloc((void **)&f->cctr[k], (size_t)(2 * nc) * sizeof(int32_t)), "column counters");
+  f->owned.push_back(f->cctr[k]);
+  f->ccols[k] = nc;
+  f->bytes += nc * (int64_t)((2 * m0 + c0) * el + 2 * sizeof(int32_t));
+  reset_cwork(f, prec, s);
+}
+
+struct Batch;
+static void build_cols(Batch &bt, parac_factor_t f, int nc, const double *r, int64_t ldr,
+                       double *z, int64_t ldz, int prec, const int *skip, int skip_stride,
+                       hipStream_t s);
+static void apply_cols(parac_factor_t f, int nc, const double *r, int64_t ldr, double *z,
+                       int64_t ldz, int prec, hipStream_t s);
+
+// a block of nc columns: with cpl = 0 one dependency-driven sweep pair per
+// column, all columns in the same two launches; else level-synchronous block
+// launches of that shape (the factor read once for all columns)
 static void apply_block(parac_factor_t f, const parac_block_shape &shp, int nc, const double *r,
                         int64_t ldr, double *z, int64_t ldz, int prec, const int *skip,
                         hipStream_t s) {
   if (f->n == 0) return;
+  if (shp.cpl == 0) {
+    apply_cols(f, nc, r, ldr, z, ldz, prec, s);
+    return;
+  }
   ensure_bwork(f, prec, nc);
   SolveArgs a = solve_args(f, skip);
   BlockShape sh{shp.cpl, tail_start(f, shp.tail_rows)};
@@ -735,43 +792,19 @@ static void apply_block(parac_factor_t f, const parac_block_shape &shp, int nc, 
       "block apply");
 }
 
-// the shape for (nc, prec): fixed by the caller, or timed on this input
-// (r -> z, both overwritten by the real apply afterwards)
-static parac_block_shape block_shape(parac_factor_t f, int nc, int prec, const double *r,
-                                     int64_t ldr, double *z, int64_t ldz, hipStream_t s) {
+// the shape for (nc, prec): fixed by the caller, else column sweeps
+static parac_block_shape block_shape(parac_factor_t f, int nc, int prec) {
   const auto key = std::make_pair(nc, prec_slot(prec));
   auto it = f->shapes.find(key);
   if (it != f->shapes.end()) return it->second;
-  parac_block_shape best{1, kTailDefault};
-  if (f->n == 0) return best;
-  Events ev;
-  ev.create();
-  auto time_one = [&](const parac_block_shape &c) {
-    chk(hipEventRecord(ev.e[0], s), "hipEventRecord");
-    apply_block(f, c, nc, r, ldr, z, ldz, prec, nullptr, s);
-    chk(hipEventRecord(ev.e[1], s), "hipEventRecord");
-    chk(hipEventSynchronize(ev.e[1]), "sync");
-    return ev.ms(0, 1);
-  };
-  (void)time_one(best);  // warm-up
-  double tbest = time_one(best);
-  for (int cpl : {2, 4}) {  // columns per lane at the default tail
-    if (cpl > nc) continue;
-    parac_block_shape c{cpl, kTailDefault};
-    const double t = time_one(c);
-    if (t < tbest) tbest = t, best = c;
-  }
-  for (int64_t rows : {(int64_t)64, (int64_t)1024}) {  // then the tail threshold
-    parac_block_shape c{best.cpl, rows};
-    const double t = time_one(c);
-    if (t < tbest) tbest = t, best = c;
-  }
-  f->shapes[key] = best;
-  return best;
+  // column sweeps unless the caller fixed a level-synchronous shape
+  const parac_block_shape sweeps{0, kTailDefault};
+  f->shapes[key] = sweeps;
+  return sweeps;
 }
 
 static bool shape_ok(const parac_block_shape &c) {
-  return (c.cpl == 1 || c.cpl == 2 || c.cpl == 4) && c.tail_rows >= 0;
+  return (c.cpl == 0 || c.cpl == 1 || c.cpl == 2 || c.cpl == 4) && c.tail_rows >= 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -856,6 +889,7 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     fs[k] = f;
     ensure_work(f, prec, s);
     as[k].a = solve_args(f, ps[k].ist + 1);
+    as[k].ldr = as[k].ldz = 1;
     as[k].r = ps[k].r;
     as[k].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
     as[k].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
@@ -883,6 +917,7 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hi
   ensure_work(f, prec, s);
   std::vector<ApplySlot> as(1);
   as[0].a = solve_args(f, f->zero);
+  as[0].ldr = as[0].ldz = 1;
   as[0].r = r;
   as[0].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
   as[0].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
@@ -895,6 +930,49 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hi
   chk(slots_apply(bt.B, prec, s), "apply");
   chk(hipStreamSynchronize(s), "sync");
   check_sweeps(f, prec, s);
+}
+
+// the column sweeps of a block: column j of r (stride ldr) into column j of
+// z, each a slot of its own over the same factor; skip (optional) gives
+// column j's done flag at skip + j * skip_stride
+static void build_cols(Batch &bt, parac_factor_t f, int nc, const double *r, int64_t ldr,
+                       double *z, int64_t ldz, int prec, const int *skip, int skip_stride,
+                       hipStream_t s) {
+  ensure_cwork(f, prec, nc, s);
+  const int k = prec_slot(prec);
+  const size_t el = k ? 4 : 8;
+  const int64_t m = std::max<int64_t>(f->ntot, 1), c = std::max<int64_t>(f->ncs, 1);
+  std::vector<ApplySlot> as(nc);
+  for (int j = 0; j < nc; ++j) {
+    as[j].a = solve_args(f, skip ? skip + (int64_t)j * skip_stride : f->zero);
+    as[j].ldr = ldr;
+    as[j].ldz = ldz;
+    as[j].r = r + j;
+    as[j].y = (char *)f->cy[k] + (size_t)(j * m) * el;
+    as[j].x = (char *)f->cx[k] + (size_t)(j * m) * el;
+    as[j].cs = (char *)f->ccs[k] + (size_t)(j * c) * el;
+    as[j].ctr = f->cctr[k] + 2 * j;
+    as[j].z = z + j;
+  }
+  build_apply_tables(bt, as, std::vector<parac_factor_t>(nc, f), s);
+  bt.B.nslots = nc;
+}
+
+static void check_col_sweeps(parac_factor_t f, int prec, hipStream_t s) {
+  if (read1(f->serr, s) == 0) return;
+  reset_cwork(f, prec, s);
+  chk(hipMemsetAsync(f->serr, 0, sizeof(int), s), "memset");
+  chk(hipStreamSynchronize(s), "sync");
+  throw Err{PARAC_ETIMEOUT, "triangular sweep watchdog expired"};
+}
+
+static void apply_cols(parac_factor_t f, int nc, const double *r, int64_t ldr, double *z,
+                       int64_t ldz, int prec, hipStream_t s) {
+  Batch bt;
+  build_cols(bt, f, nc, r, ldr, z, ldz, prec, nullptr, 0, s);
+  chk(slots_apply(bt.B, prec, s), "column sweeps");
+  chk(hipStreamSynchronize(s), "sync");
+  check_col_sweeps(f, prec, s);
 }
 
 // one system as a batch of one: the same launches, hence the same bits, as
@@ -1050,10 +1128,21 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
     chk(bpcg_launch_init(n, nc, o.rtol, b + c0, nrhs, x + c0, nrhs, r, p, partial, bst, bist, gfl,
                          s),
         "bpcg_init");
-    const parac_block_shape shp = block_shape(f, nc, o.precision, r, nc, z, nc, s);
+    const parac_block_shape shp = block_shape(f, nc, o.precision);
+    // column sweeps: one batch for the whole solve, a converged column's
+    // sweeps skipped through its done flag
+    Batch cols;
+    if (shp.cpl == 0 && n > 0) build_cols(cols, f, nc, r, nc, z, nc, o.precision, bist + 1, 4, s);
+    auto apply = [&]() {
+      if (shp.cpl == 0) {
+        if (n > 0) chk(slots_apply(cols.B, o.precision, s), "column sweeps");
+      } else {
+        apply_block(f, shp, nc, r, nc, z, nc, o.precision, gfl + 1, s);
+      }
+    };
     int applies = 0;
     mark(false);
-    apply_block(f, shp, nc, r, nc, z, nc, o.precision, gfl + 1, s);
+    apply();
     mark(false);
     ++applies;
     chk(bpcg_launch_rz(n, nc, r, z, p, partial, bst, bist, gfl, 1, s), "bpcg_rz");
@@ -1068,7 +1157,7 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
                              bist, gfl, s),
             "bpcg_step");
         mark(false);
-        apply_block(f, shp, nc, r, nc, z, nc, o.precision, gfl + 1, s);
+        apply();
         mark(false);
         ++applies;
         chk(bpcg_launch_rz(n, nc, r, z, p, partial, bst, bist, gfl, 0, s), "bpcg_rz");
@@ -1082,6 +1171,7 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
                              partial, bst, bist, gfl, s),
         "bpcg_true_res");
     mark(true);  // last: end
+    if (shp.cpl == 0 && n > 0) check_col_sweeps(f, o.precision, s);
     std::vector<double> hst(8 * nc);
     std::vector<int> hist(4 * nc);
     chk(hipMemcpyAsync(hst.data(), bst, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s),
@@ -1532,7 +1622,7 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z, int64_t n
     } else {
       for (int64_t c0 = 0; c0 < nrhs; c0 += kBlockCols) {
         const int nc = (int)std::min<int64_t>(kBlockCols, nrhs - c0);
-        const parac_block_shape shp = block_shape(f, nc, precision, r + c0, nrhs, z + c0, nrhs, s);
+        const parac_block_shape shp = block_shape(f, nc, precision);
         apply_block(f, shp, nc, r + c0, nrhs, z + c0, nrhs, precision, nullptr, s);
       }
     }

@@ -257,6 +257,7 @@ struct PcgSlot {
 };
 struct ApplySlot {
   SolveArgs a;  // a.skip points at the system's done flag
+  int64_t ldr, ldz;  // element strides of r and z (1, or the columns of a block)
   const double *r;
   void *y, *x;  // position-space work vectors (precision of the apply), all pending
   void *cs;     // chunk sums of long rows (precision of the apply), all pending
@@ -316,8 +317,13 @@ struct parac_factor_s {
   // solve work vectors (position space) and chunk sums per precision
   void *wy64 = nullptr, *wx64 = nullptr, *wy32 = nullptr, *wx32 = nullptr;
   void *cs64 = nullptr, *cs32 = nullptr;
+  // column sweeps of a block apply, per precision: work vectors and chunk
+  // sums of ccols columns (column-major), ticket counters (2 per column)
+  void *cy[2] = {nullptr, nullptr}, *cx[2] = {nullptr, nullptr}, *ccs[2] = {nullptr, nullptr};
+  int32_t *cctr[2] = {nullptr, nullptr};
+  int64_t ccols[2] = {0, 0};
   // block work vectors (ntot x bcols) per precision, launch shape per
-  // (columns, precision): set by the caller or picked by timing
+  // (columns, precision): set by the caller (else column sweeps)
   void *bwy[2] = {nullptr, nullptr}, *bwx[2] = {nullptr, nullptr};
   int64_t bcols[2] = {0, 0};
   std::map<std::pair<int, int>, parac_block_shape> shapes;

@@ -262,7 +262,7 @@ struct Sweep {
     if constexpr (BWD) {
       return FactorVals<T>::dinv(q.a)[pos] * ((const T *)q.y)[pos];
     } else {
-      return (T)q.r[q.a.src[pos]];
+      return (T)q.r[(int64_t)q.a.src[pos] * q.ldr];
     }
   }
   // publish row pos; forward resets x[pos], backward resets y[pos] and
@@ -271,7 +271,7 @@ struct Sweep {
     publish(out + pos, v);
     if constexpr (BWD) {
       reset((T *)q.y + pos);
-      q.z[q.a.src[pos]] = (double)v;
+      q.z[(int64_t)q.a.src[pos] * q.ldz] = (double)v;
     } else {
       reset((T *)q.x + pos);
     }

@@ -192,8 +192,9 @@ def parac_apply(f: Factor, r, z, precision=PREC_FP64, stream=None):
 
 
 def parac_block_shape_set(f: Factor, cols, precision=PREC_FP64, cpl=None, tail_rows=1024):
-    """Fix the block-apply shape for chunks of `cols` columns (cpl=None
-    forgets it, so the next block apply times the candidates again)."""
+    """Fix the block-apply shape for chunks of `cols` columns: cpl 0 = column
+    sweeps, 1/2/4 = level-synchronous launches (cpl=None forgets it, back to
+    column sweeps)."""
     sh = None if cpl is None else C.byref(parac_block_shape(cpl, tail_rows))
     _raise(lib().parac_block_shape_set(f.h, cols, precision, sh))
 

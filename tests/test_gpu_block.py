@@ -39,7 +39,8 @@ def setup_case(kind, nrhs):
     return A, perm, seed, np.ascontiguousarray(B), ex is not None
 
 
-SHAPES = [(c, t) for c in (1, 2, 4) for t in (0, 64, 1024, 1 << 40)]
+# cpl 0: one dependency-driven sweep pair per column; else level-synchronous
+SHAPES = [(0, 256)] + [(c, t) for c in (1, 2, 4) for t in (0, 64, 1024, 1 << 40)]
 
 
 @pytest.mark.parametrize("kind", ["grid", "sddm"])
@@ -75,10 +76,11 @@ def test_block_apply_tuned_shape(orc, nrhs):
     got = z.cpu().numpy()
     for j in range(nrhs):
         assert same_bits(got[:, j], orc.apply(ref, B[:, j].copy())), j
-    # chunks of at most 64 columns, each with a shape fixed by the timing
+    # chunks of at most 64 columns, each solved by column sweeps unless a
+    # level-synchronous shape is fixed
     for cols in sorted({min(64, nrhs - c0) for c0 in range(0, nrhs, 64)}):
         sh = parac.parac_block_shape_get(f, cols)
-        assert sh["cpl"] in (1, 2, 4) and sh["tail_rows"] >= 0
+        assert sh["cpl"] == 0 and sh["tail_rows"] >= 0
     # the single-vector path agrees as well
     z1 = torch.empty(A.n, dtype=torch.float64, device="cuda")
     parac.parac_apply(f, r[:, 0].contiguous(), z1)
@@ -116,6 +118,12 @@ def test_block_pcg_fp64_per_column(orc, kind):
         if not sddm:
             x, xr = x - x.mean(), xr - xr.mean()
         assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr), j
+    # the level-synchronous block apply gives the same bits
+    parac.parac_block_shape_set(f, nrhs, 0, cpl=2, tail_rows=64)
+    x2 = torch.full_like(bt, np.nan)
+    sts2 = parac.parac_pcg(dA, f, bt, x2, rtol=1e-6)
+    assert [s["iterations"] for s in sts2] == [s["iterations"] for s in sts]
+    assert same_bits(x2.cpu().numpy(), X)
 
 
 def test_block_pcg_mixed_and_chunks(orc):
