@@ -214,16 +214,17 @@ __device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool val
 #pragma unroll
   for (int u = 0; u < 16; ++u) v[u] = in[u] ? load_bits(vec + ci[u]) : (typename B::U)0;
   wait_ready<T, 16, DESC>(vec, ci, in, v, w);
-  // the lane's own products, folded from its first; a lane without entries
-  // passes the running sum on
-  auto fold = [&](T t, bool first) {
+  // the lane's own products, folded from its first.  An absent entry
+  // contributes -0.0, which leaves every sum unchanged (x + (-0.0) = x
+  // exactly, for every x), so the fold is a plain chain of additions; a lane
+  // without entries passes the running sum on.
+  T p[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      if (in[u]) {
-        const T p = f[u] * B::val(v[u]);
-        t = (first && u == 0) ? p : t + p;
-      }
-    }
+  for (int u = 0; u < 16; ++u) p[u] = in[u] ? f[u] * B::val(v[u]) : (T)-0.0;
+  auto fold = [&](T t, bool first) {
+    t = first ? p[0] : t + p[0];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) t = t + p[u];
     return t;
   };
   if constexpr (G == 1) {
