@@ -145,7 +145,7 @@ struct Watch {
   }
 };
 
-// Wait until every lane's entries v[u] (those with in[u]) are solved.  The
+// Wait until every lane's entries v[u], u < cnt, are solved.  The
 // wave polls one address at a time: of its pending entries the one solved
 // last in sweep order (positions follow the levels: the highest position
 // forward, DESC: the lowest backward), then reloads the others, which are
@@ -153,20 +153,20 @@ struct Watch {
 // memory system to the loads and stores of the rows being solved.
 template <typename T, int M, bool DESC>
 __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
-                                           const bool (&in)[M], typename Bits<T>::U (&v)[M],
+                                           int cnt, typename Bits<T>::U (&v)[M],
                                            Watch &w) {
   using B = Bits<T>;
   auto reload = [&]() {
 #pragma unroll
     for (int u = 0; u < M; ++u)
-      if (in[u] && v[u] == B::kPending) v[u] = load_bits(vec + ci[u]);
+      if (u < cnt && v[u] == B::kPending) v[u] = load_bits(vec + ci[u]);
   };
   for (;;) {
     int key = INT32_MIN;
 #pragma unroll
     for (int u = 0; u < M; ++u) {
       const int k = DESC ? -ci[u] : ci[u];
-      if (in[u] && v[u] == B::kPending && k > key) key = k;
+      if (u < cnt && v[u] == B::kPending && k > key) key = k;
     }
     if (!__ballot(key != INT32_MIN)) return;
 #pragma unroll
@@ -203,24 +203,25 @@ __device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool val
   const int64_t a = b + 16 * (int64_t)q;
   int32_t ci[16];
   T f[16];
-  bool in[16];
+  // the lane's entries are a prefix of its 16 slots
+  const int64_t left = valid ? e1 - a : 0;
+  const int cnt = left <= 0 ? 0 : (left < 16 ? (int)left : 16);
   typename B::U v[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    in[u] = valid && a + u < e1;
-    ci[u] = in[u] ? idx[a + u] : 0;
-    f[u] = in[u] ? fv[a + u] : (T)0;
+    ci[u] = u < cnt ? idx[a + u] : 0;
+    f[u] = u < cnt ? fv[a + u] : (T)0;
   }
 #pragma unroll
-  for (int u = 0; u < 16; ++u) v[u] = in[u] ? load_bits(vec + ci[u]) : (typename B::U)0;
-  wait_ready<T, 16, DESC>(vec, ci, in, v, w);
+  for (int u = 0; u < 16; ++u) v[u] = u < cnt ? load_bits(vec + ci[u]) : (typename B::U)0;
+  wait_ready<T, 16, DESC>(vec, ci, cnt, v, w);
   // the lane's own products, folded from its first.  An absent entry
   // contributes -0.0, which leaves every sum unchanged (x + (-0.0) = x
   // exactly, for every x), so the fold is a plain chain of additions; a lane
   // without entries passes the running sum on.
   T p[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) p[u] = in[u] ? f[u] * B::val(v[u]) : (T)-0.0;
+  for (int u = 0; u < 16; ++u) p[u] = u < cnt ? f[u] * B::val(v[u]) : (T)-0.0;
   auto fold = [&](T t, bool first) {
     t = first ? p[0] : t + p[0];
 #pragma unroll
@@ -357,10 +358,10 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
       for (int base = 0; base < nch; base += kWave) {
         const int m = nch - base < kWave ? nch - base : kWave;
         int32_t ci[1] = {u.w + base + l};
-        bool in[1] = {l < m};
-        typename Bits<T>::U v[1] = {in[0] ? load_bits(cs + ci[0]) : (typename Bits<T>::U)0};
-        wait_ready<T, 1, false>(cs, ci, in, v, w);
-        if (in[0]) reset(cs + ci[0]);
+        const int cnt = l < m ? 1 : 0;
+        typename Bits<T>::U v[1] = {cnt ? load_bits(cs + ci[0]) : (typename Bits<T>::U)0};
+        wait_ready<T, 1, false>(cs, ci, cnt, v, w);
+        if (cnt) reset(cs + ci[0]);
         const T c = Bits<T>::val(v[0]);
         for (int k = 0; k < m; ++k) acc = acc - readlane_t(c, k);
       }
