@@ -885,7 +885,7 @@ __device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
   return t;
 }
 
-__global__ __launch_bounds__(256, 3) void k_eliminate(ElimArgs a) {
+__global__ __launch_bounds__(256, 2) void k_eliminate(ElimArgs a) {
   __shared__ int hist[4][256];          // radix-sort histogram of each wave
   __shared__ double coarse[4][kCoarse];  // coarse suffix sums of each wave
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
