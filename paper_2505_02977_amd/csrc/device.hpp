@@ -194,6 +194,7 @@ static __device__ uint64_t g_radix_sink[2];
 template <typename K, typename V>
 __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *shifts, int npass,
                                 int *h) {
+  constexpr int kGroup = 8;  // chunks of 64 loaded together
   static_assert(sizeof(K) <= 8 && sizeof(V) <= 8, "sink holds 8-byte values");
   if (n <= 0) return true;
   const int l = lane();
@@ -208,11 +209,17 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
     V *vd = in_a ? vb : va;
     for (int t = l; t < 256; t += kWave) h[t] = 0;
     fence_wave_local();
-#pragma unroll 4
-    for (int base = 0; base < n; base += kWave) {
-      const int i = base + l;
-      const K k = ks[i < n ? i : n - 1];
-      if (i < n) atomicAdd(&h[(int)(((uint64_t)k >> sh) & 255)], 1);
+    // histogram, eight chunks of loads in flight
+    for (int base = 0; base < n; base += kGroup * kWave) {
+      K kk[kGroup];
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
+        const int i = base + q * kWave + l;
+        kk[q] = ks[i < n ? i : n - 1];
+      }
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q)
+        if (base + q * kWave + l < n) atomicAdd(&h[(int)(((uint64_t)kk[q] >> sh) & 255)], 1);
     }
     fence_wave_local();
     // exclusive scan of the 256 buckets, four per lane
@@ -231,34 +238,44 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
     h[4 * l + 2] = ex + c0 + c1;
     h[4 * l + 3] = ex + c0 + c1 + c2;
     fence_wave_local();
-    // stable scatter, 64 elements at a time in index order (the next
-    // chunk's elements are loaded while the current one is placed)
-    K knext = ks[l < n ? l : n - 1];
-    V vnext = vs[l < n ? l : n - 1];
-    for (int base = 0; base < n; base += kWave) {
-      const int i = base + l;
-      const bool valid = i < n;
-      const K k = knext;
-      const V v = vnext;
-      const int inext = i + kWave < n ? i + kWave : n - 1;
-      knext = ks[inext];
-      vnext = vs[inext];
-      const int d = (int)(((uint64_t)k >> sh) & 255);
-      uint64_t peers = __ballot(valid);
+    // stable scatter, 64 elements at a time in index order; the loads of
+    // eight chunks are issued together, so waiting for them waits for the
+    // previous group's stores once per eight chunks (loads and stores share
+    // one counter)
+    for (int base = 0; base < n; base += kGroup * kWave) {
+      K kk[kGroup];
+      V vv[kGroup];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const uint64_t bm = __ballot(valid && ((d >> b) & 1));
-        peers &= ((d >> b) & 1) ? bm : ~bm;
+      for (int q = 0; q < kGroup; ++q) {
+        const int i = base + q * kWave + l;
+        const int ic = i < n ? i : n - 1;
+        kk[q] = ks[ic];
+        vv[q] = vs[ic];
       }
-      const int off = valid ? h[d] : 0;
-      fence_wave_local();
-      const int rank = __popcll(peers & lanemask_lt());
-      K *pk = valid ? kd + off + rank : sink_k;
-      V *pv = valid ? vd + off + rank : sink_v;
-      *pk = k;
-      *pv = v;
-      if (valid && rank == 0) h[d] = off + __popcll(peers);
-      fence_wave_local();
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
+        if (base + q * kWave >= n) break;  // uniform
+        const int i = base + q * kWave + l;
+        const bool valid = i < n;
+        const K k = kk[q];
+        const V v = vv[q];
+        const int d = (int)(((uint64_t)k >> sh) & 255);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const uint64_t bm = __ballot(valid && ((d >> b) & 1));
+          peers &= ((d >> b) & 1) ? bm : ~bm;
+        }
+        const int off = valid ? h[d] : 0;
+        fence_wave_local();
+        const int rank = __popcll(peers & lanemask_lt());
+        K *pk = valid ? kd + off + rank : sink_k;
+        V *pv = valid ? vd + off + rank : sink_v;
+        *pk = k;
+        *pv = v;
+        if (valid && rank == 0) h[d] = off + __popcll(peers);
+        fence_wave_local();
+      }
     }
     fence_wave_local();
     in_a = !in_a;
