@@ -258,7 +258,10 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   // persistent grid
   int maxwg = eliminate_max_workgroups();
   if (maxwg <= 0) throw Err{PARAC_EDEVICE, "occupancy query failed"};
-  int workers = (maxwg * 4) / kSubQueues * kSubQueues;
+  // one workgroup in kTeamShare is a team for the largest pivots (none when
+  // the graph is too small to have any)
+  const int nteam = ntot > 4 * kTeamMin ? maxwg / kTeamShare : 0;
+  int workers = ((maxwg - nteam) * 4) / kSubQueues * kSubQueues;
   // no more workers than a quarter of the pivots could keep busy
   workers = std::min<int64_t>(workers, std::max<int64_t>(kSubQueues, (ntot / 4) / kSubQueues * kSubQueues));
   if (opt.workers > 0) workers = std::min(workers, std::max(kSubQueues, opt.workers / kSubQueues * kSubQueues));
@@ -273,6 +276,11 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   int32_t *qdone = qhead + kSubQueues * kTailStride;
   int32_t *tqc = qdone + kSubQueues * kTailStride;  // tail head, tail, count
   int32_t *tq = tmp.alloc<int32_t>(ntot, "tail queue");
+  // team queue: every handed-off pivot takes a fresh slot, and each team
+  // holds at most one claimed slot beyond them
+  const int32_t bq_cap = (int32_t)(ntot + nteam + 1);
+  int32_t *bq = tmp.alloc<int32_t>(bq_cap, "team queue");
+  int32_t *bqc = tmp.alloc<int32_t>(2 * kTailStride, "team queue counters");
   int32_t *fill_cnt = tmp.alloc<int32_t>(ntot, "fill_cnt");
   Rec *inl = tmp.alloc<Rec>(ntot * kInline, "inline inbox");
   int32_t *ptab = tmp.alloc<int32_t>(ntot * (kPages - 1), "page table");
@@ -321,6 +329,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     chk(hipMemsetAsync(qtail, 0, (3 * kSubQueues * kTailStride + 3 * kTailStride) * sizeof(int32_t), s),
         "memset");
     chk(hipMemsetAsync(tq, 0xff, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
+    chk(hipMemsetAsync(bq, 0xff, (size_t)bq_cap * sizeof(int32_t), s), "memset");
+    chk(hipMemsetAsync(bqc, 0, 2 * kTailStride * sizeof(int32_t), s), "memset");
     chk(hipMemsetAsync(fill_cnt, 0, std::max<int64_t>(ntot, 1) * sizeof(int32_t), s), "memset");
     chk(hipMemsetAsync(ptab, 0xff, std::max<int64_t>(ntot * (kPages - 1), 1) * sizeof(int32_t), s),
         "memset");
@@ -383,7 +393,13 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     ea.tq_head = tqc;
     ea.tq_tail = tqc + kTailStride;
     ea.tq_count = tqc + 2 * kTailStride;
-    if (ntot > 0) chk(launch_eliminate(ea, wgs, s), "eliminate");
+    ea.bq = bq;
+    ea.bq_head = bqc;
+    ea.bq_tail = bqc + kTailStride;
+    ea.bq_cap = bq_cap;
+    ea.team_min = nteam > 0 ? kTeamMin : 0;
+    ea.team_wg0 = wgs;
+    if (ntot > 0) chk(launch_eliminate(ea, wgs + nteam, s), "eliminate");
     chk(hipEventRecord(ev.e[2], s), "event");
     int herr = 0;
     chk(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s), "read");

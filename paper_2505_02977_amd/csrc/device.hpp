@@ -180,47 +180,99 @@ __device__ __forceinline__ int bitonic_partner(int l, int p, int j, bool first) 
 
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (key, payload) pairs by one wave, ping-ponging
-// between two buffers: 8-bit digits at the given shifts, a 256-bucket
-// histogram in the wave's LDS slice h, in-wave ranks by matching digits with
-// ballots.  Returns true when the sorted data ends in the first buffer.
-// Every lane issues the same global loads and stores in every chunk (lanes
-// past the end read the last element and store to a sink), so the wait for
-// the next chunk's prefetched loads does not also wait for this chunk's
-// stores.
+// Stable LSD radix sort of (key, payload) pairs, 8-bit digits at the given
+// shifts, ping-ponging between two buffers.  A pass is a 256-bucket
+// histogram in LDS, an exclusive scan of it, and a stable scatter in index
+// order with in-wave ranks from ballots.  The histogram and the scatter work
+// on an index range, so that several waves can share a pass (each takes a
+// contiguous range, the scan orders the ranges).  Every lane issues the same
+// global loads and stores in every chunk (lanes past the end read the last
+// element of the range and store to a sink), so the wait for prefetched
+// loads does not also wait for stores of the same group.
 // ---------------------------------------------------------------------------
 static __device__ uint64_t g_radix_sink[2];
+constexpr int kRadixGroup = 8;  // chunks of 64 whose loads are issued together
 
+// h[digit] += count of the keys in [lo, hi) (h in LDS, owned by this wave)
+template <typename K>
+__device__ __forceinline__ void radix_count(const K *ks, int lo, int hi, int sh, int *h) {
+  const int l = lane();
+  for (int base = lo; base < hi; base += kRadixGroup * kWave) {
+    K kk[kRadixGroup];
+#pragma unroll
+    for (int q = 0; q < kRadixGroup; ++q) {
+      const int i = base + q * kWave + l;
+      kk[q] = ks[i < hi ? i : hi - 1];
+    }
+#pragma unroll
+    for (int q = 0; q < kRadixGroup; ++q)
+      if (base + q * kWave + l < hi) atomicAdd(&h[(int)(((uint64_t)kk[q] >> sh) & 255)], 1);
+  }
+}
+
+// stable scatter of [lo, hi) to the running bucket offsets h (LDS, owned by
+// this wave), 64 elements at a time in index order; the loads of eight
+// chunks are issued together, so waiting for them waits for the previous
+// group's stores once per eight chunks (loads and stores share one counter)
 template <typename K, typename V>
-__device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *shifts, int npass,
-                                int *h) {
-  constexpr int kGroup = 8;  // chunks of 64 loaded together
+__device__ __forceinline__ void radix_scatter(const K *ks, const V *vs, K *kd, V *vd, int lo,
+                                              int hi, int sh, int *h) {
   static_assert(sizeof(K) <= 8 && sizeof(V) <= 8, "sink holds 8-byte values");
-  if (n <= 0) return true;
   const int l = lane();
   K *const sink_k = (K *)&g_radix_sink[0];
   V *const sink_v = (V *)&g_radix_sink[1];
+  for (int base = lo; base < hi; base += kRadixGroup * kWave) {
+    K kk[kRadixGroup];
+    V vv[kRadixGroup];
+#pragma unroll
+    for (int q = 0; q < kRadixGroup; ++q) {
+      const int i = base + q * kWave + l;
+      const int ic = i < hi ? i : hi - 1;
+      kk[q] = ks[ic];
+      vv[q] = vs[ic];
+    }
+#pragma unroll
+    for (int q = 0; q < kRadixGroup; ++q) {
+      if (base + q * kWave >= hi) break;  // uniform
+      const int i = base + q * kWave + l;
+      const bool valid = i < hi;
+      const K k = kk[q];
+      const V v = vv[q];
+      const int d = (int)(((uint64_t)k >> sh) & 255);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bm = __ballot(valid && ((d >> b) & 1));
+        peers &= ((d >> b) & 1) ? bm : ~bm;
+      }
+      const int off = valid ? h[d] : 0;
+      fence_wave_local();
+      const int rank = __popcll(peers & lanemask_lt());
+      K *pk = valid ? kd + off + rank : sink_k;
+      V *pv = valid ? vd + off + rank : sink_v;
+      *pk = k;
+      *pv = v;
+      if (valid && rank == 0) h[d] = off + __popcll(peers);
+      fence_wave_local();
+    }
+  }
+}
+
+// the whole sort by one wave; returns true when the sorted data ends in the
+// first buffer
+template <typename K, typename V>
+__device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *shifts, int npass,
+                                int *h) {
+  if (n <= 0) return true;
+  const int l = lane();
   bool in_a = true;
   for (int pass = 0; pass < npass; ++pass) {
     const int sh = shifts[pass];
     K *ks = in_a ? ka : kb;
     V *vs = in_a ? va : vb;
-    K *kd = in_a ? kb : ka;
-    V *vd = in_a ? vb : va;
     for (int t = l; t < 256; t += kWave) h[t] = 0;
     fence_wave_local();
-    // histogram, eight chunks of loads in flight
-    for (int base = 0; base < n; base += kGroup * kWave) {
-      K kk[kGroup];
-#pragma unroll
-      for (int q = 0; q < kGroup; ++q) {
-        const int i = base + q * kWave + l;
-        kk[q] = ks[i < n ? i : n - 1];
-      }
-#pragma unroll
-      for (int q = 0; q < kGroup; ++q)
-        if (base + q * kWave + l < n) atomicAdd(&h[(int)(((uint64_t)kk[q] >> sh) & 255)], 1);
-    }
+    radix_count(ks, 0, n, sh, h);
     fence_wave_local();
     // exclusive scan of the 256 buckets, four per lane
     const int c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
@@ -238,45 +290,7 @@ __device__ bool wave_radix_sort(K *ka, V *va, K *kb, V *vb, int n, const int *sh
     h[4 * l + 2] = ex + c0 + c1;
     h[4 * l + 3] = ex + c0 + c1 + c2;
     fence_wave_local();
-    // stable scatter, 64 elements at a time in index order; the loads of
-    // eight chunks are issued together, so waiting for them waits for the
-    // previous group's stores once per eight chunks (loads and stores share
-    // one counter)
-    for (int base = 0; base < n; base += kGroup * kWave) {
-      K kk[kGroup];
-      V vv[kGroup];
-#pragma unroll
-      for (int q = 0; q < kGroup; ++q) {
-        const int i = base + q * kWave + l;
-        const int ic = i < n ? i : n - 1;
-        kk[q] = ks[ic];
-        vv[q] = vs[ic];
-      }
-#pragma unroll
-      for (int q = 0; q < kGroup; ++q) {
-        if (base + q * kWave >= n) break;  // uniform
-        const int i = base + q * kWave + l;
-        const bool valid = i < n;
-        const K k = kk[q];
-        const V v = vv[q];
-        const int d = (int)(((uint64_t)k >> sh) & 255);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const uint64_t bm = __ballot(valid && ((d >> b) & 1));
-          peers &= ((d >> b) & 1) ? bm : ~bm;
-        }
-        const int off = valid ? h[d] : 0;
-        fence_wave_local();
-        const int rank = __popcll(peers & lanemask_lt());
-        K *pk = valid ? kd + off + rank : sink_k;
-        V *pv = valid ? vd + off + rank : sink_v;
-        *pk = k;
-        *pv = v;
-        if (valid && rank == 0) h[d] = off + __popcll(peers);
-        fence_wave_local();
-      }
-    }
+    radix_scatter(ks, vs, in_a ? kb : ka, in_a ? vb : va, 0, n, sh, h);
     fence_wave_local();
     in_a = !in_a;
   }

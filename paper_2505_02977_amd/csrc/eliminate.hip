@@ -224,6 +224,7 @@ __device__ __forceinline__ bool alloc_column(const ElimArgs &a, Worker &wk, int 
 // workgroup on one CU: workgroup-scope fences suffice, and it has its own
 // queue.
 struct WideSync {
+  static constexpr bool kTeams = true;  // the largest pivots go to teams
   static __device__ __forceinline__ void release() { store_wait(); }
   static __device__ __forceinline__ void acquire() { compiler_fence(); }
   static __device__ __forceinline__ bool enqueue(const ElimArgs &a, int32_t u) {
@@ -236,6 +237,7 @@ struct WideSync {
   }
 };
 struct TailSync {
+  static constexpr bool kTeams = false;
   static __device__ __forceinline__ void release() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   }
@@ -515,6 +517,178 @@ __device__ __forceinline__ void rank_sort_wu(const double *mw, const int32_t *mu
   }
 }
 
+// Merge the runs of equal u whose first entry lies in [lo, hi) of the sorted
+// list [0, g): each run's weights are summed left to right in key order, and
+// the j-th run goes to position d0 + j.  Returns d0 + the number of runs.
+// Chunks of 64 sorted entries are held one per lane: runs inside a chunk are
+// folded in lockstep through shuffles, a run that reaches the end of a chunk
+// is carried (label cu, partial sum cacc, length cm) into the next one.  A
+// run that begins before lo belongs to the wave holding its beginning: it is
+// carried as a phantom and dropped; the last run may run on past hi.
+__device__ __forceinline__ int merge_runs(const uint64_t *keyS, const double *wS, int lo, int hi, int g, int d0,
+                          int32_t *mu, double *mw, int32_t *mm) {
+  const int l = lane();
+  int d = d0;
+  int32_t cu = -1;
+  bool phantom = false;
+  if (lo > 0 && lo < hi) {
+    cu = (int32_t)(keyS[lo - 1] >> 32);
+    phantom = true;
+  }
+  double cacc = 0.0;
+  int cm = 0;
+  auto emit_carry = [&]() {
+    if (!phantom) {
+      if (l == 0) {
+        mu[d] = cu;
+        mw[d] = cacc;
+        mm[d] = cm;
+      }
+      ++d;
+    }
+    cu = -1;
+    phantom = false;
+  };
+  uint64_t knext = lo + l < g ? keyS[lo + l] : ~0ull;
+  double wnext = lo + l < g ? wS[lo + l] : 0.0;
+  for (int ib = lo; ib < g; ib += kWave) {
+    if (ib >= hi && cu < 0) break;
+    const int i = ib + l;
+    const int n = g - ib < kWave ? g - ib : kWave;
+    const bool valid = i < g;
+    const int32_t u = valid ? (int32_t)(knext >> 32) : -1;
+    const double w = wnext;
+    if (i + kWave < g) {
+      knext = keyS[i + kWave];
+      wnext = wS[i + kWave];
+    }
+    // lanes continuing the carried run form a prefix [0, c)
+    int c = 0;
+    if (cu >= 0) {
+      const uint64_t cont = __ballot(valid && u == cu);
+      c = ~cont == 0 ? kWave : __builtin_ctzll(~cont);
+      if (!phantom)
+        for (int j = 0; j < c; ++j) cacc = cacc + shfl_f64(w, j);
+      cm += c;
+      if (c < n) emit_carry();
+      if (c == n) continue;  // the whole chunk continues the carried run
+    }
+    if (ib >= hi) break;  // runs that begin here belong to the next range
+    const int32_t uprev = shfl(u, l > 0 ? l - 1 : 0);
+    const bool head = valid && l >= c && (l == c || uprev != u);
+    double acc = head ? w : 0.0;
+    int m = head ? 1 : 0;
+    bool active = head;
+    for (int step = 1; step < kWave; ++step) {
+      const int sl = l + step < kWave ? l + step : kWave - 1;
+      const double ws = shfl_f64(w, sl);
+      const int32_t us = shfl(u, sl);
+      const bool cont2 = active && (l + step < n) && us == u;
+      if (cont2) {
+        acc = acc + ws;
+        ++m;
+      }
+      active = cont2;
+      if (!__any(active)) break;
+    }
+    const uint64_t hm = __ballot(head);
+    uint64_t em = hm;
+    if (hm && n == kWave && ib + kWave < g) {
+      const int hl = 63 - __clzll(hm);  // the chunk's last run reaches lane 63?
+      if (shfl(u, kWave - 1) == shfl(u, hl)) {
+        em &= ~(1ull << hl);
+        cu = shfl(u, hl);
+        cacc = shfl_f64(acc, hl);
+        cm = shfl(m, hl);
+      }
+    }
+    if ((em >> l) & 1) {
+      const int pos = d + __popcll(em & lanemask_lt());
+      mu[pos] = u;
+      mw[pos] = acc;
+      mm[pos] = m;
+    }
+    d += __popcll(em);
+  }
+  if (cu >= 0) emit_carry();
+  return d;
+}
+
+// Sampled edges of the slots [ib, ib + 4*64) of a pivot with d merged
+// neighbours in (w, u) order (weights sw, labels su, suffix sums S, D_k = S[0]).
+// The partner of slot s is the first m > s with S[m+1] <= t (S
+// non-increasing, S[d] = 0).  A coarse copy of S in LDS (coarse[j] =
+// S[j st + 1], j < nco) narrows the search to st entries, and the searches
+// of the four rounds of 64 slots run interleaved.
+constexpr int kSampleRounds = 4;
+__device__ __forceinline__ bool sample_rounds(const ElimArgs &a, Worker &wk, int32_t k, int d, int ib,
+                              const double *S, const double *sw, const int32_t *su, double Dk,
+                              const double *coarse, int st, int nco, uint64_t deadline) {
+  constexpr int R = kSampleRounds;
+  const int l = lane();
+  int lo[R], hi[R];
+  double t[R], Sp1[R];
+  bool ins[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int sl = ib + r * kWave + l;
+    ins[r] = sl < d - 1;
+    Sp1[r] = ins[r] ? S[sl + 1] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int sl = ib + r * kWave + l;
+    lo[r] = sl + 1;
+    hi[r] = d - 1;
+    if (!ins[r]) {
+      lo[r] = hi[r] = 0;
+      continue;
+    }
+    t[r] = draw_unit(a.seed, (uint32_t)k, (uint32_t)sl) * Sp1[r];
+    // coarse: smallest j with m_j >= lo and coarse[j] <= t (exists unless
+    // the answer lies beyond the last coarse point)
+    int jl = (lo[r] + st - 1) / st, jh = nco;
+    while (jl < jh) {
+      const int mid = (jl + jh) >> 1;
+      if (coarse[mid] <= t[r]) jh = mid;
+      else jl = mid + 1;
+    }
+    if (jl < nco) hi[r] = jl * st;
+    const int lo2 = (jl - 1) * st + 1;
+    if (jl > 0 && lo2 > lo[r]) lo[r] = lo2;
+  }
+  // fine search in global memory, the four rounds' loads overlapping
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (lo[r] < hi[r]) {
+        const int mid = (lo[r] + hi[r]) >> 1;
+        const double sn = mid + 1 < d ? S[mid + 1] : 0.0;
+        if (sn <= t[r]) hi[r] = mid;
+        else lo[r] = mid + 1;
+        any = true;
+      }
+    }
+    if (!__any(any)) break;
+  }
+  int32_t tgt[R], oth[R];
+  double c[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int sl = ib + r * kWave + l;
+    tgt[r] = oth[r] = 0;
+    c[r] = 0.0;
+    if (ins[r]) {
+      const int32_t ua = su[sl], ub = su[lo[r]];
+      c[r] = (Sp1[r] * sw[sl]) / Dk;
+      tgt[r] = ua < ub ? ua : ub;
+      oth[r] = ua < ub ? ub : ua;
+    }
+  }
+  return insert_records<R>(a, wk, ins, tgt, oth, k, c, deadline);
+}
+
 // ---------------------------------------------------------------------------
 // larger neighbourhoods: the same steps over wave-private scratch in HBM;
 // sorting by rank (keys are unique), suffix sums tile by tile
@@ -598,82 +772,8 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       return false;
     }
   }
-  // merge runs of equal u (left fold in key order).  Chunks of 64 sorted
-  // entries are held one per lane: runs inside a chunk are folded in
-  // lockstep through shuffles, a run that reaches the end of a chunk is
-  // carried (label cu, partial sum cacc, length cm) into the next one.
-  int d = 0;
-  int32_t cu = -1;
-  double cacc = 0.0;
-  int cm = 0;
-  auto emit_carry = [&]() {
-    if (l == 0) {
-      mu[d] = cu;
-      mw[d] = cacc;
-      mm[d] = cm;
-    }
-    ++d;
-    cu = -1;
-  };
-  uint64_t knext = l < g ? keyS[l] : ~0ull;
-  double wnext = l < g ? wS[l] : 0.0;
-  for (int ib = 0; ib < g; ib += kWave) {
-    const int i = ib + l;
-    const int n = g - ib < kWave ? g - ib : kWave;
-    const bool valid = i < g;
-    const int32_t u = valid ? (int32_t)(knext >> 32) : -1;
-    const double w = wnext;
-    if (i + kWave < g) {
-      knext = keyS[i + kWave];
-      wnext = wS[i + kWave];
-    }
-    // lanes continuing the carried run form a prefix [0, c)
-    int c = 0;
-    if (cu >= 0) {
-      const uint64_t cont = __ballot(valid && u == cu);
-      c = ~cont == 0 ? kWave : __builtin_ctzll(~cont);
-      for (int j = 0; j < c; ++j) cacc = cacc + shfl_f64(w, j);
-      cm += c;
-      if (c < n) emit_carry();
-      if (c == n) continue;  // the whole chunk continues the carried run
-    }
-    const int32_t uprev = shfl(u, l > 0 ? l - 1 : 0);
-    const bool head = valid && l >= c && (l == c || uprev != u);
-    double acc = head ? w : 0.0;
-    int m = head ? 1 : 0;
-    bool active = head;
-    for (int step = 1; step < kWave; ++step) {
-      const int sl = l + step < kWave ? l + step : kWave - 1;
-      const double ws = shfl_f64(w, sl);
-      const int32_t us = shfl(u, sl);
-      const bool cont2 = active && (l + step < n) && us == u;
-      if (cont2) {
-        acc = acc + ws;
-        ++m;
-      }
-      active = cont2;
-      if (!__any(active)) break;
-    }
-    const uint64_t hm = __ballot(head);
-    uint64_t em = hm;
-    if (hm && n == kWave && ib + kWave < g) {
-      const int hl = 63 - __clzll(hm);  // the chunk's last run reaches lane 63?
-      if (shfl(u, kWave - 1) == shfl(u, hl)) {
-        em &= ~(1ull << hl);
-        cu = shfl(u, hl);
-        cacc = shfl_f64(acc, hl);
-        cm = shfl(m, hl);
-      }
-    }
-    if ((em >> l) & 1) {
-      const int pos = d + __popcll(em & lanemask_lt());
-      mu[pos] = u;
-      mw[pos] = acc;
-      mm[pos] = m;
-    }
-    d += __popcll(em);
-  }
-  if (cu >= 0) emit_carry();
+  // merge runs of equal u
+  const int d = merge_runs(keyS, wS, 0, g, g, 0, mu, mw, mm);
   fence_wave_local();
   // 3. sampling order (w asc, u asc)
   if (d <= kRankMax) {
@@ -732,10 +832,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   }
   fence_wave_local();
   const double Dk = S[0];
-  // 4. sampled edges.  The partner of slot s is the first m > s with
-  // S[m+1] <= t (S non-increasing, S[d] = 0).  A coarse copy of S in the
-  // wave's LDS (every st-th entry) narrows the search to st entries, and the
-  // searches of four rounds of 64 slots run interleaved.
+  // 4. sampled edges
   const int st = (d + kCoarse - 1) / kCoarse;
   const int nco = (d + st - 1) / st;  // coarse points m_j = j st, j < nco
   for (int j = l; j < nco; j += kWave) {
@@ -743,70 +840,8 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     coarse[j] = m + 1 < d ? S[m + 1] : 0.0;
   }
   fence_wave_local();
-  constexpr int R = 4;
-  for (int ib = 0; ib < d - 1; ib += R * kWave) {
-    int lo[R], hi[R];
-    double t[R], Sp1[R];
-    bool ins[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int sl = ib + r * kWave + l;
-      ins[r] = sl < d - 1;
-      Sp1[r] = ins[r] ? S[sl + 1] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int sl = ib + r * kWave + l;
-      lo[r] = sl + 1;
-      hi[r] = d - 1;
-      if (!ins[r]) {
-        lo[r] = hi[r] = 0;
-        continue;
-      }
-      t[r] = draw_unit(a.seed, (uint32_t)k, (uint32_t)sl) * Sp1[r];
-      // coarse: smallest j with m_j >= lo and coarse[j] <= t (exists unless
-      // the answer lies beyond the last coarse point)
-      int jl = (lo[r] + st - 1) / st, jh = nco;
-      while (jl < jh) {
-        const int mid = (jl + jh) >> 1;
-        if (coarse[mid] <= t[r]) jh = mid;
-        else jl = mid + 1;
-      }
-      if (jl < nco) hi[r] = jl * st;
-      const int lo2 = (jl - 1) * st + 1;
-      if (jl > 0 && lo2 > lo[r]) lo[r] = lo2;
-    }
-    // fine search in global memory, the four rounds' loads overlapping
-    for (;;) {
-      bool any = false;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (lo[r] < hi[r]) {
-          const int mid = (lo[r] + hi[r]) >> 1;
-          const double sn = mid + 1 < d ? S[mid + 1] : 0.0;
-          if (sn <= t[r]) hi[r] = mid;
-          else lo[r] = mid + 1;
-          any = true;
-        }
-      }
-      if (!__any(any)) break;
-    }
-    int32_t tgt[R], oth[R];
-    double c[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int sl = ib + r * kWave + l;
-      tgt[r] = oth[r] = 0;
-      c[r] = 0.0;
-      if (ins[r]) {
-        const int32_t ua = su[sl], ub = su[lo[r]];
-        c[r] = (Sp1[r] * sw[sl]) / Dk;
-        tgt[r] = ua < ub ? ua : ub;
-        oth[r] = ua < ub ? ub : ua;
-      }
-    }
-    if (!insert_records<R>(a, wk, ins, tgt, oth, k, c, deadline)) return false;
-  }
+  for (int ib = 0; ib < d - 1; ib += kSampleRounds * kWave)
+    if (!sample_rounds(a, wk, k, d, ib, S, sw, su, Dk, coarse, st, nco, deadline)) return false;
   // 5. column k of F
   int64_t fbase;
   if (!alloc_column(a, wk, d, fbase)) return false;
@@ -840,9 +875,12 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   return true;
 }
 
+// the outcome of eliminate_pivot
+enum PivotOutcome { kPivotFailed = 0, kPivotDone = 1, kPivotHanded = 2 };
+
 template <class Sync>
-__device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
-                                int *h, double *coarse) {
+__device__ __forceinline__ int eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
+                               int *h, double *coarse) {
   const int64_t u0 = a.uptr[k];
   const int nU = (int)(a.uptr[k + 1] - u0);
   const int nF = ld_acq_relaxed(&a.fill_cnt[k]);
@@ -853,11 +891,19 @@ __device__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64
       a.colstart[k] = 0;
       a.colcnt[k] = 0;
     }
-    return true;
+    return kPivotDone;
+  }
+  if (Sync::kTeams && a.team_min > 0 && g > a.team_min) {
+    // to the team queue (its slots are never reused: no wrap)
+    if (lane() == 0) {
+      const int pos = fetch_add(a.bq_tail, 1);
+      __hip_atomic_exchange(&a.bq[pos], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return kPivotHanded;
   }
   const int levk = ld_acq_relaxed(&a.lev[k]);
-  if (g <= kWave) return small_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline);
-  return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h, coarse);
+  if (g <= kWave) return small_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline) ? kPivotDone : kPivotFailed;
+  return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h, coarse) ? kPivotDone : kPivotFailed;
 }
 
 // After a slot has delivered label k: read k's counter (agent scope).  Zero
@@ -885,11 +931,421 @@ __device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
   return t;
 }
 
+// ---------------------------------------------------------------------------
+// The largest neighbourhoods: the four waves of a workgroup on one pivot.
+// Most of the time of a power-law factorisation goes to a chain of pivots
+// with thousands of gathered entries, each of which depends on the one
+// before; a team shortens every link of that chain.  Each step keeps the
+// order of its arithmetic -- the same stable sorts, the same left folds of
+// runs, the same 64-wide tiles and carries of the suffix sums, the same
+// draws -- so the factor does not depend on which path eliminated a pivot.
+// A wave that claims such a pivot hands it to the team queue; teams are
+// workgroups of their own in the persistent grid.
+// ---------------------------------------------------------------------------
+constexpr int kTeamWaves = 4;
+constexpr int kTeamThreads = kTeamWaves * kWave;
+constexpr int kTeamCoarse = kTeamWaves * kCoarse;
+
+struct TeamShared {
+  int64_t sc_base;       // scratch of the pivot (in wave 0's region)
+  int64_t fbase;         // column k of F
+  int32_t k;             // the pivot; -1: leave
+  int fail;              // a wave failed (the error word is set)
+  int cnt[kTeamWaves];   // per-wave counts
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int j) {
+  return __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(v), j));
+}
+
+// wave w's share of [0, n): a quarter of the chunks of 64, in order
+__device__ __forceinline__ void team_range(int n, int w, int &lo, int &hi) {
+  const int nch = (n + kWave - 1) / kWave;
+  const int per = (nch + kTeamWaves - 1) / kTeamWaves;
+  lo = w * per * kWave < n ? w * per * kWave : n;
+  hi = (w + 1) * per * kWave < n ? (w + 1) * per * kWave : n;
+}
+
+// the stable LSD sort of wave_radix_sort by the team: wave w counts and
+// scatters its share, and bucket b of share w starts after every smaller
+// bucket and after bucket b of the shares before w.  The digits are the
+// bytes 0 .. npass-1 of the key, or with half > 0 the bytes 0 .. half-1 of
+// its low word and then of its high word.
+template <typename K, typename V>
+__device__ __forceinline__ bool team_radix_sort(K *ka, V *va, K *kb, V *vb, int n, int npass, int half,
+                                int (*hist)[256], int *wtot) {
+  const int t = threadIdx.x, l = lane(), w = t >> 6;
+  int lo, hi;
+  team_range(n, w, lo, hi);
+  bool in_a = true;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int sh = half > 0 && pass >= half ? 32 + 8 * (pass - half) : 8 * pass;
+    K *ks = in_a ? ka : kb;
+    V *vs = in_a ? va : vb;
+    for (int b = l; b < 256; b += kWave) hist[w][b] = 0;
+    fence_wave_local();
+    if (lo < hi) radix_count(ks, lo, hi, sh, hist[w]);
+    __syncthreads();
+    int c[kTeamWaves], tot = 0;
+#pragma unroll
+    for (int q = 0; q < kTeamWaves; ++q) {
+      c[q] = hist[q][t];
+      tot += c[q];
+    }
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      int y = __shfl_up(incl, o, kWave);
+      if (l >= o) incl += y;
+    }
+    if (l == kWave - 1) wtot[w] = incl;
+    __syncthreads();
+    int run = incl - tot;
+    for (int q = 0; q < w; ++q) run += wtot[q];
+#pragma unroll
+    for (int q = 0; q < kTeamWaves; ++q) {
+      hist[q][t] = run;
+      run += c[q];
+    }
+    __syncthreads();
+    if (lo < hi) radix_scatter(ks, vs, in_a ? kb : ka, in_a ? vb : va, lo, hi, sh, hist[w]);
+    __syncthreads();
+    in_a = !in_a;
+  }
+  return in_a;
+}
+
+// true when any wave of the team reported a failure (every wave must call it
+// at the same point)
+__device__ __forceinline__ bool team_failed(TeamShared &ts, bool mine) {
+  if (mine && lane() == 0) ts.fail = 1;
+  __syncthreads();
+  return ts.fail != 0;
+}
+
+__device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
+                           int (*hist)[256], double *coarse, TeamShared &ts, int *wtot) {
+  const int t = threadIdx.x, l = lane(), w = t >> 6;
+  const int64_t u0 = a.uptr[k];
+  const int nU = (int)(a.uptr[k + 1] - u0);
+  const int nF = ld_acq_relaxed(&a.fill_cnt[k]);
+  const int g = nU + nF;
+  const int levk = ld_acq_relaxed(&a.lev[k]);
+  // scratch: wave 0's region, grown geometrically
+  if (w == 0) {
+    bool bad = false;
+    const int64_t bytes = (((int64_t)g * 68) + 255) & ~(int64_t)255;
+    if (bytes > wk.sc_size) {
+      int64_t want = bytes > 2 * wk.sc_size ? bytes : 2 * wk.sc_size;
+      long long off = 0;
+      if (l == 0) off = (long long)atomicAdd(a.arena_top, (unsigned long long)want);
+      off = __shfl(off, 0, kWave);
+      if (off + want > a.arena_cap) {
+        set_error(a.err, PARAC_EPOOL);
+        bad = true;
+      } else {
+        wk.sc_base = off;
+        wk.sc_size = want;
+      }
+    }
+    if (l == 0) {
+      ts.fail = bad ? 1 : 0;
+      ts.sc_base = wk.sc_base;
+    }
+  }
+  __syncthreads();
+  if (ts.fail) return false;
+  char *base = a.arena + ts.sc_base;
+  uint64_t *keyA = (uint64_t *)base;
+  double *wA = (double *)(keyA + g);
+  uint64_t *keyB = (uint64_t *)(wA + g);
+  double *wB = (double *)(keyB + g);
+  double *mw = wB + g;
+  double *sw = mw + g;
+  double *S = sw + g;
+  int32_t *mu = (int32_t *)(S + g);
+  int32_t *mm = mu + g;
+  int32_t *su = mm + g;
+  // 1. gather
+#pragma unroll 4
+  for (int i = t; i < g; i += kTeamThreads) {
+    int32_t u, src;
+    double wt;
+    if (i < nU) {
+      u = a.uidx[u0 + i];
+      src = -1;
+      wt = a.uw[u0 + i];
+    } else {
+      Rec rc = load_rec(a, k, i - nU);
+      u = rc.other;
+      src = rc.src;
+      wt = rc.w;
+    }
+    keyA[i] = merge_key(u, src);
+    wA[i] = wt;
+  }
+  __syncthreads();
+  // 2. sort by (u, src)
+  {
+    // the bytes a key can use: src + 1 in the low word, u in the high word,
+    // both below 2^bits(ntot + 1)
+    const int nb = 32 - __clz(a.ntot + 1);
+    const int half = (nb + 7) / 8;
+    const bool in_a = team_radix_sort<uint64_t, uint64_t>(keyA, (uint64_t *)wA, keyB,
+                                                          (uint64_t *)wB, g, 2 * half, half, hist, wtot);
+    if (!in_a) {  // sorted data in the B buffers: swap names
+      uint64_t *tk = keyA;
+      keyA = keyB;
+      keyB = tk;
+      double *tw = wA;
+      wA = wB;
+      wB = tw;
+    }
+  }
+  const uint64_t *keyS = keyA;
+  const double *wS = wA;
+  // labels above k, and the runs that begin in each wave's share
+  int lo, hi;
+  team_range(g, w, lo, hi);
+  {
+    bool bad = false;
+    int cnt = 0;
+    for (int ib = lo; ib < hi; ib += kWave) {
+      const int i = ib + l;
+      const bool valid = i < hi;
+      const int32_t u = valid ? (int32_t)(keyS[i] >> 32) : 0;
+      const int32_t up = valid && i > 0 ? (int32_t)(keyS[i - 1] >> 32) : -1;
+      bad |= valid && (u <= k || u >= a.ntot);
+      cnt += __popcll(__ballot(valid && (i == 0 || up != u)));
+    }
+    if (__any(bad)) set_error(a.err, PARAC_EINTERNAL);
+    if (l == 0) ts.cnt[w] = cnt;
+    if (team_failed(ts, __any(bad))) return false;
+  }
+  int d0 = 0, d = 0;
+#pragma unroll
+  for (int q = 0; q < kTeamWaves; ++q) {
+    d0 += q < w ? ts.cnt[q] : 0;
+    d += ts.cnt[q];
+  }
+  {
+    const int d1 = merge_runs(keyS, wS, lo, hi, g, d0, mu, mw, mm);
+    const bool bad = d1 != d0 + ts.cnt[w];
+    if (bad) set_error(a.err, PARAC_EINTERNAL);
+    if (team_failed(ts, bad)) return false;
+  }
+  // 3. sampling order (w asc, u asc): the merged list is in ascending u, so
+  // a stable sort on the bits of w alone yields it
+  {
+    uint64_t *kx = keyB, *vx = (uint64_t *)wB, *ky = (uint64_t *)keyA, *vy = (uint64_t *)wA;
+    for (int i = t; i < d; i += kTeamThreads) {
+      kx[i] = dbits(mw[i]);
+      vx[i] = (uint64_t)(uint32_t)mu[i];
+    }
+    __syncthreads();
+    const bool in_x = team_radix_sort<uint64_t, uint64_t>(kx, vx, ky, vy, d, 8, 0, hist, wtot);
+    const uint64_t *kr = in_x ? kx : ky, *vr = in_x ? vx : vy;
+    for (int i = t; i < d; i += kTeamThreads) {
+      sw[i] = bitsd(kr[i]);
+      su[i] = (int32_t)(uint32_t)vr[i];
+    }
+    __syncthreads();
+  }
+  // suffix sums in the tiles and carries of the one-wave path: in-tile sums
+  // by all waves, the carry chain (right to left) in wave 0, then in-tile
+  // maxima, the maxima of the tiles to the right, and the final maximum
+  const int ntile = (d + kWave - 1) / kWave;
+  double *T = (double *)keyA;   // tile totals
+  double *Cy = (double *)wA;    // carry each tile receives
+  double *TM = (double *)keyB;  // tile maxima
+  double *MX = (double *)wB;    // maximum of the tiles to the right
+  for (int tt = w; tt < ntile; tt += kTeamWaves) {
+    const int t0 = tt * kWave;
+    const int len = d - t0 < kWave ? d - t0 : kWave;
+    double v = l < len ? sw[t0 + l] : 0.0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
+      if (l + o < len) v = v + y;
+    }
+    if (l < len) S[t0 + l] = v;
+    if (l == 0) T[tt] = v;
+  }
+  __syncthreads();
+  if (w == 0) {
+    double carry = 0.0;
+    for (int cb = ((ntile - 1) / kWave) * kWave; cb >= 0; cb -= kWave) {
+      const double tv = cb + l < ntile ? T[cb + l] : 0.0;
+      double cy = 0.0;
+      const int jt = ntile - 1 - cb < kWave - 1 ? ntile - 1 - cb : kWave - 1;
+      for (int j = jt; j >= 0; --j) {
+        const double tj = readlane_f64(tv, j);
+        if (l == j) cy = carry;
+        carry = (cb + j == ntile - 1) ? tj : tj + carry;
+      }
+      if (cb + l < ntile) Cy[cb + l] = cy;
+    }
+  }
+  __syncthreads();
+  for (int tt = w; tt < ntile; tt += kTeamWaves) {
+    const int t0 = tt * kWave;
+    const int len = d - t0 < kWave ? d - t0 : kWave;
+    double v = l < len ? S[t0 + l] : 0.0;
+    if (tt != ntile - 1) v = v + Cy[tt];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
+      if (l + o < len && y > v) v = y;
+    }
+    if (l < len) S[t0 + l] = v;
+    if (l == 0) TM[tt] = v;
+  }
+  __syncthreads();
+  if (w == 0) {
+    double run = 0.0;
+    for (int cb = ((ntile - 1) / kWave) * kWave; cb >= 0; cb -= kWave) {
+      const double tv = cb + l < ntile ? TM[cb + l] : 0.0;
+      double mx = 0.0;
+      const int jt = ntile - 1 - cb < kWave - 1 ? ntile - 1 - cb : kWave - 1;
+      for (int j = jt; j >= 0; --j) {
+        const double tj = readlane_f64(tv, j);
+        if (l == j) mx = run;
+        if (tj > run) run = tj;
+      }
+      if (cb + l < ntile) MX[cb + l] = mx;
+    }
+  }
+  __syncthreads();
+  for (int tt = w; tt < ntile; tt += kTeamWaves) {
+    const int t0 = tt * kWave;
+    const int len = d - t0 < kWave ? d - t0 : kWave;
+    const double mx = MX[tt];
+    if (l < len) {
+      const double v = S[t0 + l];
+      if (mx > v) S[t0 + l] = mx;
+    }
+  }
+  __syncthreads();
+  const double Dk = S[0];
+  // 4. sampled edges, the rounds of slots dealt to the waves in turn
+  {
+    const int st = (d + kTeamCoarse - 1) / kTeamCoarse;
+    const int nco = (d + st - 1) / st;
+    for (int j = t; j < nco; j += kTeamThreads) {
+      const int m = j * st;
+      coarse[j] = m + 1 < d ? S[m + 1] : 0.0;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int ib = w * kSampleRounds * kWave; ib < d - 1; ib += kTeamWaves * kSampleRounds * kWave)
+      if (!sample_rounds(a, wk, k, d, ib, S, sw, su, Dk, coarse, st, nco, deadline)) {
+        bad = true;
+        break;
+      }
+    if (team_failed(ts, bad)) return false;
+  }
+  // 5. column k of F
+  {
+    bool bad = false;
+    if (w == 0) {
+      int64_t fb = 0;
+      bad = !alloc_column(a, wk, d, fb);
+      if (l == 0) ts.fbase = fb;
+    }
+    if (team_failed(ts, bad)) return false;
+  }
+  const int64_t fbase = ts.fbase;
+  for (int i = t; i < d; i += kTeamThreads) {
+    const int32_t uu = mu[i];
+    a.frow[fbase + i] = uu;
+    a.fval[fbase + i] = -(mw[i] / Dk);
+    fetch_max(&a.lev[uu], levk + 1);
+  }
+  if (t == 0) {
+    a.D[k] = Dk;
+    a.colstart[k] = fbase;
+    a.colcnt[k] = d;
+  }
+  // 6. publish (every wave's stores complete before any counter drops),
+  // then delete the pivot's edges
+  WideSync::release();
+  __syncthreads();
+  bool bad = false;
+  for (int ib = w * 4 * kWave; ib < d; ib += kTeamWaves * 4 * kWave) {
+    bool valid[4];
+    int32_t uu[4];
+    int mmv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ib + q * kWave + l;
+      valid[q] = i < d;
+      uu[q] = valid[q] ? mu[i] : 0;
+      mmv[q] = valid[q] ? mm[i] : 0;
+    }
+    if (!decrement_batch<WideSync, 4>(a, valid, uu, mmv)) {
+      bad = true;
+      break;
+    }
+  }
+  return !team_failed(ts, bad);
+}
+
+// A team workgroup: claims slots of the team queue in increasing order, as
+// the waves claim shard slots, and leaves once every pivot it could be
+// waiting for is eliminated.
+__device__ __forceinline__ void team_worker(const ElimArgs &a, int (*hist)[256], double *coarse, TeamShared &ts,
+                            int *wtot) {
+  const int t = threadIdx.x, l = lane(), w = t >> 6;
+  const uint64_t deadline = now_ticks() + a.timeout_ticks;
+  const int64_t all = a.stop_at < (int64_t)a.ntot ? a.stop_at : (int64_t)a.ntot;
+  Worker wk{0, 0, 0, 0, 0, 0};
+  int slot = 0;
+  if (w == 0) {
+    if (l == 0) slot = atomicAdd(a.bq_head, 1);
+    slot = first_lane_i32(slot);
+  }
+  for (;;) {
+    if (w == 0) {
+      int32_t k = -1;
+      Backoff bo;
+      for (int it = 0;; ++it) {
+        int32_t v = -1;
+        if (l == 0 && slot < a.bq_cap) v = ld_acq_relaxed(&a.bq[slot]);
+        k = first_lane_i32(v);
+        if (k >= 0) break;
+        if ((it & 15) == 15 && (timed_out(a, deadline) || pivots_done(a) >= all)) break;
+        bo.pause();
+      }
+      if (k >= 0 && !sync_with_producers<WideSync>(a, k)) k = -1;
+      if (k >= 0) {
+        int nx = 0;
+        if (l == 0) nx = atomicAdd(a.bq_head, 1);
+        slot = first_lane_i32(nx);
+      }
+      if (l == 0) ts.k = k;
+    }
+    __syncthreads();
+    const int32_t k = ts.k;
+    if (k < 0) return;
+    WideSync::acquire();
+    if (!team_pivot(a, wk, k, deadline, hist, coarse, ts, wtot)) return;
+    if (t == 0) atomicAdd(&a.done[(k & (kSubQueues - 1)) * kTailStride], 1);
+    __syncthreads();  // ts.k is rewritten for the next pivot
+  }
+}
+
 __global__ __launch_bounds__(256, 2) void k_eliminate(ElimArgs a) {
   __shared__ int hist[4][256];          // radix-sort histogram of each wave
   __shared__ double coarse[4][kCoarse];  // coarse suffix sums of each wave
+  __shared__ TeamShared ts;
+  __shared__ int wtot[kTeamWaves];
+  if (a.stop_at <= 0) return;
+  if ((int)blockIdx.x >= a.team_wg0) {
+    team_worker(a, hist, &coarse[0][0], ts, wtot);
+    return;
+  }
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wid >= a.nworkers || a.stop_at <= 0) return;
+  if (wid >= a.nworkers) return;
   const uint64_t deadline = now_ticks() + a.timeout_ticks;
   // Shard x holds exactly the labels v = x (mod kSubQueues), so its slot
   // count is known.  Workers claim its slots in increasing order (the next
@@ -932,10 +1388,10 @@ __global__ __launch_bounds__(256, 2) void k_eliminate(ElimArgs a) {
     if (!sync_with_producers<WideSync>(a, k)) return;
     if (lane() == 0) next = atomicAdd(head, 1);
     next = __shfl(next, 0, kWave);
-    if (!eliminate_pivot<WideSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
-                                   coarse[threadIdx.x >> 6]))
-      return;
-    if (lane() == 0) atomicAdd(&a.done[x * kTailStride], 1);
+    const int out = eliminate_pivot<WideSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
+                                              coarse[threadIdx.x >> 6]);
+    if (out == kPivotFailed) return;
+    if (out == kPivotDone && lane() == 0) atomicAdd(&a.done[x * kTailStride], 1);
   }
 }
 
@@ -982,8 +1438,8 @@ __global__ __launch_bounds__(1024) void k_eliminate_tail(ElimArgs a) {
     if (!sync_with_producers<TailSync>(a, k)) return;
     if (lane() == 0) next = __hip_atomic_fetch_add(a.tq_head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     next = __shfl(next, 0, kWave);
-    if (!eliminate_pivot<TailSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
-                                   coarse[threadIdx.x >> 6]))
+    if (eliminate_pivot<TailSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
+                                  coarse[threadIdx.x >> 6]) != kPivotDone)
       return;
   }
 }

@@ -28,6 +28,8 @@ constexpr int kInline = 8;
 constexpr int kPages = 17;             // capacity 8 (2^17 - 1) ~ 1M records
 constexpr int kSubQueues = 64;         // ready-queue shards (power of two)
 constexpr int kTailStride = 32;        // ints between shard tails (128 B)
+constexpr int kTeamMin = 1024;         // gathered entries above which a team eliminates
+constexpr int kTeamShare = 16;         // one workgroup in this many is a team
 constexpr int kFChunk = 2048;          // largest factor-entry reservation
 constexpr int kPageChunk = 4096;       // largest fill-record reservation
 
@@ -68,6 +70,11 @@ struct ElimArgs {
   int64_t stop_at;     // the wide kernel leaves once this many are eliminated
   int32_t *tq;         // tail queue [ntot] (-1 = empty slot)
   int32_t *tq_head, *tq_tail, *tq_count;  // tail claim, append, pivots left
+  int32_t *bq;         // team queue [bq_cap] (-1 = empty slot)
+  int32_t *bq_head, *bq_tail;  // team claim, append
+  int32_t bq_cap;
+  int32_t team_min;    // pivots with more gathered entries go to teams (0: none)
+  int32_t team_wg0;    // workgroups from this index on are teams
 };
 
 // --- launchers (setup.hip) ---

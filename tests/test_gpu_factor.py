@@ -127,6 +127,43 @@ def test_tail_kernel_split_is_exact(orc, tail):
     compare_factor(f, ref)
 
 
+_PL = {}
+
+
+def power_law_case(orc):
+    """A Chung-Lu graph (16k vertices, beta 2.1) whose largest gathered
+    neighbourhoods are far above a thousand entries, with its oracle factor."""
+    if not _PL:
+        rng = np.random.default_rng(78)
+        i, j = inputs.chung_lu_edges(1 << 14, 16.0, 2.1, rng)
+        m, i, j, _ = inputs.largest_component(1 << 14, i, j)
+        A = lap(m, i, j, rng.uniform(0.5, 2.0, len(i)))
+        perm = np.random.default_rng(79).permutation(m).astype(np.int32)
+        ref = orc.factor(A, perm=perm, seed=4242)
+        assert ref.status == 0 and ref.stats["max_gather"] > 2048
+        _PL.update(A=A, perm=perm, ref=ref)
+    return _PL["A"], _PL["perm"], _PL["ref"]
+
+
+@pytest.mark.parametrize("workers,tail,pool", [(64, -1.0, 4.0), (0, 0.3, 4.0), (0, 1.0, 4.0),
+                                               (256, -1.0, 0.02)])
+def test_team_path_is_exact(orc, workers, tail, pool):
+    """Pivots with more than a thousand gathered entries are eliminated by
+    the four waves of a team workgroup, the others by single waves.  The
+    factor does not change with the number of single-wave workers, with a
+    hand-over to the tail kernel (which has no teams) part-way or from the
+    start, or with pool exhaustion and retries inside team pivots."""
+    need_gpu()
+    A, perm, ref = power_law_case(orc)
+    f = gpu_factor(A, perm, 4242, workers=workers, tail_fraction=tail, pool_factor=pool)
+    if pool < 1.0:
+        assert f.info()["retries"] >= 1
+    info = f.info()
+    assert info["max_gather"] == ref.stats["max_gather"]
+    assert info["depth"] == ref.stats["depth"]
+    compare_factor(f, ref)
+
+
 def test_pool_exhaustion_retry_is_exact(orc):
     """A pool far too small forces EPOOL and internal retries with larger
     pools; the result is unchanged because storage does not enter the
