@@ -932,10 +932,11 @@ __device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
 }
 
 // ---------------------------------------------------------------------------
-// The largest neighbourhoods: the four waves of a workgroup on one pivot.
-// Most of the time of a power-law factorisation goes to a chain of pivots
-// with thousands of gathered entries, each of which depends on the one
-// before; a team shortens every link of that chain.  Each step keeps the
+// Larger neighbourhoods: the four waves of a workgroup on one pivot.  The
+// critical path of a factorisation is a chain of pivots, each depending on
+// the one before, and the longest links are the pivots with many gathered
+// entries (thousands on power-law graphs, a few hundred on 3D grids); a
+// team shortens every such link.  Each step keeps the
 // order of its arithmetic -- the same stable sorts, the same left folds of
 // runs, the same 64-wide tiles and carries of the suffix sums, the same
 // draws -- so the factor does not depend on which path eliminated a pivot.
