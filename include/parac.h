@@ -81,7 +81,9 @@ typedef struct {
   double pool_factor;     /* fill-pool capacity in records per stored entry
                              of L (default 4.0, as in §IV-A); doubled and
                              retried automatically on exhaustion            */
-  int32_t workers;        /* persistent waves (0 = all that fit)            */
+  int32_t workers;        /* single-wave workers of the persistent grid
+                             (0 = all that fit beside the team workgroups,
+                             which take pivots above 128 gathered entries) */
   int32_t keep_fp32;      /* also build the FP32 copy used by MIXED apply   */
   double timeout_s;       /* elimination watchdog (0 = 30 s)                */
   double tail_fraction;   /* share of pivots left to the single-workgroup
@@ -98,7 +100,7 @@ typedef struct {
   int64_t max_deg;        /* largest merged neighbourhood d_k               */
   int64_t depth;          /* levels of the elimination dependency DAG       */
   int64_t n_zero_pivots;  /* D_k = 0 (one per connected component)          */
-  int32_t workers;        /* persistent waves used                          */
+  int32_t workers;        /* single-wave workers used (teams not counted)   */
   int32_t retries;        /* pool-exhaustion retries                        */
   double pool_factor;     /* pool factor of the successful attempt          */
   double ms_setup;        /* relabel, upper adjacency, counters, queue      */

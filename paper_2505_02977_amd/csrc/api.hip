@@ -261,12 +261,12 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   // one workgroup in kTeamShare is a team for the largest pivots (none when
   // the graph is too small to have any)
   const int nteam = ntot > 4 * kTeamMin ? maxwg / kTeamShare : 0;
-  int workers = ((maxwg - nteam) * 4) / kSubQueues * kSubQueues;
+  int workers = ((maxwg - nteam) * kElimWaves) / kSubQueues * kSubQueues;
   // no more workers than a quarter of the pivots could keep busy
   workers = std::min<int64_t>(workers, std::max<int64_t>(kSubQueues, (ntot / 4) / kSubQueues * kSubQueues));
   if (opt.workers > 0) workers = std::min(workers, std::max(kSubQueues, opt.workers / kSubQueues * kSubQueues));
   if (workers < kSubQueues) throw Err{PARAC_EDEVICE, "device too small for the persistent grid"};
-  const int wgs = workers / 4;
+  const int wgs = workers / kElimWaves;
 
   // per-attempt state
   const int32_t cap_q = (int32_t)((ntot + kSubQueues - 1) / kSubQueues);

@@ -943,7 +943,7 @@ __device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
 // A wave that claims such a pivot hands it to the team queue; teams are
 // workgroups of their own in the persistent grid.
 // ---------------------------------------------------------------------------
-constexpr int kTeamWaves = 4;
+constexpr int kTeamWaves = kElimWaves;
 constexpr int kTeamThreads = kTeamWaves * kWave;
 constexpr int kTeamCoarse = kTeamWaves * kCoarse;
 
@@ -987,26 +987,31 @@ __device__ __forceinline__ bool team_radix_sort(K *ka, V *va, K *kb, V *vb, int 
     fence_wave_local();
     if (lo < hi) radix_count(ks, lo, hi, sh, hist[w]);
     __syncthreads();
-    int c[kTeamWaves], tot = 0;
+    // thread t < 256 owns bucket t (the first four waves)
+    int c[kTeamWaves], tot = 0, incl = 0;
+    if (t < 256) {
 #pragma unroll
-    for (int q = 0; q < kTeamWaves; ++q) {
-      c[q] = hist[q][t];
-      tot += c[q];
-    }
-    int incl = tot;
+      for (int q = 0; q < kTeamWaves; ++q) {
+        c[q] = hist[q][t];
+        tot += c[q];
+      }
+      incl = tot;
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      int y = __shfl_up(incl, o, kWave);
-      if (l >= o) incl += y;
+      for (int o = 1; o < kWave; o <<= 1) {
+        int y = __shfl_up(incl, o, kWave);
+        if (l >= o) incl += y;
+      }
+      if (l == kWave - 1) wtot[w] = incl;
     }
-    if (l == kWave - 1) wtot[w] = incl;
     __syncthreads();
-    int run = incl - tot;
-    for (int q = 0; q < w; ++q) run += wtot[q];
+    if (t < 256) {
+      int run = incl - tot;
+      for (int q = 0; q < w; ++q) run += wtot[q];
 #pragma unroll
-    for (int q = 0; q < kTeamWaves; ++q) {
-      hist[q][t] = run;
-      run += c[q];
+      for (int q = 0; q < kTeamWaves; ++q) {
+        hist[q][t] = run;
+        run += c[q];
+      }
     }
     __syncthreads();
     if (lo < hi) radix_scatter(ks, vs, in_a ? kb : ka, in_a ? vb : va, lo, hi, sh, hist[w]);
@@ -1335,9 +1340,10 @@ __device__ __forceinline__ void team_worker(const ElimArgs &a, int (*hist)[256],
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_eliminate(ElimArgs a) {
-  __shared__ int hist[4][256];          // radix-sort histogram of each wave
-  __shared__ double coarse[4][kCoarse];  // coarse suffix sums of each wave
+static_assert(kElimWaves >= 4 && kElimWaves <= 8, "team sorts assume 4 to 8 waves");
+__global__ __launch_bounds__(kElimWaves * kWave, 8 / kElimWaves) void k_eliminate(ElimArgs a) {
+  __shared__ int hist[kElimWaves][256];          // radix-sort histogram of each wave
+  __shared__ double coarse[kElimWaves][kCoarse];  // coarse suffix sums of each wave
   __shared__ TeamShared ts;
   __shared__ int wtot[kTeamWaves];
   if (a.stop_at <= 0) return;
@@ -1446,7 +1452,7 @@ __global__ __launch_bounds__(1024) void k_eliminate_tail(ElimArgs a) {
 }
 
 hipError_t launch_eliminate(const ElimArgs &a, int wgs, hipStream_t s) {
-  hipLaunchKernelGGL(k_eliminate, dim3((unsigned)wgs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_eliminate, dim3((unsigned)wgs), dim3(kElimWaves * kWave), 0, s, a);
   hipLaunchKernelGGL(k_tail_seed, dim3((unsigned)((a.ntot + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_eliminate_tail, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
@@ -1457,7 +1463,7 @@ int eliminate_max_workgroups() {
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eliminate, 256, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eliminate, kElimWaves * kWave, 0) != hipSuccess)
     return 0;
   return per_cu * prop.multiProcessorCount;
 }
