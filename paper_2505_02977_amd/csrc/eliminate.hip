@@ -932,7 +932,7 @@ __device__ __forceinline__ int64_t pivots_done(const ElimArgs &a) {
 }
 
 // ---------------------------------------------------------------------------
-// Larger neighbourhoods: the four waves of a workgroup on one pivot.  The
+// Larger neighbourhoods: the eight waves of a workgroup on one pivot.  The
 // critical path of a factorisation is a chain of pivots, each depending on
 // the one before, and the longest links are the pivots with many gathered
 // entries (thousands on power-law graphs, a few hundred on 3D grids); a

@@ -28,7 +28,7 @@ constexpr int kInline = 8;
 constexpr int kPages = 17;             // capacity 8 (2^17 - 1) ~ 1M records
 constexpr int kSubQueues = 64;         // ready-queue shards (power of two)
 constexpr int kTailStride = 32;        // ints between shard tails (128 B)
-constexpr int kElimWaves = 4;          // waves per workgroup of the persistent elimination
+constexpr int kElimWaves = 8;          // waves per workgroup of the persistent elimination
 constexpr int kTeamMin = 128;          // gathered entries above which a team eliminates
 constexpr int kTeamShare = 16;         // one workgroup in this many is a team
 constexpr int kFChunk = 2048;          // largest factor-entry reservation

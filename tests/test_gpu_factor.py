@@ -149,7 +149,7 @@ def power_law_case(orc):
                                                (256, -1.0, 0.02)])
 def test_team_path_is_exact(orc, workers, tail, pool):
     """Pivots with more than 128 gathered entries are eliminated by the
-    four waves of a team workgroup, the others by single waves.  The
+    eight waves of a team workgroup, the others by single waves.  The
     factor does not change with the number of single-wave workers, with a
     hand-over to the tail kernel (which has no teams) part-way or from the
     start, or with pool exhaustion and retries inside team pivots."""
