@@ -1021,6 +1021,42 @@ __device__ __forceinline__ bool team_radix_sort(K *ka, V *va, K *kb, V *vb, int 
   return in_a;
 }
 
+// Rank sort by the team for at most kTeamRankMax entries: the keys are staged
+// in LDS (lk), and each thread counts, for each of its entries, the keys
+// below it -- or equal to it at a smaller index, which makes the result the
+// stable order, that of team_radix_sort -- and writes the entry to its rank.
+constexpr int kTeamRankMax = 512;
+static_assert(kTeamRankMax <= kTeamWaves * kCoarse, "rank-sort keys live in the coarse-table LDS");
+__device__ __forceinline__ void team_rank_sort(const uint64_t *ks, const uint64_t *vs, uint64_t *kd,
+                                               uint64_t *vd, int n, uint64_t *lk) {
+  constexpr int E = (kTeamRankMax + kTeamThreads - 1) / kTeamThreads;
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += kTeamThreads) lk[i] = ks[i];
+  __syncthreads();
+  uint64_t mk[E];
+  int r[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + e * kTeamThreads;
+    mk[e] = i < n ? lk[i] : ~0ull;
+    r[e] = 0;
+  }
+  for (int j = 0; j < n; ++j) {
+    const uint64_t kj = lk[j];
+#pragma unroll
+    for (int e = 0; e < E; ++e) r[e] += (kj < mk[e] || (kj == mk[e] && j < t + e * kTeamThreads)) ? 1 : 0;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + e * kTeamThreads;
+    if (i < n) {
+      kd[r[e]] = mk[e];
+      vd[r[e]] = vs[i];
+    }
+  }
+  __syncthreads();
+}
+
 // true when any wave of the team reported a failure (every wave must call it
 // at the same point)
 __device__ __forceinline__ bool team_failed(TeamShared &ts, bool mine) {
@@ -1097,8 +1133,12 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
     // both below 2^bits(ntot + 1)
     const int nb = 32 - __clz(a.ntot + 1);
     const int half = (nb + 7) / 8;
-    const bool in_a = team_radix_sort<uint64_t, uint64_t>(keyA, (uint64_t *)wA, keyB,
-                                                          (uint64_t *)wB, g, 2 * half, half, hist, wtot);
+    bool in_a = false;
+    if (g <= kTeamRankMax)
+      team_rank_sort(keyA, (const uint64_t *)wA, keyB, (uint64_t *)wB, g, (uint64_t *)coarse);
+    else
+      in_a = team_radix_sort<uint64_t, uint64_t>(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g,
+                                                 2 * half, half, hist, wtot);
     if (!in_a) {  // sorted data in the B buffers: swap names
       uint64_t *tk = keyA;
       keyA = keyB;
@@ -1149,7 +1189,11 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
       vx[i] = (uint64_t)(uint32_t)mu[i];
     }
     __syncthreads();
-    const bool in_x = team_radix_sort<uint64_t, uint64_t>(kx, vx, ky, vy, d, 8, 0, hist, wtot);
+    bool in_x = false;
+    if (d <= kTeamRankMax)
+      team_rank_sort(kx, vx, ky, vy, d, (uint64_t *)coarse);
+    else
+      in_x = team_radix_sort<uint64_t, uint64_t>(kx, vx, ky, vy, d, 8, 0, hist, wtot);
     const uint64_t *kr = in_x ? kx : ky, *vr = in_x ? vx : vy;
     for (int i = t; i < d; i += kTeamThreads) {
       sw[i] = bitsd(kr[i]);
