@@ -1057,6 +1057,44 @@ __device__ __forceinline__ void team_rank_sort(const uint64_t *ks, const uint64_
   __syncthreads();
 }
 
+// Radix sorts of at most kTeamLdsSort entries run in LDS: the pairs are
+// copied in once, every pass reads and writes LDS (a workgroup has its CU to
+// itself, so the LDS is otherwise idle), and the result is copied out once.
+constexpr int kTeamLdsSort = 3072;
+struct TeamSortLds {
+  uint64_t k[2][kTeamLdsSort];
+  uint64_t v[2][kTeamLdsSort];
+};
+// The team's stable sort of the pairs (ka, va) of n entries, with the
+// buffers (kb, vb) beside them, all in global memory; the key bytes are given
+// as for team_radix_sort.  Returns true when the result is in (ka, va),
+// false when it is in (kb, vb).
+__device__ __forceinline__ bool team_sort_pairs(uint64_t *ka, uint64_t *va, uint64_t *kb,
+                                                uint64_t *vb, int n, int npass, int half,
+                                                int (*hist)[256], int *wtot, uint64_t *lk,
+                                                TeamSortLds &ls) {
+  const int t = threadIdx.x;
+  if (n <= kTeamRankMax) {
+    team_rank_sort(ka, va, kb, vb, n, lk);
+    return false;
+  }
+  if (n > kTeamLdsSort) return team_radix_sort<uint64_t, uint64_t>(ka, va, kb, vb, n, npass, half, hist, wtot);
+  for (int i = t; i < n; i += kTeamThreads) {
+    ls.k[0][i] = ka[i];
+    ls.v[0][i] = va[i];
+  }
+  __syncthreads();
+  const bool in0 = team_radix_sort<uint64_t, uint64_t>(ls.k[0], ls.v[0], ls.k[1], ls.v[1], n, npass,
+                                                       half, hist, wtot);
+  const uint64_t *rk = ls.k[in0 ? 0 : 1], *rv = ls.v[in0 ? 0 : 1];
+  for (int i = t; i < n; i += kTeamThreads) {
+    kb[i] = rk[i];
+    vb[i] = rv[i];
+  }
+  __syncthreads();
+  return false;
+}
+
 // true when any wave of the team reported a failure (every wave must call it
 // at the same point)
 __device__ __forceinline__ bool team_failed(TeamShared &ts, bool mine) {
@@ -1066,7 +1104,8 @@ __device__ __forceinline__ bool team_failed(TeamShared &ts, bool mine) {
 }
 
 __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
-                           int (*hist)[256], double *coarse, TeamShared &ts, int *wtot) {
+                           int (*hist)[256], double *coarse, TeamShared &ts, int *wtot,
+                           TeamSortLds &ls) {
   const int t = threadIdx.x, l = lane(), w = t >> 6;
   const int64_t u0 = a.uptr[k];
   const int nU = (int)(a.uptr[k + 1] - u0);
@@ -1133,12 +1172,8 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
     // both below 2^bits(ntot + 1)
     const int nb = 32 - __clz(a.ntot + 1);
     const int half = (nb + 7) / 8;
-    bool in_a = false;
-    if (g <= kTeamRankMax)
-      team_rank_sort(keyA, (const uint64_t *)wA, keyB, (uint64_t *)wB, g, (uint64_t *)coarse);
-    else
-      in_a = team_radix_sort<uint64_t, uint64_t>(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g,
-                                                 2 * half, half, hist, wtot);
+    const bool in_a = team_sort_pairs(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g, 2 * half, half,
+                                      hist, wtot, (uint64_t *)coarse, ls);
     if (!in_a) {  // sorted data in the B buffers: swap names
       uint64_t *tk = keyA;
       keyA = keyB;
@@ -1189,11 +1224,7 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
       vx[i] = (uint64_t)(uint32_t)mu[i];
     }
     __syncthreads();
-    bool in_x = false;
-    if (d <= kTeamRankMax)
-      team_rank_sort(kx, vx, ky, vy, d, (uint64_t *)coarse);
-    else
-      in_x = team_radix_sort<uint64_t, uint64_t>(kx, vx, ky, vy, d, 8, 0, hist, wtot);
+    const bool in_x = team_sort_pairs(kx, vx, ky, vy, d, 8, 0, hist, wtot, (uint64_t *)coarse, ls);
     const uint64_t *kr = in_x ? kx : ky, *vr = in_x ? vx : vy;
     for (int i = t; i < d; i += kTeamThreads) {
       sw[i] = bitsd(kr[i]);
@@ -1344,7 +1375,7 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
 // the waves claim shard slots, and leaves once every pivot it could be
 // waiting for is eliminated.
 __device__ __forceinline__ void team_worker(const ElimArgs &a, int (*hist)[256], double *coarse, TeamShared &ts,
-                            int *wtot) {
+                            int *wtot, TeamSortLds &ls) {
   const int t = threadIdx.x, l = lane(), w = t >> 6;
   const uint64_t deadline = now_ticks() + a.timeout_ticks;
   const int64_t all = a.stop_at < (int64_t)a.ntot ? a.stop_at : (int64_t)a.ntot;
@@ -1378,7 +1409,7 @@ __device__ __forceinline__ void team_worker(const ElimArgs &a, int (*hist)[256],
     const int32_t k = ts.k;
     if (k < 0) return;
     WideSync::acquire();
-    if (!team_pivot(a, wk, k, deadline, hist, coarse, ts, wtot)) return;
+    if (!team_pivot(a, wk, k, deadline, hist, coarse, ts, wtot, ls)) return;
     if (t == 0) atomicAdd(&a.done[(k & (kSubQueues - 1)) * kTailStride], 1);
     __syncthreads();  // ts.k is rewritten for the next pivot
   }
@@ -1390,9 +1421,10 @@ __global__ __launch_bounds__(kElimWaves * kWave, 8 / kElimWaves) void k_eliminat
   __shared__ double coarse[kElimWaves][kCoarse];  // coarse suffix sums of each wave
   __shared__ TeamShared ts;
   __shared__ int wtot[kTeamWaves];
+  __shared__ TeamSortLds tls;
   if (a.stop_at <= 0) return;
   if ((int)blockIdx.x >= a.team_wg0) {
-    team_worker(a, hist, &coarse[0][0], ts, wtot);
+    team_worker(a, hist, &coarse[0][0], ts, wtot, tls);
     return;
   }
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
