@@ -1,8 +1,10 @@
 // eliminate.hip -- the persistent elimination kernel.
 //
-// One wave64 eliminates one pivot at a time.  Workers poll their slots of the
-// ready queue round-robin (§IV-A, work scheduling), so the whole factorisation
-// is one launch (§IV-C, persistent kernel).  For a pivot k the wave
+// Workers poll their slots of the ready queue round-robin (§IV-A, work
+// scheduling), so the whole factorisation is one launch (§IV-C, persistent
+// kernel).  A worker is one wave64 for a pivot of up to 128 gathered entries;
+// a larger pivot is handed to a team, one of the workgroups reserved for them,
+// whose eight waves share every step below.  For a pivot k the worker
 //   1. gathers the input upper edges of k and every fill record addressed to k
 //      (all present once k is ready: insertions precede deletions, §III);
 //   2. merges parallel edges (sort by (u, src), left fold per run -- the
