@@ -226,7 +226,6 @@ __device__ __forceinline__ bool alloc_column(const ElimArgs &a, Worker &wk, int 
 // workgroup on one CU: workgroup-scope fences suffice, and it has its own
 // queue.
 struct WideSync {
-  static constexpr bool kTeams = true;  // the largest pivots go to teams
   static __device__ __forceinline__ void release() { store_wait(); }
   static __device__ __forceinline__ void acquire() { compiler_fence(); }
   static __device__ __forceinline__ bool enqueue(const ElimArgs &a, int32_t u) {
@@ -239,7 +238,6 @@ struct WideSync {
   }
 };
 struct TailSync {
-  static constexpr bool kTeams = false;
   static __device__ __forceinline__ void release() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   }
@@ -877,35 +875,35 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   return true;
 }
 
-// the outcome of eliminate_pivot
-enum PivotOutcome { kPivotFailed = 0, kPivotDone = 1, kPivotHanded = 2 };
+// the gathered size of ready pivot k: nU input upper edges from u0, and its
+// fill records
+struct PivotSize {
+  int64_t u0;
+  int nU, g;
+};
+__device__ __forceinline__ PivotSize pivot_size(const ElimArgs &a, int32_t k) {
+  PivotSize z;
+  z.u0 = a.uptr[k];
+  z.nU = (int)(a.uptr[k + 1] - z.u0);
+  z.g = z.nU + ld_acq_relaxed(&a.fill_cnt[k]);
+  return z;
+}
 
 template <class Sync>
-__device__ __forceinline__ int eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k, uint64_t deadline,
-                               int *h, double *coarse) {
-  const int64_t u0 = a.uptr[k];
-  const int nU = (int)(a.uptr[k + 1] - u0);
-  const int nF = ld_acq_relaxed(&a.fill_cnt[k]);
-  const int g = nU + nF;
-  if (g == 0) {  // empty neighbourhood: D_k = 0 (Alg. 3/4)
+__device__ __forceinline__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, int32_t k,
+                                                const PivotSize &z, uint64_t deadline, int *h,
+                                                double *coarse) {
+  if (z.g == 0) {  // empty neighbourhood: D_k = 0 (Alg. 3/4)
     if (lane() == 0) {
       a.D[k] = 0.0;
       a.colstart[k] = 0;
       a.colcnt[k] = 0;
     }
-    return kPivotDone;
-  }
-  if (Sync::kTeams && a.team_min > 0 && g > a.team_min) {
-    // to the team queue (its slots are never reused: no wrap)
-    if (lane() == 0) {
-      const int pos = fetch_add(a.bq_tail, 1);
-      __hip_atomic_exchange(&a.bq[pos], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return kPivotHanded;
+    return true;
   }
   const int levk = ld_acq_relaxed(&a.lev[k]);
-  if (g <= kWave) return small_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline) ? kPivotDone : kPivotFailed;
-  return large_pivot<Sync>(a, wk, k, u0, nU, g, levk, deadline, h, coarse) ? kPivotDone : kPivotFailed;
+  if (z.g <= kWave) return small_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline);
+  return large_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline, h, coarse);
 }
 
 // After a slot has delivered label k: read k's counter (agent scope).  Zero
@@ -1382,13 +1380,13 @@ __device__ __forceinline__ void team_worker(const ElimArgs &a, int (*hist)[256],
   const uint64_t deadline = now_ticks() + a.timeout_ticks;
   const int64_t all = a.stop_at < (int64_t)a.ntot ? a.stop_at : (int64_t)a.ntot;
   Worker wk{0, 0, 0, 0, 0, 0};
-  int slot = 0;
-  if (w == 0) {
-    if (l == 0) slot = atomicAdd(a.bq_head, 1);
-    slot = first_lane_i32(slot);
-  }
   for (;;) {
+    // a team claims a slot only when it is free, so that a handed-off pivot
+    // never waits for a busy team while another one idles
     if (w == 0) {
+      int slot = 0;
+      if (l == 0) slot = atomicAdd(a.bq_head, 1);
+      slot = first_lane_i32(slot);
       int32_t k = -1;
       Backoff bo;
       for (int it = 0;; ++it) {
@@ -1399,12 +1397,7 @@ __device__ __forceinline__ void team_worker(const ElimArgs &a, int (*hist)[256],
         if ((it & 15) == 15 && (timed_out(a, deadline) || pivots_done(a) >= all)) break;
         bo.pause();
       }
-      if (k >= 0 && !sync_with_producers<WideSync>(a, k)) k = -1;
-      if (k >= 0) {
-        int nx = 0;
-        if (l == 0) nx = atomicAdd(a.bq_head, 1);
-        slot = first_lane_i32(nx);
-      }
+      // the wave that handed k over has seen its counter at zero
       if (l == 0) ts.k = k;
     }
     __syncthreads();
@@ -1471,12 +1464,21 @@ __global__ __launch_bounds__(kElimWaves * kWave, 8 / kElimWaves) void k_eliminat
       bo.pause();
     }
     if (!sync_with_producers<WideSync>(a, k)) return;
+    // a pivot above team_min goes to the team queue (whose slots are never
+    // reused) before the next claim
+    const PivotSize z = pivot_size(a, k);
+    const bool handed = a.team_min > 0 && z.g > a.team_min;
+    if (handed && lane() == 0) {
+      const int pos = fetch_add(a.bq_tail, 1);
+      __hip_atomic_exchange(&a.bq[pos], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (lane() == 0) next = atomicAdd(head, 1);
     next = __shfl(next, 0, kWave);
-    const int out = eliminate_pivot<WideSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
-                                              coarse[threadIdx.x >> 6]);
-    if (out == kPivotFailed) return;
-    if (out == kPivotDone && lane() == 0) atomicAdd(&a.done[x * kTailStride], 1);
+    if (handed) continue;
+    if (!eliminate_pivot<WideSync>(a, wk, k, z, deadline, hist[threadIdx.x >> 6],
+                                   coarse[threadIdx.x >> 6]))
+      return;
+    if (lane() == 0) atomicAdd(&a.done[x * kTailStride], 1);
   }
 }
 
@@ -1523,8 +1525,8 @@ __global__ __launch_bounds__(1024) void k_eliminate_tail(ElimArgs a) {
     if (!sync_with_producers<TailSync>(a, k)) return;
     if (lane() == 0) next = __hip_atomic_fetch_add(a.tq_head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     next = __shfl(next, 0, kWave);
-    if (eliminate_pivot<TailSync>(a, wk, k, deadline, hist[threadIdx.x >> 6],
-                                  coarse[threadIdx.x >> 6]) != kPivotDone)
+    if (!eliminate_pivot<TailSync>(a, wk, k, pivot_size(a, k), deadline, hist[threadIdx.x >> 6],
+                                   coarse[threadIdx.x >> 6]))
       return;
   }
 }
