@@ -614,7 +614,7 @@ __device__ __forceinline__ int merge_runs(const uint64_t *keyS, const double *wS
   return d;
 }
 
-// Sampled edges of the slots [ib, ib + 4*64) of a pivot with d merged
+// Sampled edges of the slots ib + r*stride + [0, 64), r < 4, of a pivot with d merged
 // neighbours in (w, u) order (weights sw, labels su, suffix sums S, D_k = S[0]).
 // The partner of slot s is the first m > s with S[m+1] <= t (S
 // non-increasing, S[d] = 0).  A coarse copy of S in LDS (coarse[j] =
@@ -622,8 +622,8 @@ __device__ __forceinline__ int merge_runs(const uint64_t *keyS, const double *wS
 // of the four rounds of 64 slots run interleaved.
 constexpr int kSampleRounds = 4;
 __device__ __forceinline__ bool sample_rounds(const ElimArgs &a, Worker &wk, int32_t k, int d, int ib,
-                              const double *S, const double *sw, const int32_t *su, double Dk,
-                              const double *coarse, int st, int nco, uint64_t deadline) {
+                              int stride, const double *S, const double *sw, const int32_t *su,
+                              double Dk, const double *coarse, int st, int nco, uint64_t deadline) {
   constexpr int R = kSampleRounds;
   const int l = lane();
   int lo[R], hi[R];
@@ -631,13 +631,13 @@ __device__ __forceinline__ bool sample_rounds(const ElimArgs &a, Worker &wk, int
   bool ins[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int sl = ib + r * kWave + l;
+    const int sl = ib + r * stride + l;
     ins[r] = sl < d - 1;
     Sp1[r] = ins[r] ? S[sl + 1] : 0.0;
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int sl = ib + r * kWave + l;
+    const int sl = ib + r * stride + l;
     lo[r] = sl + 1;
     hi[r] = d - 1;
     if (!ins[r]) {
@@ -676,7 +676,7 @@ __device__ __forceinline__ bool sample_rounds(const ElimArgs &a, Worker &wk, int
   double c[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int sl = ib + r * kWave + l;
+    const int sl = ib + r * stride + l;
     tgt[r] = oth[r] = 0;
     c[r] = 0.0;
     if (ins[r]) {
@@ -841,7 +841,7 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   }
   fence_wave_local();
   for (int ib = 0; ib < d - 1; ib += kSampleRounds * kWave)
-    if (!sample_rounds(a, wk, k, d, ib, S, sw, su, Dk, coarse, st, nco, deadline)) return false;
+    if (!sample_rounds(a, wk, k, d, ib, kWave, S, sw, su, Dk, coarse, st, nco, deadline)) return false;
   // 5. column k of F
   int64_t fbase;
   if (!alloc_column(a, wk, d, fbase)) return false;
@@ -1308,7 +1308,7 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
   }
   __syncthreads();
   const double Dk = S[0];
-  // 4. sampled edges, the rounds of slots dealt to the waves in turn
+  // 4. sampled edges, the rounds of 64 slots dealt to the waves in turn
   {
     const int st = (d + kTeamCoarse - 1) / kTeamCoarse;
     const int nco = (d + st - 1) / st;
@@ -1318,8 +1318,11 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
     }
     __syncthreads();
     bool bad = false;
-    for (int ib = w * kSampleRounds * kWave; ib < d - 1; ib += kTeamWaves * kSampleRounds * kWave)
-      if (!sample_rounds(a, wk, k, d, ib, S, sw, su, Dk, coarse, st, nco, deadline)) {
+    // wave w takes the 64-slot rounds w, w + 8, w + 16, ...: small pivots
+    // spread over all waves
+    for (int ib = w * kWave; ib < d - 1; ib += kTeamWaves * kSampleRounds * kWave)
+      if (!sample_rounds(a, wk, k, d, ib, kTeamWaves * kWave, S, sw, su, Dk, coarse, st, nco,
+                         deadline)) {
         bad = true;
         break;
       }
@@ -1352,13 +1355,14 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
   WideSync::release();
   __syncthreads();
   bool bad = false;
-  for (int ib = w * 4 * kWave; ib < d; ib += kTeamWaves * 4 * kWave) {
+  // wave w takes the 64-entry chunks w, w + 8, w + 16, ...
+  for (int ib = w * kWave; ib < d; ib += kTeamWaves * 4 * kWave) {
     bool valid[4];
     int32_t uu[4];
     int mmv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = ib + q * kWave + l;
+      const int i = ib + q * kTeamWaves * kWave + l;
       valid[q] = i < d;
       uu[q] = valid[q] ? mu[i] : 0;
       mmv[q] = valid[q] ? mm[i] : 0;
