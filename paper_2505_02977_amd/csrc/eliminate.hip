@@ -959,7 +959,7 @@ __device__ __forceinline__ double readlane_f64(double v, int j) {
   return __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(v), j));
 }
 
-// wave w's share of [0, n): a quarter of the chunks of 64, in order
+// wave w's share of [0, n): an equal part of the chunks of 64, in order
 __device__ __forceinline__ void team_range(int n, int w, int &lo, int &hi) {
   const int nch = (n + kWave - 1) / kWave;
   const int per = (nch + kTeamWaves - 1) / kTeamWaves;
