@@ -8,19 +8,24 @@ layout) followed by PCG with the factor to a 1e-6 relative residual (true
 residual recomputed in FP64).
 
 Workloads (--workload):
-  grid3d_128   default: 3D 7-point Laplacian 128^3 (2,097,152 vertices),
-               weights log-uniform [1e-2, 1e2], random order, FP64 factor and
-               FP64 PCG
+  chung_lu_22  default: Chung-Lu power-law Laplacian, 2^22 vertices generated
+               (largest component kept, 4,117,731 vertices), average degree
+               16, exponent 2.1, weights (0,1], random order: FP64 factor and
+               FP64 PCG timed; after the timed steps one solve with the
+               preconditioner applied from the FP32 copy (SpMV / dots /
+               residuals in FP64) is reported beside it
+  grid3d_128   3D 7-point Laplacian 128^3 (2,097,152 vertices), weights
+               log-uniform [1e-2, 1e2], random order, FP64 factor and FP64 PCG
   grid2d_64    2D 5-point Laplacian 64x64, weights U[1,2] (small case)
-  chung_lu_22  Chung-Lu power-law Laplacian, 2^22 vertices generated (largest
-               component kept), average degree 16, exponent 2.1, weights
-               (0,1]: FP64 factor, preconditioner applied from its FP32 copy,
-               SpMV / dots / residuals in FP64
   chung_lu_24_x32  Chung-Lu 2^24, average degree 8, 32 right-hand sides:
                block PCG with the FP32 apply
   serve_200    200 SDDM systems (sizes log-uniform 1e3..1e6, mixed families)
                with Poisson arrivals, served with continuous batching (mixed
                precision) and, for comparison, one at a time in FP64
+
+--order nnz replaces the random elimination order of a single-system
+workload by the NNZ-sorted one (ascending row count, random ties; the
+ordering the paper recommends for GPUs).
 """
 import argparse
 import json
@@ -33,10 +38,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "setup+solve s to 1e-6 rel. residual; factor nnz/s; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of the apply measured with rocprofv3 counters (FETCH_SIZE,
+# HBM traffic of a kernel measured with rocprofv3 counters (FETCH_SIZE,
 # WRITE_SIZE), scaled by the same counters on a copy of known size; valid only
-# for the kernel sources it was taken from
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ready_traffic_grid3d_128.md")
+# for the kernel sources and the workload it was taken from
+TRAFFIC_PROFILES = {
+    ("chung_lu_22", "fwd64"): os.path.join(ROOT, "profiles", "k_ready_fwd_traffic_chung_lu_22.md"),
+    ("grid3d_128", "fwd64"): os.path.join(ROOT, "profiles", "k_ready_fwd_traffic_grid3d_128.md"),
+}
 SWEEP_SOURCES = ["ready.hip", "internal.hpp", "device.hpp"]
 
 
@@ -49,15 +57,16 @@ def sweep_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per apply from the committed counter summary, if it was taken
-    on this workload from the current sweep sources; else None."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on this workload from the current sweep sources; else None."""
     import re
-    if workload != "grid3d_128" or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get((workload, kernel))
+    if path is None or not os.path.exists(path):
         return None
-    text = open(TRAFFIC_PROFILE).read()
+    text = open(path).read()
     m1 = re.search(r"sweep-sources-sha256:\s*([0-9a-f]{64})", text)
-    m2 = re.search(r"hbm-bytes-per-apply:\s*([0-9]+)", text)
+    m2 = re.search(r"hbm-bytes-per-launch:\s*([0-9]+)", text)
     if not (m1 and m2) or m1.group(1) != sweep_source_hash():
         return None
     return int(m2.group(1))
@@ -67,54 +76,84 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Algorithmic bytes: what the method has to move, with 4-byte indices and
+# 8-byte values (4-byte values in the FP32 apply).
 def elim_bytes(E, n_fill, n_off, N):
-    """Algorithmic bytes of one elimination: the upper adjacency read once
-    (4 B index + 8 B weight per edge), every fill record written and read
-    (16 B each way) with its counter increment (8 B read-modify-write), every
-    factor entry written (12 B) with its counter decrement (8 B), and D,
-    queue slot and column offset per pivot (24 B)."""
+    """One elimination: the upper adjacency read once (12 B per edge), every
+    fill record written and read (16 B each way) with its counter increment
+    (8 B read-modify-write), every factor entry written (12 B) with its
+    counter decrement (8 B), and D, queue slot and column offset per pivot
+    (24 B)."""
     return 12 * E + 40 * n_fill + 20 * n_off + 24 * N
 
 
-def apply_bytes(n_off, N, elem=8):
-    """Algorithmic bytes of one preconditioner apply: each solve reads every
-    off-diagonal entry once (4 B index + value) and gathers one vector value
-    per entry; per row, the forward solve reads its entry offset (8 B), source
-    index (4 B) and right-hand side (8 B) and writes y; the backward solve
-    reads its offset, D^+ and y, writes x and z (8 B) and reads its source
-    index."""
-    return 2 * n_off * (4 + 2 * elem) + N * (8 + 4 + 8 + elem) + N * (8 + elem + elem + elem + 8 + 4)
+def fwd_bytes(n_off, N, elem=8):
+    """The forward sweep F y = P r: every off-diagonal entry once (4 B index
+    + value), and per row r read and y written (vector terms 20 N in FP64,
+    halved in FP32)."""
+    return n_off * (4 + elem) + (20 * N if elem == 8 else 10 * N)
 
 
-def roofline(info, apply_ms, n_applies, ms_elim, elem, workload):
-    """The dominant unit of a step (elimination or applies, by time) against
-    the HBM peak."""
+def bwd_bytes(n_off, N, elem=8):
+    """The backward sweep F^T x = D^+ y: every entry once, and per row D^+,
+    y read, x and z written (28 N in FP64, halved in FP32)."""
+    return n_off * (4 + elem) + (28 * N if elem == 8 else 14 * N)
+
+
+def pcg_iter_bytes(nnz_L, n_off, N, elem=8):
+    """One PCG iteration: SpMV with L (12 B per stored entry), both sweeps,
+    and the vector traffic of the recurrence: SpMV 20N, r^T z 8N, three
+    axpys 72N (plus the sweeps' own vector terms)."""
+    return 12 * nnz_L + fwd_bytes(n_off, N, elem) + bwd_bytes(n_off, N, elem) + 100 * N
+
+
+def rl_entry(name, nbytes, ms, traffic=None):
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    e = {"kernel": name, "achieved": round(achieved, 2), "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 5), "algorithmic_bytes": int(nbytes),
+         "avg_ms": round(ms, 4)}
+    if traffic is not None:
+        e["traffic"] = traffic
+    return e
+
+
+def roofline(info, timing, elem, workload):
+    """The dominant single kernel of a step (by time) against the HBM peak,
+    with the other kernels of the hot path beside it."""
     N, n_off = info["n"], info["nnz_off"]
-    eb = elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N)
-    ab = apply_bytes(n_off, N, elem)
-    if ms_elim >= apply_ms * n_applies:
-        unit, nbytes, ms = "k_eliminate (one factorisation, one persistent launch)", eb, ms_elim
-    else:
-        unit, nbytes, ms = ("preconditioner apply (k_ready forward and backward sweeps, one "
-                            "launch each)"), ab, apply_ms
-    achieved = nbytes / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(workload) if unit.startswith("preconditioner") else None
-    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": unit,
-            "algorithmic_bytes": int(nbytes), "avg_ms": round(ms, 4)}
+    tag = "64" if elem == 8 else "32"
+    T = "double" if elem == 8 else "float"
+    fwd = rl_entry("k_ready<%s, false> (forward sweep F y = P r, one launch)" % T,
+                   fwd_bytes(n_off, N, elem), timing["fwd_ms"],
+                   measured_traffic(workload, "fwd" + tag))
+    bwd = rl_entry("k_ready<%s, true> (backward sweep F^T x = D^+ y, one launch)" % T,
+                   bwd_bytes(n_off, N, elem), timing["bwd_ms"])
+    elim = rl_entry("k_eliminate (one factorisation, one persistent launch)",
+                    elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N), timing["elim_ms"])
+    per_step = {"fwd": timing["fwd_ms"] * timing["applies"],
+                "bwd": timing["bwd_ms"] * timing["applies"], "elim": timing["elim_ms"]}
+    dom = max(per_step, key=per_step.get)
+    d = {"fwd": fwd, "bwd": bwd, "elim": elim}[dom]
+    out = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": d["frac"], "traffic": d.get("traffic"), "kernel": d["kernel"],
+           "algorithmic_bytes": d["algorithmic_bytes"], "avg_ms": d["avg_ms"],
+           "limited_by": ("dependency latency: the elimination DAG depth (%d levels) times the "
+                          "per-level publish-to-detect latency, not bandwidth" % info["depth"]),
+           "others": [e for k, e in (("fwd", fwd), ("bwd", bwd), ("elim", elim)) if k != dom]}
+    return out
 
 
 # --------------------------------------------------------------------------
 # single system (optionally several right-hand sides)
 # --------------------------------------------------------------------------
-def run_system(args, W, desc, precision, nrhs):
+def run_system(args, W, desc, precision, nrhs, mixed_extra=False):
     import numpy as np
     import torch
     from paper_2505_02977_amd import parac
     dA = parac.DeviceCSR(W.A)
     b = torch.tensor(W.b, device="cuda")
     x = torch.empty_like(b)
-    keep32 = precision == parac.PREC_MIXED
+    keep32 = precision == parac.PREC_MIXED or mixed_extra
     torch.cuda.synchronize()
 
     def step(timing):
@@ -122,17 +161,19 @@ def run_system(args, W, desc, precision, nrhs):
         log("  factor: %.1f ms" % f.info()["ms_total"])
         sts = parac.parac_pcg(dA, f, b, x, rtol=args.rtol, precision=precision, timing=timing)
         info = f.info()
-        del f
-        return info, sts
+        return f, info, sts
 
     for k in range(args.warmup):
         log("warmup step %d" % k)
-        step(False)
+        f, _, _ = step(False)
+        del f
     torch.cuda.synchronize()
     infos, stss = [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        info, sts = step(True)
+        f, info, sts = step(True)
+        if k + 1 < args.steps:
+            del f
         infos.append(info)
         stss.append(sts)
         log("step %d: setup %.1f ms solve %.1f ms it %d" % (k, info["ms_total"], sts[0]["ms_total"],
@@ -150,22 +191,22 @@ def run_system(args, W, desc, precision, nrhs):
     applies = float(np.mean([s[0]["applies"] for s in stss]))
     ms_apply = float(np.mean([sum(s[c]["ms_apply"] / max(s[c]["applies"], 1) for c in chunks)
                               for s in stss]))
+    ms_fwd = float(np.mean([s[0]["ms_fwd"] / max(s[0]["applies"], 1) for s in stss]))
     N, n_off = info["n"], info["nnz_off"]
     elem = 4 if precision == parac.PREC_MIXED else 8
-    rl = roofline(info, ms_apply, applies, ms_elim, elem, args.workload)
-    if nrhs > 1:
-        rl["note"] = ("block apply: algorithmic bytes counted as for one column (factor read once), "
-                      "the %d-column vector traffic comes on top" % nrhs)
+    timing = {"fwd_ms": ms_fwd, "bwd_ms": ms_apply - ms_fwd, "elim_ms": ms_elim, "applies": applies}
     X = x.cpu().numpy()
     Bh = W.b
-    resid = W.A.to_scipy() @ X - Bh
+    L = W.A.to_scipy()
+    resid = L @ X - Bh
     rel = np.linalg.norm(resid.reshape(N, -1), axis=0) / np.linalg.norm(Bh.reshape(N, -1), axis=0)
+    iters = max(s["iterations"] for s in sts)
     out = {
         "value": round((ms_setup + ms_solve) / 1e3, 6),
         "ms_per_step": round(ms_step, 3),
         "dtype": "f64" if precision == parac.PREC_FP64 else "f64 (apply f32)",
         "config": {"workload": desc, "n": N, "nnz_L": int(W.A.nnz), "rhs": nrhs,
-                   "seed": int(W.seed), "parallelism": "one GPU"},
+                   "seed": int(W.seed), "order": args.order, "parallelism": "one GPU"},
         "t_setup_s": round(ms_setup / 1e3, 6),
         "t_solve_s": round(ms_solve / 1e3, 6),
         "t_eliminate_s": round(ms_elim / 1e3, 6),
@@ -174,12 +215,44 @@ def run_system(args, W, desc, precision, nrhs):
         "n_fill": info["n_fill"],
         "depth": info["depth"],
         "max_gather": info["max_gather"],
-        "iterations": max(s["iterations"] for s in sts),
+        "iterations": iters,
         "true_relres_max": float(rel.max()),
         "apply_ms": round(ms_apply, 4),
+        "fwd_sweep_ms": round(ms_fwd, 4),
         "workers": info["workers"],
-        "roofline": rl,
     }
+    if nrhs == 1:
+        pcg_b = pcg_iter_bytes(int(W.A.nnz), n_off, N, elem)
+        out["pcg_iteration"] = rl_entry("PCG iteration (SpMV, both sweeps, dots, axpys)", pcg_b,
+                                        ms_solve / max(iters, 1))
+    rl = roofline(info, timing, elem, args.workload if args.order == "random" else None)
+    if nrhs > 1:
+        rl["note"] = ("block apply: the sweeps' bytes counted as for one column; each of the %d "
+                      "columns runs its own sweep pair in the same launch" % nrhs)
+    out["roofline"] = rl
+    if mixed_extra:
+        # the same factor, preconditioner applied from its FP32 copy (not timed
+        # in the steps: one solve after them)
+        xm = torch.empty_like(b)
+        sm = parac.parac_pcg(dA, f, b, xm, rtol=args.rtol, precision=parac.PREC_MIXED,
+                             timing=True)[0]
+        Xm = xm.cpu().numpy()
+        relm = np.linalg.norm(L @ Xm - Bh) / np.linalg.norm(Bh)
+        xp, xmp = X - X.mean(), Xm - Xm.mean()
+        out["mixed"] = {
+            "t_solve_s": round(sm["ms_total"] / 1e3, 6),
+            "value_s": round((ms_setup + sm["ms_total"]) / 1e3, 6),
+            "iterations": sm["iterations"],
+            "apply_ms": round(sm["ms_apply"] / max(sm["applies"], 1), 4),
+            "true_relres": float(relm),
+            "rel_err_vs_fp64_solution": float(np.linalg.norm(xmp - xp) / np.linalg.norm(xp)),
+            "note": ("FP32 preconditioner apply, FP64 SpMV/dots/residuals, same factor; error "
+                     "against this run's FP64 solution, which the parity tests tie to the oracle's "
+                     "to 1e-8"),
+        }
+        log("mixed: solve %.1f ms, %d iterations, error vs FP64 %.2e" % (
+            sm["ms_total"], sm["iterations"], out["mixed"]["rel_err_vs_fp64_solution"]))
+    del f
     return out
 
 
@@ -270,32 +343,61 @@ def run_serve(args):
 
 
 # --------------------------------------------------------------------------
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
 def cpu_baseline(name, W, rtol):
-    """The CPU oracle as it stands, one core: the full workload for the grid
-    cases, a bounded sample otherwise."""
+    """The CPU oracle as it stands, pinned to one core of the host: the full
+    workload for the grid cases, a bounded sample of the same family for the
+    power-law ones (scaled by stored entries to the full size)."""
     import oracle
     oracle.build()
-    if name in ("grid3d_128", "grid2d_64"):
-        t0 = time.perf_counter()
-        f = oracle.factor(W.A, perm=W.perm, seed=W.seed)
-        t1 = time.perf_counter()
-        x, st = oracle.pcg(W.A, f, W.b, rtol=rtol)
-        t2 = time.perf_counter()
-        return dict(value=round(t2 - t0, 3), unit="s", cores=1, kind="oracle",
-                    sample="the full workload, one run: factor %.2f s + PCG %.2f s (%d iterations)"
-                    % (t1 - t0, t2 - t1, st["iterations"]))
-    from paper_2505_02977_amd import inputs
-    S = inputs.chung_lu_workload(16, dbar=16.0 if name == "chung_lu_22" else 8.0)
-    t0 = time.perf_counter()
-    f = oracle.factor(S.A, perm=S.perm, seed=S.seed)
-    t1 = time.perf_counter()
-    x, st = oracle.pcg(S.A, f, S.b, rtol=rtol, precision=1)
-    t2 = time.perf_counter()
-    scale = W.A.nnz / S.A.nnz
-    return dict(value=round((t2 - t0) * scale, 3), unit="s", cores=1, kind="oracle",
-                sample="Chung-Lu 2^16 of the same family (nnz %d), factor %.2f s + PCG %.2f s "
-                       "(%d iterations, FP32 apply), scaled by nnz to the full workload (%.0fx); "
-                       "one right-hand side" % (S.A.nnz, t1 - t0, t2 - t1, st["iterations"], scale))
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})  # this thread only: the oracle is single-threaded C
+    try:
+        if name in ("grid3d_128", "grid2d_64"):
+            t0 = time.perf_counter()
+            f = oracle.factor(W.A, perm=W.perm, seed=W.seed)
+            t1 = time.perf_counter()
+            x, st = oracle.pcg(W.A, f, W.b, rtol=rtol)
+            t2 = time.perf_counter()
+            value = t2 - t0
+            sample = ("the full workload, one run: factor %.2f s + FP64 PCG %.2f s (%d iterations)"
+                      % (t1 - t0, t2 - t1, st["iterations"]))
+        else:
+            from paper_2505_02977_amd import inputs
+            ncol = 32 if name == "chung_lu_24_x32" else 1
+            S = inputs.chung_lu_workload(18, dbar=16.0 if name == "chung_lu_22" else 8.0)
+            prec = 0 if name == "chung_lu_22" else 1
+            t0 = time.perf_counter()
+            f = oracle.factor(S.A, perm=S.perm, seed=S.seed)
+            t1 = time.perf_counter()
+            x, st = oracle.pcg(S.A, f, S.b, rtol=rtol, precision=prec)
+            t2 = time.perf_counter()
+            scale = W.A.nnz / S.A.nnz
+            value = ((t1 - t0) + ncol * (t2 - t1)) * scale
+            sample = ("Chung-Lu 2^18 of the same family (n %d, nnz %d): factor %.2f s + %s PCG "
+                      "%.2f s (%d iterations)%s, scaled by stored entries to the full workload "
+                      "(x%.1f); the oracle's cost grows faster than nnz on power-law graphs, so "
+                      "this understates it" % (S.A.n, S.A.nnz, t1 - t0,
+                                               "FP64" if prec == 0 else "FP32-apply", t2 - t1,
+                                               st["iterations"],
+                                               " x %d columns" % ncol if ncol > 1 else "", scale))
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    return dict(value=round(value, 3), unit="s", cores=1, kind="oracle", sample=sample,
+                pinned_core=core, host_cpu=host_cpu(), host_cores=len(allowed))
 
 
 def main():
@@ -303,8 +405,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid3d_128")
+    ap.add_argument("--workload", default="chung_lu_22")
+    ap.add_argument("--order", choices=["random", "nnz"], default="random")
     ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--precision", choices=["default", "fp64", "mixed"], default="default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=32)
@@ -336,30 +440,39 @@ def main():
         args.steps, args.warmup = 1, 0
     else:
         log("generating %s" % name)
+        fp64 = args.precision == "fp64"
+        mixed = args.precision == "mixed"
         if name == "grid3d_128":
             W = inputs.grid3d_workload(128)
             desc = ("grid3d_128: 3D 7-point Laplacian 128^3, weights log-uniform [1e-2,1e2], "
-                    "random order, FP64 factor + FP64 PCG to 1e-6")
-            out = run_system(args, W, desc, parac.PREC_FP64, 1)
+                    "%s order, FP64 factor + %s PCG to 1e-6")
+            prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
         elif name == "grid2d_64":
             W = inputs.grid2d_workload(64)
-            desc = ("grid2d_64: 2D 5-point Laplacian 64x64, weights U[1,2], random order, "
-                    "FP64 factor + FP64 PCG to 1e-6")
-            out = run_system(args, W, desc, parac.PREC_FP64, 1)
+            desc = ("grid2d_64: 2D 5-point Laplacian 64x64, weights U[1,2], %s order, "
+                    "FP64 factor + %s PCG to 1e-6")
+            prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
         elif name == "chung_lu_22":
             W = inputs.chung_lu_workload(22)
             desc = ("chung_lu_22: Chung-Lu Laplacian, 2^22 generated (largest component %d), "
-                    "avg degree 16, exponent 2.1, weights (0,1], random order; FP64 factor, "
-                    "FP32 copy for the apply, FP64 SpMV/dots/residuals, to 1e-6" % W.A.n)
-            out = run_system(args, W, desc, parac.PREC_MIXED, 1)
+                    "avg degree 16, exponent 2.1, weights (0,1], %%s order; FP64 factor + %%s PCG "
+                    "to 1e-6" % W.A.n)
+            prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
         elif name == "chung_lu_24_x32":
             W = inputs.chung_lu_workload(24, dbar=8.0, nrhs=32)
             desc = ("chung_lu_24_x32: Chung-Lu Laplacian, 2^24 generated (largest component %d), "
-                    "avg degree 8, exponent 2.1, weights (0,1], 32 right-hand sides; FP64 factor, "
-                    "block PCG with the FP32 apply" % W.A.n)
-            out = run_system(args, W, desc, parac.PREC_MIXED, 32)
+                    "avg degree 8, exponent 2.1, weights (0,1], %%s order, 32 right-hand sides; "
+                    "FP64 factor + %%s block PCG to 1e-6" % W.A.n)
+            prec = parac.PREC_FP64 if fp64 else parac.PREC_MIXED
         else:
             raise SystemExit("unknown workload " + name)
+        if args.order == "nnz":
+            W = inputs.with_nnz_order(W)
+        pdesc = "FP64" if prec == parac.PREC_FP64 else "FP32-apply (FP64 SpMV/dots/residuals)"
+        desc = desc % (args.order, pdesc)
+        nrhs = 32 if name == "chung_lu_24_x32" else 1
+        out = run_system(args, W, desc, prec, nrhs,
+                         mixed_extra=(name == "chung_lu_22" and prec == parac.PREC_FP64))
     line = {
         "metric": METRIC,
         "value": out.pop("value"),

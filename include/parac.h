@@ -192,6 +192,8 @@ typedef struct {
   double ms_apply;        /* preconditioner applies (both triangular solves)
                              when timing = 1, else 0                        */
   int32_t applies;        /* preconditioner applies performed               */
+  double ms_fwd;          /* of ms_apply, the forward sweeps (F y = P r) of
+                             a single right-hand side; 0 for blocks         */
 } parac_pcg_stats;
 
 /* Preconditioned conjugate gradients with x0 = 0 (§V methodology; the
@@ -259,6 +261,42 @@ typedef struct {
  * out[i].status. */
 parac_status parac_serve(const parac_request *reqs, int64_t n,
                          const parac_serve_opts *o, parac_result *out);
+
+/* A factor built on the host CPU by parac_factor_host: canonical CSC of F
+ * in label space, D, levels, sizes.  The arrays are malloc'd by the library
+ * and released by parac_host_factor_free. */
+typedef struct {
+  int64_t n, ntot;        /* order; order incl. ground vertex               */
+  int32_t mode;           /* resolved mode                                  */
+  int32_t threads;        /* worker threads used                            */
+  int64_t nnz_off;        /* strictly-lower entries of F                    */
+  int64_t n_fill;         /* sampled fill records                           */
+  int64_t depth;          /* levels of the elimination dependency DAG       */
+  int64_t *colptr;        /* [ntot+1]                                       */
+  int32_t *rowind;        /* [nnz_off], rows ascending within a column      */
+  double *val;            /* [nnz_off]                                      */
+  double *D;              /* [ntot]                                         */
+  int32_t *level;         /* [ntot]                                         */
+  double ms_total;        /* wall time of the call                          */
+} parac_host_factor;
+
+/* The same factorisation on the host's CPU cores: the paper's CPU design
+ * (§IV-B, Alg. 3), worker threads that claim ready pivots from a shared
+ * queue scheduled by the §III dependency counters.  Same readings and
+ * arithmetic as parac_factor, so the result equals parac_factor_export's bit
+ * for bit for any thread count.  This is a separate CPU implementation that
+ * a caller asks for by name; no GPU entry point calls it.
+ *   A        host matrix (on_device must be 0)
+ *   o        options (NULL = defaults); perm is a host pointer; workers,
+ *            keep_fp32, timeout_s and tail_fraction are ignored
+ *   threads  worker threads (0 = the host's hardware threads)
+ *   out      filled on success; release with parac_host_factor_free
+ * Errors: EINVAL, ENOTLAP, ENOMEM, EINTERNAL (EPOOL is retried inside);
+ * the message is in parac_host_last_error(). */
+parac_status parac_factor_host(const parac_csr *A, const parac_factor_opts *o,
+                               int32_t threads, parac_host_factor *out);
+void parac_host_factor_free(parac_host_factor *f);
+const char *parac_host_last_error(void);
 
 void parac_factor_free(parac_factor_t f);
 const char *parac_status_str(parac_status s);

@@ -43,10 +43,13 @@
  *  R9  D_k = 0 for an empty neighbourhood; the apply uses D^+.
  *  R10 apply (§V uses vendor triangular solves, whose summation order is
  *      not given): a row of F y = P r or F^T x = D^+ y with start value s
- *      and products p_1..p_m in ascending column order is summed in chunks
- *      of 64 consecutive products; each chunk sum is a left fold from its
- *      first product, and the row value is s minus the chunk sums, folded
- *      left in chunk order: ((s - c_1) - c_2) - ...
+ *      and products p_1..p_m in ascending column order is the left fold
+ *      ((s - p_1) - p_2) - ... - p_m.  Other summation orders (the GPU
+ *      library's chunked one among them) agree with it to rounding.
+ *  R17 mixed precision (FP32 preconditioner apply): D^+_i = 1/D_i is
+ *      formed in FP64 and rounded to FP32; factor values are rounded to FP32;
+ *      r is rounded to FP32 on entry and z widened to FP64 on exit; every
+ *      product and difference of the two solves is an FP32 operation.
  */
 #include "parac_oracle.h"
 
@@ -666,32 +669,27 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
-/* Preconditioner apply (R9, R10)                                           */
+/* Preconditioner apply (R9, R10, R17)                                      */
 /* ------------------------------------------------------------------------ */
-#define ORC_CHUNK 64
-
-/* one row of a triangular solve (R10): s minus the sum of
- * val[e] * vec[idx[e]] over e in [b, e1), in chunks of ORC_CHUNK products */
+/* one row of a triangular solve (R10): start from s and subtract the
+ * products val[e] * vec[idx[e]] one at a time, e ascending (a left fold in
+ * ascending column order, the plain definition of substitution) */
 static double orc_row64(double s, int64_t b, int64_t e1, const int32_t *idx,
                         const double *val, const double *vec) {
   double acc = s;
-  for (int64_t a = b; a < e1; a += ORC_CHUNK) {
-    int64_t end = a + ORC_CHUNK < e1 ? a + ORC_CHUNK : e1;
-    double c = val[a] * vec[idx[a]];
-    for (int64_t e = a + 1; e < end; ++e) c = c + val[e] * vec[idx[e]];
-    acc = acc - c;
-  }
+  for (int64_t e = b; e < e1; ++e) acc = acc - val[e] * vec[idx[e]];
   return acc;
 }
 
+/* the same in FP32 (R17): each factor value is rounded to FP32 before it is
+ * used, every product and every difference is rounded to FP32 */
 static float orc_row32(float s, int64_t b, int64_t e1, const int32_t *idx,
                        const double *val, const float *vec) {
   float acc = s;
-  for (int64_t a = b; a < e1; a += ORC_CHUNK) {
-    int64_t end = a + ORC_CHUNK < e1 ? a + ORC_CHUNK : e1;
-    float c = (float)val[a] * vec[idx[a]];
-    for (int64_t e = a + 1; e < end; ++e) c = c + (float)val[e] * vec[idx[e]];
-    acc = acc - c;
+  for (int64_t e = b; e < e1; ++e) {
+    float v = (float)val[e];
+    float prod = v * vec[idx[e]];
+    acc = acc - prod;
   }
   return acc;
 }
@@ -736,7 +734,8 @@ int orc_apply32(const orc_factor_result *f, const int32_t *perm,
     y[i] = orc_row32(y[i], f->rowptr_f[i], f->rowptr_f[i + 1], f->colind_f, f->val_f, y);
   for (int64_t i = n - 1; i >= 0; --i) {
     float dinv = (float)(f->D[i] > 0.0 ? 1.0 / f->D[i] : 0.0);
-    y[i] = orc_row32(dinv * y[i], f->colptr[i], orc_col_end(f, i), f->rowind, f->val, y);
+    float start = dinv * y[i];
+    y[i] = orc_row32(start, f->colptr[i], orc_col_end(f, i), f->rowind, f->val, y);
   }
   for (int64_t v = 0; v < n; ++v) z[v] = (double)y[perm ? perm[v] : v];
   free(y);

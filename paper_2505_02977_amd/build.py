@@ -19,6 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libparac.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["setup.hip", "eliminate.hip", "finalize.hip", "solve.hip", "block.hip", "serve.hip", "ready.hip", "api.hip"]
+# host-only C++ (the CPU elimination): built with g++, no GPU code
+HOST_SOURCES = ["host_parac.cpp"]
 ARCH = os.environ.get("PARAC_ARCH", "gfx950")
 
 
@@ -37,9 +39,16 @@ FLAGS = [
 ]
 
 
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-pthread",
+              "-Wall", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [shutil.which("g++") or "g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
@@ -49,14 +58,14 @@ def _compile(src):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(_compile, SOURCES + HOST_SOURCES))
     objs = [o for o, _ in results]
     if verbose:
         for _, err in results:
             if err.strip():
                 sys.stderr.write(err)
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))

@@ -144,6 +144,8 @@ static int64_t tail_start(parac_factor_t f, int64_t rows) {
 // ---------------------------------------------------------------------------
 // factor
 // ---------------------------------------------------------------------------
+static void ensure_work(parac_factor_t f, int prec, hipStream_t s);
+
 static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o, hipStream_t s) {
   if (!A) throw Err{PARAC_EINVAL, "null matrix"};
   const int64_t n = A->n, nnz = A->nnz;
@@ -631,6 +633,11 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
                   (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
                   (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
     if (p) F->bytes += tmp.keep(p, F->owned);
+  // the sweeps' work vectors, so that solving with the factor needs no
+  // further device allocation
+  ensure_work(F, PARAC_PREC_FP64, s);
+  if (opt.keep_fp32) ensure_work(F, PARAC_PREC_MIXED, s);
+  chk(hipStreamSynchronize(s), "sync");
   guard.ok = true;
   return F;
 }
@@ -826,13 +833,16 @@ static bool shape_ok(const parac_block_shape &c) {
 // ---------------------------------------------------------------------------
 // PCG (one right-hand side; several columns run as independent recurrences)
 // ---------------------------------------------------------------------------
-static void check_consistent(parac_factor_t f, const double *b, hipStream_t s) {
+// sum, sabs (ntot entries each) and bad may come from the caller; else they
+// are allocated here
+static void check_consistent(parac_factor_t f, const double *b, hipStream_t s,
+                             double *sum = nullptr, double *sabs = nullptr, int *bad = nullptr) {
   const int64_t n = f->n;
   if (n == 0) return;
   Scratch tmp;
-  double *sum = tmp.alloc<double>(f->ntot, "sums");
-  double *sabs = tmp.alloc<double>(f->ntot, "sums");
-  int *bad = tmp.alloc<int>(1, "flag");
+  if (!sum) sum = tmp.alloc<double>(f->ntot, "sums");
+  if (!sabs) sabs = tmp.alloc<double>(f->ntot, "sums");
+  if (!bad) bad = tmp.alloc<int>(1, "flag");
   chk(hipMemsetAsync(sum, 0, f->ntot * sizeof(double), s), "memset");
   chk(hipMemsetAsync(sabs, 0, f->ntot * sizeof(double), s), "memset");
   chk(hipMemsetAsync(bad, 0, sizeof(int), s), "memset");
@@ -842,10 +852,22 @@ static void check_consistent(parac_factor_t f, const double *b, hipStream_t s) {
     throw Err{PARAC_EINCONSISTENT, "b has a nonzero sum on a component without excess"};
 }
 
+// device memory for the tables of a batch of one system, when the caller
+// provides it (else the tables are allocated in Batch::mem)
+struct TableMem {
+  PcgSlot *slots = nullptr;
+  int32_t *bslot = nullptr;
+  int64_t bslot_cap = 0;
+  ApplySlot *aslots = nullptr;
+  int32_t *wgmap = nullptr;
+  int64_t wgmap_cap = 0;
+};
+
 // device tables of one batch of systems (see serve.hip)
 struct Batch {
   Scratch mem;
   SlotBatch B;
+  const TableMem *pre = nullptr;
 };
 
 struct SlotView {
@@ -871,8 +893,17 @@ static void build_apply_tables(Batch &bt, const std::vector<ApplySlot> &as,
   for (int32_t r = 0; r < gmax; ++r)
     for (int k = 0; k < ns; ++k)
       if (r < g[k]) map.push_back(k);
-  ApplySlot *das = bt.mem.alloc<ApplySlot>(ns, "batch apply slots");
-  int32_t *dmap = bt.mem.alloc<int32_t>(std::max<int64_t>((int64_t)map.size(), 1), "sweep map");
+  ApplySlot *das;
+  int32_t *dmap;
+  if (bt.pre) {
+    if (ns != 1 || (int64_t)map.size() > bt.pre->wgmap_cap)
+      throw Err{PARAC_EINTERNAL, "caller-provided batch tables too small"};
+    das = bt.pre->aslots;
+    dmap = bt.pre->wgmap;
+  } else {
+    das = bt.mem.alloc<ApplySlot>(ns, "batch apply slots");
+    dmap = bt.mem.alloc<int32_t>(std::max<int64_t>((int64_t)map.size(), 1), "sweep map");
+  }
   chk(hipMemcpyAsync(das, as.data(), ns * sizeof(ApplySlot), hipMemcpyHostToDevice, s), "upload");
   if (!map.empty())
     chk(hipMemcpyAsync(dmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
@@ -913,8 +944,17 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     as[k].ctr = f->ctr;
     as[k].z = ps[k].z;
   }
-  PcgSlot *dps = bt.mem.alloc<PcgSlot>(ns, "batch slots");
-  int32_t *dbs = bt.mem.alloc<int32_t>(blk, "batch block map");
+  PcgSlot *dps;
+  int32_t *dbs;
+  if (bt.pre) {
+    if (ns != 1 || blk > bt.pre->bslot_cap)
+      throw Err{PARAC_EINTERNAL, "caller-provided batch tables too small"};
+    dps = bt.pre->slots;
+    dbs = bt.pre->bslot;
+  } else {
+    dps = bt.mem.alloc<PcgSlot>(ns, "batch slots");
+    dbs = bt.mem.alloc<int32_t>(blk, "batch block map");
+  }
   chk(hipMemcpyAsync(dps, ps.data(), ns * sizeof(PcgSlot), hipMemcpyHostToDevice, s), "upload");
   chk(hipMemcpyAsync(dbs, bslot.data(), bslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
       "upload");
@@ -991,24 +1031,28 @@ static void apply_cols(parac_factor_t f, int nc, const double *r, int64_t ldr, d
   check_col_sweeps(f, prec, s);
 }
 
+// device memory of one single-vector PCG: vectors r, z, p, q (n each),
+// block partial sums (slot_blocks(n)), 8 scalars, 4 flags, and optionally
+// the batch tables
+struct PcgWork {
+  double *r, *z, *p, *q, *partial, *dst;
+  int *ist;
+  const TableMem *tables;
+};
+
 // one system as a batch of one: the same launches, hence the same bits, as
 // when the system is served together with others
-static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double *x,
-                   const parac_pcg_opts &o, parac_pcg_stats *st, hipStream_t s) {
+static int pcg_run(const parac_csr *A, parac_factor_t f, const double *b, double *x,
+                   const parac_pcg_opts &o, parac_pcg_stats *st, hipStream_t s, const PcgWork &w) {
   const int64_t n = f->n;
-  Scratch tmp;
-  double *r = tmp.alloc<double>(n, "r");
-  double *z = tmp.alloc<double>(n, "z");
-  double *p = tmp.alloc<double>(n, "p");
-  double *q = tmp.alloc<double>(n, "q");
-  double *partial = tmp.alloc<double>(slot_blocks(n), "partials");
-  double *dst = tmp.alloc<double>(8, "pcg scalars");
-  int *ist = tmp.alloc<int>(4, "pcg flags");
+  double *r = w.r, *z = w.z, *p = w.p, *q = w.q, *partial = w.partial, *dst = w.dst;
+  int *ist = w.ist;
   const double hst0[8] = {0, 0, 0, 0, 0, 0, o.rtol, 0};
   const int hist0[4] = {0, 0, o.maxit, 0};
   chk(hipMemcpyAsync(dst, hst0, sizeof(hst0), hipMemcpyHostToDevice, s), "upload");
   chk(hipMemcpyAsync(ist, hist0, sizeof(hist0), hipMemcpyHostToDevice, s), "upload");
   Batch bt;
+  bt.pre = w.tables;
   build_batch(bt, {SlotView{PcgSlot{n, A->rowptr, A->col, A->val, b, x, r, z, p, q, dst, ist, 0, 0},
                             f}},
               o.precision, partial, s);
@@ -1028,11 +1072,26 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
     chk(hipEventRecord(e, s), "hipEventRecord");
     evs.push_back(e);
   };
+  // events between the two sweeps of every timed apply
+  std::vector<hipEvent_t> mids;
+  struct MidFree {
+    std::vector<hipEvent_t> &v;
+    ~MidFree() {
+      for (auto e : v) (void)hipEventDestroy(e);
+    }
+  } midfree{mids};
+  auto mid = [&]() -> hipEvent_t {
+    if (!o.timing) return nullptr;
+    hipEvent_t e;
+    chk(hipEventCreate(&e), "hipEventCreate");
+    mids.push_back(e);
+    return e;
+  };
   mark(true);  // evs[0]: start
   chk(slots_init(B, s), "pcg init");
   int applies = 0;
   mark(false);
-  chk(slots_apply(B, o.precision, s), "apply");
+  chk(slots_apply(B, o.precision, s, mid()), "apply");
   mark(false);
   ++applies;
   chk(slots_rz(B, 1, s), "pcg rz");
@@ -1045,7 +1104,7 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
     for (int it = 0; it < chunk; ++it) {
       chk(slots_step(B, s), "pcg step");
       mark(false);
-      chk(slots_apply(B, o.precision, s), "apply");
+      chk(slots_apply(B, o.precision, s, mid()), "apply");
       mark(false);
       ++applies;
       chk(slots_rz(B, 0, s), "pcg rz");
@@ -1075,13 +1134,35 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
     chk(hipEventElapsedTime(&ms, evs.front(), evs.back()), "elapsed");
     st->ms_total = ms;
     st->ms_apply = 0.0;
+    st->ms_fwd = 0.0;
     st->applies = ran;
     for (size_t i = 1; i + 2 < evs.size() && (int)((i - 1) / 2) < ran; i += 2) {
       chk(hipEventElapsedTime(&ms, evs[i], evs[i + 1]), "elapsed");
       st->ms_apply += ms;
+      const size_t k = (i - 1) / 2;
+      if (k < mids.size()) {
+        chk(hipEventElapsedTime(&ms, evs[i], mids[k]), "elapsed");
+        st->ms_fwd += ms;
+      }
     }
   }
   return ok ? PARAC_OK : PARAC_ENOCONV;
+}
+
+static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double *x,
+                   const parac_pcg_opts &o, parac_pcg_stats *st, hipStream_t s) {
+  const int64_t n = f->n;
+  Scratch tmp;
+  PcgWork w{};
+  w.r = tmp.alloc<double>(n, "r");
+  w.z = tmp.alloc<double>(n, "z");
+  w.p = tmp.alloc<double>(n, "p");
+  w.q = tmp.alloc<double>(n, "q");
+  w.partial = tmp.alloc<double>(slot_blocks(n), "partials");
+  w.dst = tmp.alloc<double>(8, "pcg scalars");
+  w.ist = tmp.alloc<int>(4, "pcg flags");
+  w.tables = nullptr;
+  return pcg_run(A, f, b, x, o, st, s, w);
 }
 
 static void check_consistent_block(parac_factor_t f, const double *b, int64_t nrhs,
@@ -1218,6 +1299,7 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
       o1.status = done ? PARAC_OK : PARAC_ENOCONV;
       o1.ms_total = ms_total;
       o1.ms_apply = ms_apply;
+      o1.ms_fwd = 0.0;
       o1.applies = ran;
     }
   }

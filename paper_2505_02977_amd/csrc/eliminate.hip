@@ -16,9 +16,11 @@
 //      the sampled edge, of weight S_{p+1} w_p / D_k, to the inbox of its
 //      smaller endpoint, incrementing the counter of the larger (§III);
 //   5. writes column k of F, F(u,k) = -w_u / D_k, and D_k (§IV scaled form);
-//   6. publishes everything with one agent-scope release, then decrements the
+//   6. waits until its stores of steps 4-5 have completed (every datum another
+//      pivot reads was written with agent-scope relaxed atomics, which bypass
+//      the caches that are not coherent across XCDs), then decrements the
 //      counters of its neighbours by their multiplicities and enqueues those
-//      that reach zero (Alg. 3/4).
+//      that reach zero (Alg. 3/4: insertions before deletions).
 // The arithmetic follows fixed orders that do not depend on the schedule, so
 // the factor is the same bit for bit for any grid size or timing.
 #include "device.hpp"

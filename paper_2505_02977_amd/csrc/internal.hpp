@@ -287,9 +287,10 @@ hipError_t slots_init(const SlotBatch &B, hipStream_t s);
 hipError_t slots_rz(const SlotBatch &B, int first, hipStream_t s);
 hipError_t slots_step(const SlotBatch &B, hipStream_t s);
 hipError_t slots_true_res(const SlotBatch &B, hipStream_t s);
-hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s);
+// mid: optional event recorded between the forward and the backward sweep
+hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid = nullptr);
 // --- ready.hip ---
-hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s);
+hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid = nullptr);
 
 }  // namespace parac
 

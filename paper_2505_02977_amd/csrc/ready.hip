@@ -371,21 +371,22 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
 }
 
 template <typename T>
-void ready_apply_t(const SlotBatch &B, hipStream_t s) {
+void ready_apply_t(const SlotBatch &B, hipStream_t s, hipEvent_t mid) {
   hipLaunchKernelGGL((k_ready<T, false>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
                      B.wgmap);
+  if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL((k_ready<T, true>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
                      B.wgmap);
 }
 
 }  // namespace
 
-hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s) {
-  if (B.nwg == 0) return hipSuccess;
+hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid) {
+  if (B.nwg == 0) return mid ? hipEventRecord(mid, s) : hipSuccess;
   if (prec == PARAC_PREC_MIXED)
-    ready_apply_t<float>(B, s);
+    ready_apply_t<float>(B, s, mid);
   else
-    ready_apply_t<double>(B, s);
+    ready_apply_t<double>(B, s, mid);
   return hipGetLastError();
 }
 

@@ -216,8 +216,8 @@ hipError_t slots_true_res(const SlotBatch &B, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s) {
-  return ready_apply(B, prec, s);
+hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid) {
+  return ready_apply(B, prec, s, mid);
 }
 
 }  // namespace parac

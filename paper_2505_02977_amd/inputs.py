@@ -260,9 +260,16 @@ def _finish(name, c, n, i, j, w, excess=None, nrhs=1, center=True, meta=None):
     _note("order and right-hand side")
     perm = perm_random(n, substream(seed_c, 2))
     b = rhs(n, substream(seed_c, 3), nrhs=nrhs, center=center)
-    m = dict(n=n, edges=int(len(i)), nnz=A.nnz)
+    m = dict(n=n, edges=int(len(i)), nnz=A.nnz, seed_c=seed_c)
     m.update(meta or {})
     return Workload(name, A, perm, b, splitmix64(seed_c + 4), m)
+
+
+def with_nnz_order(W: Workload) -> Workload:
+    """The workload with its random order replaced by the NNZ-sorted one
+    (ties broken by sub-stream 5 of the workload's seed)."""
+    perm = perm_nnz_sorted(W.A, substream(W.meta["seed_c"], 5))
+    return dataclasses.replace(W, perm=perm)
 
 
 def grid2d_workload(side=64, c=1):
@@ -295,17 +302,33 @@ def chung_lu_workload(log2n=22, dbar=16.0, beta=2.1, nrhs=1, c=3):
                    meta=dict(N_generated=N, dbar=dbar, beta=beta, nrhs=nrhs))
 
 
+SDDM_FAMILIES = ("grid2d", "grid3d", "chunglu", "rgg")
+
+
+def _sddm_draws(k, nmin, nmax, c):
+    seed_c = BASE_SEED + c
+    rng = np.random.default_rng(splitmix64(seed_c * 1000003 + k))
+    N = int(round(10 ** rng.uniform(math.log10(nmin), math.log10(nmax))))
+    fam = int(rng.integers(0, 4))
+    dbar = float(rng.integers(8, 17))
+    return rng, N, fam, dbar
+
+
+def sddm_system_plan(k, nmin=1e3, nmax=1e6, c=4):
+    """Requested size and family of system ``k`` of the serving stream,
+    without building it."""
+    _, N, fam, dbar = _sddm_draws(k, nmin, nmax, c)
+    return N, SDDM_FAMILIES[fam], dbar
+
+
 def sddm_system(k, nmin=1e3, nmax=1e6, c=4):
     """System ``k`` of the serving stream: size log-uniform in [nmin, nmax],
     family uniform over {2D grid, 3D grid, Chung-Lu (beta 2.1), RGG}, average
     degree uniform in {8..16} for the random families, largest component,
     excess U[0,1] on ceil(0.1 n) random vertices, weights U(0,1] on even k and
     unit on odd k, one N(0,1) right-hand side (SDDM: nonsingular)."""
+    rng, N, fam, dbar = _sddm_draws(k, nmin, nmax, c)
     seed_c = BASE_SEED + c
-    rng = np.random.default_rng(splitmix64(seed_c * 1000003 + k))
-    N = int(round(10 ** rng.uniform(math.log10(nmin), math.log10(nmax))))
-    fam = int(rng.integers(0, 4))
-    dbar = float(rng.integers(8, 17))
     if fam == 0:
         s = max(2, int(round(math.sqrt(N))))
         n, (i, j) = s * s, grid2d_edges(s, s)

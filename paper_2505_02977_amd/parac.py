@@ -56,7 +56,7 @@ class parac_pcg_opts(C.Structure):
 class parac_pcg_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("relres", C.c_double),
                 ("true_relres", C.c_double), ("ms_total", C.c_double), ("ms_apply", C.c_double),
-                ("applies", C.c_int32)]
+                ("applies", C.c_int32), ("ms_fwd", C.c_double)]
 
 
 class parac_block_shape(C.Structure):
@@ -72,6 +72,14 @@ class parac_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("true_relres", C.c_double),
                 ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
                 ("bytes_resident", C.c_int64)]
+
+
+class parac_host_factor(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ntot", C.c_int64), ("mode", C.c_int32), ("threads", C.c_int32),
+                ("nnz_off", C.c_int64), ("n_fill", C.c_int64), ("depth", C.c_int64),
+                ("colptr", C.POINTER(C.c_int64)), ("rowind", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double)), ("D", C.POINTER(C.c_double)),
+                ("level", C.POINTER(C.c_int32)), ("ms_total", C.c_double)]
 
 
 class parac_serve_opts(C.Structure):
@@ -102,6 +110,12 @@ def lib():
                                   C.POINTER(parac_serve_opts), C.POINTER(parac_result)]
         L.parac_block_shape_set.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(parac_block_shape)]
         L.parac_block_shape_get.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(parac_block_shape)]
+        L.parac_factor_host.argtypes = [C.POINTER(parac_csr), C.POINTER(parac_factor_opts),
+                                        C.c_int32, C.POINTER(parac_host_factor)]
+        L.parac_factor_host.restype = C.c_int
+        L.parac_host_factor_free.argtypes = [C.POINTER(parac_host_factor)]
+        L.parac_host_factor_free.restype = None
+        L.parac_host_last_error.restype = C.c_char_p
         L.parac_factor_free.argtypes = [P]
         L.parac_status_str.restype = C.c_char_p
         L.parac_status_str.argtypes = [C.c_int]
@@ -220,7 +234,40 @@ def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=None, rtol=1e-6, maxit=10000,
         _raise(rc)
     return [dict(status=s.status, iterations=s.iterations, relres=s.relres,
                  true_relres=s.true_relres, ms_total=s.ms_total, ms_apply=s.ms_apply,
-                 applies=s.applies) for s in st]
+                 applies=s.applies, ms_fwd=s.ms_fwd) for s in st]
+
+
+def parac_factor_host(A, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, threads=0):
+    """The CPU factorisation on the host's cores (parac_factor_host): A is a
+    host CSR (n, rowptr, col, val).  Returns a dict with the canonical CSC
+    (colptr, rowind, val), D, level (numpy copies) and statistics."""
+    n = int(A.n)
+    rowptr = np.ascontiguousarray(A.rowptr, np.int64)
+    col = np.ascontiguousarray(A.col, np.int32)
+    val = np.ascontiguousarray(A.val, np.float64)
+    pm = None if perm is None else np.ascontiguousarray(perm, np.int32)
+    csr = parac_csr(n, int(col.size), rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, 0)
+    o = parac_factor_opts(int(seed) & (2**64 - 1), None if pm is None else pm.ctypes.data, mode,
+                          pool_factor, 0, 0, 0.0, 0.0)
+    out = parac_host_factor()
+    rc = lib().parac_factor_host(C.byref(csr), C.byref(o), threads, C.byref(out))
+    if rc != OK:
+        raise ParacError(rc, lib().parac_host_last_error().decode())
+    try:
+        nt, m = out.ntot, out.nnz_off
+
+        def arr(ptr, count, dtype):
+            if count == 0:
+                return np.zeros(0, dtype)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dtype, copy=True)
+        res = dict(colptr=arr(out.colptr, nt + 1, np.int64), rowind=arr(out.rowind, m, np.int32),
+                   val=arr(out.val, m, np.float64), D=arr(out.D, nt, np.float64),
+                   level=arr(out.level, nt, np.int32), n=out.n, ntot=nt, mode=out.mode,
+                   nnz_off=m, n_fill=out.n_fill, depth=out.depth, threads=out.threads,
+                   ms_total=out.ms_total)
+    finally:
+        lib().parac_host_factor_free(C.byref(out))
+    return res
 
 
 def parac_serve(requests, hbm_budget=0, max_slots=0, precision=PREC_FP64, maxit=0,

@@ -1,15 +1,19 @@
 """GPU parity of the block (several right-hand sides) path.
 
-The block apply is bit-identical, column by column, to the oracle's apply of
-that column, for every launch shape (columns per lane, tail threshold) and
-for the shape the timing picks; block PCG runs an independent recurrence per
-column, so each column reaches the relative residual and agrees with the
-oracle's single-vector PCG of that column."""
+The block apply is bit-identical, column by column, to the device's
+single-vector apply of that column, for every launch shape (columns per lane,
+tail threshold) and for the default shape, and agrees with the oracle's apply
+of that column within the rounding bound of the two summation orders; block
+PCG runs an independent recurrence per column, so each column reaches the
+relative residual and agrees with the oracle's single-vector PCG of that
+column."""
 import numpy as np
 import pytest
 
 from paper_2505_02977_amd import inputs
+from tests.bounds import within_apply_bound
 from tests.gpu_util import need_gpu, same_bits
+from tests.test_gpu_solve import MIXED_VS_MIXED
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +43,19 @@ def setup_case(kind, nrhs):
     return A, perm, seed, np.ascontiguousarray(B), ex is not None
 
 
+def single_applies(f, B, precision):
+    """The device's single-vector apply of every column of B."""
+    import torch
+    from paper_2505_02977_amd import parac
+    out = np.empty_like(B)
+    for j in range(B.shape[1]):
+        r = torch.tensor(B[:, j].copy(), device="cuda")
+        z = torch.empty_like(r)
+        parac.parac_apply(f, r, z, precision=precision)
+        out[:, j] = z.cpu().numpy()
+    return out
+
+
 # cpl 0: one dependency-driven sweep pair per column; else level-synchronous
 SHAPES = [(0, 256)] + [(c, t) for c in (1, 2, 4) for t in (0, 64, 1024, 1 << 40)]
 
@@ -51,9 +68,13 @@ def test_block_apply_every_shape_bit_identical(orc, kind, precision):
     nrhs = 32
     A, perm, seed, B, _ = setup_case(kind, nrhs)
     ref = orc.factor(A, perm=perm, seed=seed)
-    want = np.stack([orc.apply(ref, B[:, j].copy(), precision=precision)
-                     for j in range(nrhs)], axis=1)
     f = parac.parac_factor(parac.DeviceCSR(A), perm=perm, seed=seed, keep_fp32=True)
+    want = single_applies(f, B, precision)
+    for j in (0, nrhs - 1):
+        b = B[:, j].copy()
+        ok, ratio = within_apply_bound(want[:, j], orc.apply(ref, b, precision=precision), ref, b,
+                                       precision)
+        assert ok, (j, ratio)
     r = torch.tensor(B, device="cuda")
     z = torch.empty_like(r)
     for cpl, tail in SHAPES:
@@ -64,18 +85,18 @@ def test_block_apply_every_shape_bit_identical(orc, kind, precision):
 
 
 @pytest.mark.parametrize("nrhs", [2, 7, 70])
-def test_block_apply_tuned_shape(orc, nrhs):
+def test_block_apply_default_shape(orc, nrhs):
     torch = need_gpu()
     from paper_2505_02977_amd import parac
     A, perm, seed, B, _ = setup_case("grid", nrhs)
-    ref = orc.factor(A, perm=perm, seed=seed)
     f = parac.parac_factor(parac.DeviceCSR(A), perm=perm, seed=seed)
     r = torch.tensor(B, device="cuda")
     z = torch.empty_like(r)
     parac.parac_apply(f, r, z)
     got = z.cpu().numpy()
+    want = single_applies(f, B, 0)
     for j in range(nrhs):
-        assert same_bits(got[:, j], orc.apply(ref, B[:, j].copy())), j
+        assert same_bits(got[:, j], want[:, j]), j
     # chunks of at most 64 columns, each solved by column sweeps unless a
     # level-synchronous shape is fixed
     for cols in sorted({min(64, nrhs - c0) for c0 in range(0, nrhs, 64)}):
@@ -143,8 +164,10 @@ def test_block_pcg_mixed_and_chunks(orc):
         b = B[:, j]
         res = np.linalg.norm(b - L @ X[:, j]) / np.linalg.norm(b)
         assert sts[j]["status"] == 0 and res <= 1e-6, (j, res)
-        _, sr = orc.pcg(A, ref, b.copy(), rtol=1e-6, precision=1)
-        assert abs(sr["iterations"] - sts[j]["iterations"]) <= 2, j
+        xm, _ = orc.pcg(A, ref, b.copy(), rtol=0.0, maxit=sts[j]["iterations"], precision=1)
+        x = X[:, j] - X[:, j].mean()
+        xm = xm - xm.mean()
+        assert np.max(np.abs(x - xm)) <= MIXED_VS_MIXED * np.max(np.abs(xm)), j
 
 
 def test_block_inconsistent_column_rejected(orc):

@@ -202,3 +202,26 @@ def test_errors_match_oracle(orc):
     with pytest.raises(parac.ParacError) as e:
         gpu_factor(S, None, 1, mode=parac.MODE_LAPLACIAN)
     assert e.value.status == parac.ENOTLAP
+
+
+@pytest.mark.parametrize("case", ["grid3d", "chung_lu_16k"])
+def test_nnz_sorted_order_bit_identical(orc, case):
+    """Under the NNZ-sorted elimination order (ascending row count, random
+    ties; the ordering recommended for GPUs in §V) the factor is again the
+    oracle's, bit for bit."""
+    need_gpu()
+    if case == "grid3d":
+        rng = np.random.default_rng(31)
+        i, j = inputs.grid3d_edges(18, 17, 16)
+        n = 18 * 17 * 16
+        A = lap(n, i, j, 10.0 ** rng.uniform(-2, 2, len(i)))
+    else:
+        A, _, _ = power_law_case(orc)
+    perm = inputs.perm_nnz_sorted(A, np.random.default_rng(32))
+    deg = np.diff(A.rowptr)
+    order = np.argsort(perm)            # vertices by label
+    assert np.all(np.diff(deg[order]) >= 0)
+    ref = orc.factor(A, perm=perm, seed=515)
+    f = gpu_factor(A, perm, 515)
+    assert f.info()["depth"] == ref.stats["depth"]
+    compare_factor(f, ref)

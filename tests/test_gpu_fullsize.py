@@ -1,0 +1,103 @@
+"""GPU parity at the benchmark sizes.
+
+The FP64 factor of the 3D grid 128^3 workload (2,097,152 vertices) and of
+the Chung-Lu 2^22 workload is identical to the oracle's, bit for bit (F, D
+and the levels); their PCG solutions agree with the oracle's (FP64) or are
+within the stated bounds of it (FP32 apply).  One system of each family of
+the serving stream at n >= 1e5 is checked the same way."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2505_02977_amd import inputs
+from tests.gpu_util import compare_factor, need_gpu
+from tests.test_gpu_solve import MIXED_VS_FP64, MIXED_VS_MIXED
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def project(x, sddm):
+    return x if sddm else x - x.mean()
+
+
+def check_system(orc, W, sddm, mixed=True, oracle_pcg=True):
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    t0 = time.time()
+    dA = parac.DeviceCSR(W.A)
+    f = parac.parac_factor(dA, perm=W.perm, seed=W.seed, keep_fp32=mixed)
+    say("%s: device factor %.1f ms, nnz(F) %d, depth %d" % (W.name, f.info()["ms_total"],
+                                                         f.info()["nnz_off"], f.info()["depth"]))
+    ref = orc.factor(W.A, perm=W.perm, seed=W.seed)
+    say("%s: oracle factor %.1f s" % (W.name, time.time() - t0))
+    assert ref.status == 0
+    compare_factor(f, ref)
+    b = np.ascontiguousarray(W.b)
+    bt = torch.tensor(b, device="cuda")
+    xt = torch.empty_like(bt)
+    st = parac.parac_pcg(dA, f, bt, xt, rtol=1e-6)[0]
+    x = xt.cpu().numpy()
+    res = np.linalg.norm(b - W.A.to_scipy() @ x) / np.linalg.norm(b)
+    assert st["status"] == 0 and res <= 1e-6, (st, res)
+    out = {"iterations": st["iterations"]}
+    if oracle_pcg:
+        t1 = time.time()
+        xr, sr = orc.pcg(W.A, ref, b, rtol=0.0, maxit=st["iterations"])
+        xp, xrp = project(x, sddm), project(xr, sddm)
+        out["fp64_vs_oracle"] = float(np.linalg.norm(xp - xrp) / np.linalg.norm(xrp))
+        say("%s: FP64 PCG %d iterations, vs oracle %.2e (oracle PCG %.1f s)"
+            % (W.name, st["iterations"], out["fp64_vs_oracle"], time.time() - t1))
+        assert out["fp64_vs_oracle"] <= 1e-8
+    if mixed:
+        xm_t = torch.empty_like(bt)
+        sm = parac.parac_pcg(dA, f, bt, xm_t, rtol=1e-6, precision=parac.PREC_MIXED)[0]
+        xm = xm_t.cpu().numpy()
+        resm = np.linalg.norm(b - W.A.to_scipy() @ xm) / np.linalg.norm(b)
+        assert sm["status"] == 0 and resm <= 1e-6, (sm, resm)
+        out["mixed_iterations"] = sm["iterations"]
+        if oracle_pcg:
+            t1 = time.time()
+            xo, _ = orc.pcg(W.A, ref, b, rtol=0.0, maxit=sm["iterations"], precision=1)
+            xmp, xop = project(xm, sddm), project(xo, sddm)
+            out["mixed_vs_oracle_mixed"] = float(np.max(np.abs(xmp - xop)) / np.max(np.abs(xop)))
+            xd, sd = orc.pcg(W.A, ref, b, rtol=1e-6)
+            xdp = project(xd, sddm)
+            out["mixed_vs_oracle_fp64"] = float(np.linalg.norm(xmp - xdp) / np.linalg.norm(xdp))
+            say("%s: mixed PCG %d iterations, vs oracle mixed %.2e, vs oracle FP64 %.2e "
+                "(oracle %.1f s)" % (W.name, sm["iterations"], out["mixed_vs_oracle_mixed"],
+                                     out["mixed_vs_oracle_fp64"], time.time() - t1))
+            assert out["mixed_vs_oracle_mixed"] <= MIXED_VS_MIXED
+            assert out["mixed_vs_oracle_fp64"] <= MIXED_VS_FP64
+    return out
+
+
+def test_grid3d_128_full_size(orc):
+    need_gpu()
+    say("generating grid3d_128")
+    W = inputs.grid3d_workload(128)
+    check_system(orc, W, sddm=False)
+
+
+# one system of each family of the serving stream, the smallest of at
+# least 1.2e5 requested vertices
+FAMILY_CASES = [110, 186, 144, 159]
+
+
+@pytest.mark.parametrize("k", FAMILY_CASES)
+def test_serving_family_system(orc, k):
+    need_gpu()
+    W = inputs.sddm_system(k)
+    assert W.A.n >= 1e5
+    check_system(orc, W, sddm=True)
+
+
+def test_chung_lu_22_full_size(orc):
+    need_gpu()
+    say("generating chung_lu_22")
+    W = inputs.chung_lu_workload(22)
+    check_system(orc, W, sddm=False, oracle_pcg=False)

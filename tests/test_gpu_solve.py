@@ -1,12 +1,27 @@
-"""GPU parity of the solve: the preconditioner apply is bit-identical to the
-oracle's (same factor, same left-fold order per row) in FP64 and in FP32;
-PCG reaches the relative residual in FP64 and agrees with the oracle's
-solution to 1e-8 after removing the null-space component."""
+"""GPU parity of the solve.
+
+The preconditioner apply agrees with the oracle's element by element within
+the rounding bound of the two summation orders (the oracle folds each row
+left to right, the device sums long rows in 64-product chunks), in FP64 and
+in FP32, and repeated calls give the same bits.  PCG reaches the relative
+residual in FP64 and agrees with the oracle's solution to 1e-8 after removing
+the null-space component; the mixed-precision PCG agrees with the oracle's
+mixed PCG at equal iteration count, and its error against the FP64 oracle
+solution is bounded and reported."""
 import numpy as np
 import pytest
 
 from paper_2505_02977_amd import inputs
+from tests.bounds import within_apply_bound
 from tests.gpu_util import need_gpu, same_bits
+
+# mixed precision (FP32 apply): agreement of two mixed PCG runs whose FP32
+# applies differ only in summation order, at equal iteration count, relative
+# to the solution's largest entry, per element, after projection
+MIXED_VS_MIXED = 1e-5
+# mixed-precision solution against the FP64 oracle solution (both to a
+# relative residual of 1e-6), relative 2-norm after projection
+MIXED_VS_FP64 = 1e-4
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +76,7 @@ def setup_case(kind):
 
 @pytest.mark.parametrize("kind", ["grid", "sddm", "rand", "star_last", "star_first", "chunglu"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_apply_bit_identical(orc, kind, precision):
+def test_apply_matches_oracle_within_bound(orc, kind, precision):
     torch = need_gpu()
     from paper_2505_02977_amd import parac
     A, perm, seed, b, _ = setup_case(kind)
@@ -70,11 +85,18 @@ def test_apply_bit_identical(orc, kind, precision):
     f = parac.parac_factor(dA, perm=perm, seed=seed, keep_fp32=True)
     r = torch.tensor(b, device="cuda")
     z = torch.empty_like(r)
+    zr = orc.apply(ref, b, precision=precision)
+    first = None
     for rep in range(2):  # the second call reuses re-armed work vectors
         parac.parac_apply(f, r, z, precision=precision)
         torch.cuda.synchronize()
-        zr = orc.apply(ref, b, precision=precision)
-        assert same_bits(z.cpu().numpy(), zr), (kind, precision, rep)
+        got = z.cpu().numpy()
+        ok, ratio = within_apply_bound(got, zr, ref, b, precision)
+        assert ok, (kind, precision, rep, ratio)
+        if first is None:
+            first = got
+        else:
+            assert same_bits(got, first), (kind, precision)
 
 
 @pytest.mark.parametrize("kind", ["grid", "sddm", "rand"])
@@ -102,19 +124,38 @@ def test_pcg_fp64(orc, kind):
     assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr)
 
 
-def test_pcg_mixed(orc):
+def mixed_errors(orc, A, ref, b, x, iterations, sddm):
+    """Element-wise agreement with the oracle's mixed PCG at equal iteration
+    count, and the relative error against the oracle's FP64 solution."""
+    xm, sm = orc.pcg(A, ref, b, rtol=0.0, maxit=iterations, precision=1)
+    xd, sd = orc.pcg(A, ref, b, rtol=1e-6)
+    assert sd["status"] == 0
+    if not sddm:
+        x, xm, xd = project(x), project(xm), project(xd)
+    vs_mixed = float(np.max(np.abs(x - xm)) / np.max(np.abs(xm)))
+    vs_fp64 = float(np.linalg.norm(x - xd) / np.linalg.norm(xd))
+    return vs_mixed, vs_fp64
+
+
+@pytest.mark.parametrize("kind", ["grid", "sddm", "chunglu"])
+def test_pcg_mixed(orc, kind):
     torch = need_gpu()
     from paper_2505_02977_amd import parac
-    A, perm, seed, b, _ = setup_case("grid")
+    A, perm, seed, b, sddm = setup_case(kind)
     dA = parac.DeviceCSR(A)
     f = parac.parac_factor(dA, perm=perm, seed=seed, keep_fp32=True)
     bt = torch.tensor(b, device="cuda")
     xt = torch.empty_like(bt)
     st = parac.parac_pcg(dA, f, bt, xt, rtol=1e-6, precision=parac.PREC_MIXED)[0]
     assert st["status"] == 0 and st["true_relres"] <= 1e-6
+    x = xt.cpu().numpy()
+    assert np.linalg.norm(b - A.to_scipy() @ x) <= 1e-6 * np.linalg.norm(b)
     ref = orc.factor(A, perm=perm, seed=seed)
-    xr, sr = orc.pcg(A, ref, b, rtol=1e-6, precision=1)
-    assert abs(sr["iterations"] - st["iterations"]) <= 2
+    vs_mixed, vs_fp64 = mixed_errors(orc, A, ref, b, x, st["iterations"], sddm)
+    print("mixed %s: iterations %d, vs oracle mixed %.3e, vs oracle FP64 %.3e"
+          % (kind, st["iterations"], vs_mixed, vs_fp64))
+    assert vs_mixed <= MIXED_VS_MIXED, vs_mixed
+    assert vs_fp64 <= MIXED_VS_FP64, vs_fp64
 
 
 def test_pcg_exact_factor_one_iteration(orc):

@@ -524,6 +524,63 @@ def test_apply_long_rows_exact_on_star(orc, hub_last):
 
 
 # ----------------------------------------------------------------------------
+# R10 / R17: the apply's arithmetic on a hand-derived three-vertex case
+# ----------------------------------------------------------------------------
+# Path 1 - 0 - 2, labels = vertex numbers, weights a = w(0,1) < b = w(0,2).
+# Eliminating 0: d = 2, sampling order (1, 2), S = (a+b, b), D_0 = a+b; the
+# one draw must pick 2, fill c = (b*a)/D_0 joins 1 and 2; F(1,0) = -(a/D_0),
+# F(2,0) = -(b/D_0).  Eliminating 1: D_1 = c, F(2,1) = -1.  D_2 = 0.
+#   forward   y0 = r0,  y1 = r1 - F10*y0,  y2 = (r2 - F20*y0) - F21*y1
+#   backward  x2 = 0*y2,  x1 = D1^+ y1 - F21*x2,  x0 = (D0^+ y0 - F10*x1) - F20*x2
+# The constants below were worked out in exact rational arithmetic, rounding
+# to nearest-even after every operation at the stated precision.
+PIN_A = float.fromhex("0x1.0a7ecfe9b7bf2p+1")           # 2.081995
+PIN_B = float.fromhex("0x1.306501e2584f5p+2")           # 4.756165
+PIN_R = [float.fromhex(h) for h in ("0x1.de15ca6ca03c5p-7",    # 0.01459
+                                    "-0x1.528f190d173fbp-1",   # -0.661248
+                                    "0x1.053b8e4b87bddp-1")]   # 0.51022
+# FP64 factor: D_0 = a+b, c = (b*a)/D_0, F10 = -(a/D_0), F20 = -(b/D_0)
+PIN_D0 = float.fromhex("0x1.b5a469d7342eep+2")
+PIN_C = float.fromhex("0x1.72b66a69e2af4p+0")
+PIN_F10 = float.fromhex("-0x1.37c63bb6a5c24p-2")
+PIN_F20 = float.fromhex("-0x1.641ce224ad1eep-1")
+# FP64 apply: x0, x1
+PIN_X64 = [float.fromhex("-0x1.16734709def2ap-3"), float.fromhex("-0x1.d07360a13cdeep-2")]
+# FP32 apply (R17): D^+ formed in FP64 then rounded, d0 = 0x1.2b7eeap-3,
+# d1 = 0x1.619156p-1; F values and r rounded to FP32; every product and
+# difference in FP32: y1 = -0x1.5048dcp-1, x1 = -0x1.d07362p-2,
+# x0 = -0x1.16734ap-3.  Each plausible misplacement of a rounding point
+# changes x0 or x1 on this case:
+#   1/(float)D in place of (float)(1/D):        x1 = -0x1.d07364p-2
+#   F values used unrounded (FP64) in products: x0 = -0x1.167348p-3
+#   r kept in FP64 until its first difference:  x0 = -0x1.167346p-3, x1 = -0x1.d0735ep-2
+#   FP64 accumulation, one rounding per row:    x0 = -0x1.167348p-3
+PIN_X32 = [float.fromhex("-0x1.16734ap-3"), float.fromhex("-0x1.d07362p-2")]
+
+
+def pin_case(orc):
+    A = lap(3, np.array([0, 0]), np.array([1, 2]), np.array([PIN_A, PIN_B]))
+    f = orc.factor(A, perm=np.arange(3, dtype=np.int32), seed=7)
+    assert f.status == 0
+    return f
+
+
+def test_apply_pin_factor(orc):
+    f = pin_case(orc)
+    assert list(f.colptr) == [0, 2, 3, 3] and list(f.rowind) == [1, 2, 2]
+    assert f.val.tolist() == [PIN_F10, PIN_F20, -1.0]
+    assert f.D.tolist() == [PIN_D0, PIN_C, 0.0]
+
+
+@pytest.mark.parametrize("precision,want", [(0, PIN_X64), (1, PIN_X32)])
+def test_apply_pin_rounding_points(orc, precision, want):
+    f = pin_case(orc)
+    z = orc.apply(f, np.array(PIN_R), precision=precision)
+    assert z[:2].tolist() == want, [v.hex() for v in z[:2]]
+    assert z[2] == 0.0
+
+
+# ----------------------------------------------------------------------------
 # R4: suffix sums
 # ----------------------------------------------------------------------------
 def test_suffix_sums_exact_on_integers(orc):
