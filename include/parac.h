@@ -211,6 +211,41 @@ parac_status parac_pcg(const parac_csr *A, parac_factor_t f, const double *b,
                        double *x, int64_t nrhs, const parac_pcg_opts *o,
                        parac_pcg_stats *st, void *stream);
 
+/* Bytes of the fixed device array behind parac_pcg_static (one copy per GPU,
+ * held from library load until the process ends). */
+#define PARAC_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * single right-hand-side PCG as parac_pcg (same kernels, same launch shapes,
+ * so x and the stats are bit for bit those of parac_pcg), but every per-call
+ * buffer (the four PCG vectors, partial sums, scalars, flags, launch tables,
+ * and the consistency check's sums) lives in a fixed device array of
+ * PARAC_STATIC_SCRATCH_BYTES owned by the library; the call makes no device
+ * allocation and creates no event.  The caller still passes the inputs and
+ * the output, and the factor must have been built with the work vectors of
+ * the requested precision (every factor has FP64 ones; MIXED needs
+ * keep_fp32).
+ *   A, f, b, x, o, stream  as for parac_pcg with nrhs = 1; o->timing is
+ *              ignored (ms_* of the stats are 0)
+ *   st         one stats struct (may be NULL)
+ * Limit: the system may have at most parac_pcg_static_max_rows() rows
+ * (ground vertex included), about 4.19 million; a larger one is rejected
+ * with EINVAL before any device work.
+ * Every call on a GPU uses that GPU's one array, which keeps the previous
+ * call's contents (the call clears what it needs): calls that overlap on
+ * one GPU (different host threads or streams) race and must be serialised
+ * by the caller.
+ * Errors: as parac_pcg, plus EINVAL for a system above the limit or a
+ * factor without the precision's work vectors. */
+parac_status parac_pcg_static(const parac_csr *A, parac_factor_t f,
+                              const double *b, double *x,
+                              const parac_pcg_opts *o, parac_pcg_stats *st,
+                              void *stream);
+
+/* Largest row count (ground vertex included) parac_pcg_static accepts. */
+int64_t parac_pcg_static_max_rows(void);
+
 /* One system of a serving stream. */
 typedef struct {
   parac_csr A;            /* host arrays                                    */

@@ -843,9 +843,9 @@ static void check_consistent(parac_factor_t f, const double *b, hipStream_t s,
   if (!sum) sum = tmp.alloc<double>(f->ntot, "sums");
   if (!sabs) sabs = tmp.alloc<double>(f->ntot, "sums");
   if (!bad) bad = tmp.alloc<int>(1, "flag");
-  chk(hipMemsetAsync(sum, 0, f->ntot * sizeof(double), s), "memset");
-  chk(hipMemsetAsync(sabs, 0, f->ntot * sizeof(double), s), "memset");
-  chk(hipMemsetAsync(bad, 0, sizeof(int), s), "memset");
+  chk(launch_fill_u64((uint64_t *)sum, 0, f->ntot, s), "fill");
+  chk(launch_fill_u64((uint64_t *)sabs, 0, f->ntot, s), "fill");
+  chk(launch_fill_u32((uint32_t *)bad, 0, 1, s), "fill");
   chk(launch_comp_check(n, f->ntot > n ? n : -1, f->perm, f->root, b, sum, sabs, bad, s),
       "comp_check");
   if (read1(bad, s))
@@ -1038,6 +1038,7 @@ struct PcgWork {
   double *r, *z, *p, *q, *partial, *dst;
   int *ist;
   const TableMem *tables;
+  bool events;  // time the call with HIP events (false: no event is created)
 };
 
 // one system as a batch of one: the same launches, hence the same bits, as
@@ -1066,7 +1067,7 @@ static int pcg_run(const parac_csr *A, parac_factor_t f, const double *b, double
     }
   } evfree{evs};
   auto mark = [&](bool always) {
-    if (!o.timing && !always) return;
+    if (!w.events || (!o.timing && !always)) return;
     hipEvent_t e;
     chk(hipEventCreate(&e), "hipEventCreate");
     chk(hipEventRecord(e, s), "hipEventRecord");
@@ -1081,7 +1082,7 @@ static int pcg_run(const parac_csr *A, parac_factor_t f, const double *b, double
     }
   } midfree{mids};
   auto mid = [&]() -> hipEvent_t {
-    if (!o.timing) return nullptr;
+    if (!w.events || !o.timing) return nullptr;
     hipEvent_t e;
     chk(hipEventCreate(&e), "hipEventCreate");
     mids.push_back(e);
@@ -1131,7 +1132,7 @@ static int pcg_run(const parac_csr *A, parac_factor_t f, const double *b, double
     st->true_relres = bn > 0 ? sqrt(hst[7]) / bn : 0.0;
     st->status = ok ? PARAC_OK : PARAC_ENOCONV;
     float ms = 0.f;
-    chk(hipEventElapsedTime(&ms, evs.front(), evs.back()), "elapsed");
+    if (evs.size() >= 2) chk(hipEventElapsedTime(&ms, evs.front(), evs.back()), "elapsed");
     st->ms_total = ms;
     st->ms_apply = 0.0;
     st->ms_fwd = 0.0;
@@ -1162,7 +1163,66 @@ static int pcg_one(const parac_csr *A, parac_factor_t f, const double *b, double
   w.dst = tmp.alloc<double>(8, "pcg scalars");
   w.ist = tmp.alloc<int>(4, "pcg flags");
   w.tables = nullptr;
+  w.events = true;
   return pcg_run(A, f, b, x, o, st, s, w);
+}
+
+// ---------------------------------------------------------------------------
+// PCG without device allocation (parac_pcg_static)
+// ---------------------------------------------------------------------------
+// Every per-call buffer of a single-vector PCG (r, z, p, q, partial sums,
+// scalars, flags, the batch tables, and the consistency check's sums, which
+// share r and z before the iteration starts) lives in this fixed array, one
+// copy per GPU for the life of the process.  In host code its name is a
+// host-side stand-in, never a device address: each device's address comes
+// from hipGetSymbolAddress, once per device with that device current, and
+// only that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[PARAC_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_dev;  // device address of scratch, by device
+
+static char *static_scratch() {
+  int dev = 0;
+  chk(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Err{PARAC_EDEVICE,
+                std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    }
+    g_scratch_dev[dev] = p;
+  }
+  return (char *)g_scratch_dev[dev];
+}
+
+// byte offsets of the buffers in the array for a system of ntot rows
+struct StaticLayout {
+  size_t r, z, p, q, partial, dst, ist, bad, slots, bslot, aslots, wgmap, end;
+};
+static StaticLayout static_layout(int64_t ntot) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t vb = up((size_t)std::max<int64_t>(ntot, 1) * sizeof(double));
+  StaticLayout L{};
+  size_t o = 0;
+  L.r = o, o += vb;
+  L.z = o, o += vb;
+  L.p = o, o += vb;
+  L.q = o, o += vb;
+  L.partial = o, o += up(kSlotMaxBlocks * sizeof(double));
+  L.dst = o, o += up(8 * sizeof(double));
+  L.ist = o, o += up(4 * sizeof(int));
+  L.bad = o, o += up(sizeof(int));
+  L.slots = o, o += up(sizeof(PcgSlot));
+  L.bslot = o, o += up(kSlotMaxBlocks * sizeof(int32_t));
+  L.aslots = o, o += up(sizeof(ApplySlot));
+  L.wgmap = o, o += up(kReadyGroupsMax * sizeof(int32_t));
+  L.end = o;
+  return L;
 }
 
 static void check_consistent_block(parac_factor_t f, const double *b, int64_t nrhs,
@@ -1762,6 +1822,80 @@ parac_status parac_pcg(const parac_csr *A, parac_factor_t f, const double *b, do
       for (int64_t j = 0; j < nrhs; ++j) st[j].status = e.code;
     return status_from(e);
   }
+}
+
+parac_status parac_pcg_static(const parac_csr *A, parac_factor_t f, const double *b, double *x,
+                              const parac_pcg_opts *o, parac_pcg_stats *st, void *stream) {
+  if (!A || !f || A->n != f->n || !A->on_device || (f->n && (!b || !x))) {
+    g_last_error = "bad pcg arguments (matrix must be on the device and match the factor)";
+    return PARAC_EINVAL;
+  }
+  const StaticLayout L = static_layout(f->ntot);
+  if (L.end > (size_t)PARAC_STATIC_SCRATCH_BYTES) {
+    g_last_error = "system too large for parac_pcg_static: " + std::to_string(f->ntot) +
+                   " rows need " + std::to_string(L.end) + " bytes of the " +
+                   std::to_string((size_t)PARAC_STATIC_SCRATCH_BYTES) +
+                   "-byte static scratch (at most " +
+                   std::to_string(parac_pcg_static_max_rows()) + " rows)";
+    return PARAC_EINVAL;
+  }
+  parac_pcg_opts opt{};
+  opt.rtol = 1e-6;
+  opt.maxit = 10000;
+  if (o) {
+    opt = *o;
+    if (!(opt.rtol >= 0)) opt.rtol = 1e-6;
+    if (opt.maxit <= 0) opt.maxit = 10000;
+  }
+  opt.timing = 0;
+  if (opt.precision != PARAC_PREC_FP64 && opt.precision != PARAC_PREC_MIXED) {
+    g_last_error = "bad precision";
+    return PARAC_EINVAL;
+  }
+  if (opt.precision == PARAC_PREC_MIXED && !f->Dinv32) {
+    g_last_error = "mixed precision needs a factor built with keep_fp32";
+    return PARAC_EINVAL;
+  }
+  // the factor's sweep work vectors come with it; nothing is allocated here
+  if (f->n && !(opt.precision == PARAC_PREC_MIXED ? f->wy32 : f->wy64)) {
+    g_last_error = "factor has no sweep work vectors for this precision";
+    return PARAC_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    char *base = static_scratch();
+    check_consistent(f, b, s, (double *)(base + L.r), (double *)(base + L.z),
+                     (int *)(base + L.bad));
+    TableMem tm;
+    tm.slots = (PcgSlot *)(base + L.slots);
+    tm.bslot = (int32_t *)(base + L.bslot);
+    tm.bslot_cap = kSlotMaxBlocks;
+    tm.aslots = (ApplySlot *)(base + L.aslots);
+    tm.wgmap = (int32_t *)(base + L.wgmap);
+    tm.wgmap_cap = kReadyGroupsMax;
+    PcgWork w{};
+    w.r = (double *)(base + L.r);
+    w.z = (double *)(base + L.z);
+    w.p = (double *)(base + L.p);
+    w.q = (double *)(base + L.q);
+    w.partial = (double *)(base + L.partial);
+    w.dst = (double *)(base + L.dst);
+    w.ist = (int *)(base + L.ist);
+    w.tables = &tm;
+    w.events = false;
+    return pcg_run(A, f, b, x, opt, st, s, w);
+  } catch (Err &e) {
+    if (st) st->status = e.code;
+    return status_from(e);
+  }
+}
+
+int64_t parac_pcg_static_max_rows(void) {
+  // the largest ntot whose layout fits: the fixed part, then 4 vectors
+  const StaticLayout L0 = static_layout(1);
+  const size_t fixed = L0.end - 4 * 256;
+  const size_t avail = (size_t)PARAC_STATIC_SCRATCH_BYTES - fixed;
+  return (int64_t)((avail / 4) & ~(size_t)255) / (int64_t)sizeof(double);
 }
 
 parac_status parac_block_shape_set(parac_factor_t f, int32_t cols, int32_t precision,

@@ -106,6 +106,10 @@ def lib():
         L.parac_apply.argtypes = [P, P, P, C.c_int64, C.c_int32, P]
         L.parac_pcg.argtypes = [C.POINTER(parac_csr), P, P, P, C.c_int64,
                                 C.POINTER(parac_pcg_opts), C.POINTER(parac_pcg_stats), P]
+        L.parac_pcg_static.argtypes = [C.POINTER(parac_csr), P, P, P, C.POINTER(parac_pcg_opts),
+                                       C.POINTER(parac_pcg_stats), P]
+        L.parac_pcg_static_max_rows.argtypes = []
+        L.parac_pcg_static_max_rows.restype = C.c_int64
         L.parac_serve.argtypes = [C.POINTER(parac_request), C.c_int64,
                                   C.POINTER(parac_serve_opts), C.POINTER(parac_result)]
         L.parac_block_shape_set.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(parac_block_shape)]
@@ -121,7 +125,8 @@ def lib():
         L.parac_status_str.argtypes = [C.c_int]
         L.parac_last_error.restype = C.c_char_p
         for name in ("parac_factor", "parac_factor_info", "parac_factor_export", "parac_apply",
-                     "parac_pcg", "parac_serve", "parac_block_shape_set", "parac_block_shape_get"):
+                     "parac_pcg", "parac_pcg_static", "parac_serve", "parac_block_shape_set",
+                     "parac_block_shape_get"):
             getattr(L, name).restype = C.c_int
         L.parac_factor_free.restype = None
         _lib = L
@@ -235,6 +240,27 @@ def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=None, rtol=1e-6, maxit=10000,
     return [dict(status=s.status, iterations=s.iterations, relres=s.relres,
                  true_relres=s.true_relres, ms_total=s.ms_total, ms_apply=s.ms_apply,
                  applies=s.applies, ms_fwd=s.ms_fwd) for s in st]
+
+
+def parac_pcg_static(A: DeviceCSR, f: Factor, b, x, rtol=1e-6, maxit=10000,
+                     precision=PREC_FP64, check_every=8, stream=None):
+    """parac_pcg_static: single right-hand-side PCG whose per-call buffers
+    live in the library's fixed device array (no device allocation).
+    Returns one stat dict; raises on EINVAL/EINCONSISTENT."""
+    o = parac_pcg_opts(rtol, maxit, precision, check_every, 0)
+    st = parac_pcg_stats()
+    rc = lib().parac_pcg_static(C.byref(A.c), f.h, C.c_void_p(b.data_ptr()),
+                                C.c_void_p(x.data_ptr()), C.byref(o), C.byref(st),
+                                _stream(stream))
+    if rc not in (OK, ENOCONV):
+        _raise(rc)
+    return dict(status=st.status, iterations=st.iterations, relres=st.relres,
+                true_relres=st.true_relres, applies=st.applies)
+
+
+def pcg_static_max_rows():
+    """Largest system (rows, ground vertex included) parac_pcg_static takes."""
+    return int(lib().parac_pcg_static_max_rows())
 
 
 def parac_factor_host(A, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, threads=0):
