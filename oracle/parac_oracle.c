@@ -19,12 +19,12 @@
  *      "not a Laplacian".  SDDM inputs get a ground vertex with the last
  *      label n, joined to every i with s_i > 0 by an edge of weight s_i
  *      (§V: ground node of the augmented Laplacian).
- *  R2  merge of parallel edges (Alg. 3/4 "merge duplicates"): gathered
+ *  R2  merge of parallel edges (Alg. 3/4, duplicate fill edges): gathered
  *      entries are sorted by the key (u, src) with src = -1 for input edges
  *      and the producing pivot's label for fill; a run of equal u is summed
  *      by a left fold in key order; its length is the multiplicity m_u.
  *  R3  sampling order (Alg. 2 sort step): ascending by (w_u, u).
- *  R4  suffix sums (Alg. 3/4 "(parallel) suffix sums"): tiles of 64 sorted
+ *  R4  suffix sums of the sorted weights (Alg. 3/4): tiles of 64 sorted
  *      positions starting at position 1; inside a tile Hillis-Steele steps
  *      with offsets 1,2,4,...,32 computed from the previous step's values and
  *      adding only partners inside the tile; tile totals carried right to
@@ -45,7 +45,16 @@
  *      not given): a row of F y = P r or F^T x = D^+ y with start value s
  *      and products p_1..p_m in ascending column order is the left fold
  *      ((s - p_1) - p_2) - ... - p_m.  Other summation orders (the GPU
- *      library's chunked one among them) agree with it to rounding.
+ *      library's tree order among them) agree with it to rounding.
+ *  R18 AC(k) (§V-B, the variant with k samples per entry): each merged
+ *      neighbour u of the pivot enters the sampling as k consecutive slots
+ *      of weight w_u / k (so the slot order is (w, u, copy) ascending); R4
+ *      to R7 run over the k d slots, D_k being the first suffix sum of the
+ *      slot weights; a slot whose drawn partner is a copy of the same
+ *      neighbour yields a loop, which adds nothing to a Laplacian and is
+ *      dropped (no record, no counter increment).  R8 and the decrements
+ *      still use the merged neighbours.  k = 1 is the plain method, bit for
+ *      bit.
  *  R17 mixed precision (FP32 preconditioner apply): D^+_i = 1/D_i is
  *      formed in FP64 and rounded to FP32; factor values are rounded to FP32;
  *      r is rounded to FP32 on entry and z widened to FP64 on exit; every
@@ -201,6 +210,7 @@ typedef struct {
   /* trace */
   int32_t want_trace; int64_t *trace; int64_t ntr, captr;
   int32_t debug_flags;
+  int32_t samples;  /* R18: sampling slots per merged neighbour (1: plain) */
   int32_t error;
   int64_t n_fill, max_gather, max_deg;
 } orc_state;
@@ -268,7 +278,7 @@ static void orc_suffix_sums(const double *x, int64_t d, double *S,
 
 /* one draw: offset into the candidate range [s+1, d-1] */
 static int orc_choose(orc_state *st, int32_t k, int64_t s, int64_t d,
-                      const orc_nbr *nb, const double *S, int64_t *qstar) {
+                      const double *xw, const double *S, int64_t *qstar) {
   if (st->forced) {
     int64_t off = st->iforced < st->nforced ? st->forced[st->iforced] : 0;
     st->iforced++;
@@ -283,7 +293,7 @@ static int orc_choose(orc_state *st, int32_t k, int64_t s, int64_t d,
       if (!st->ch_pick || !st->ch_prob) return ORC_ENOMEM;
       st->ch_nopt[st->nch] = (int32_t)nopt;
       st->ch_pick[st->nch] = (int32_t)off;
-      st->ch_prob[st->nch] = nb[q].w / S[s + 1];
+      st->ch_prob[st->nch] = xw[q] / S[s + 1];
       st->nch++;
     }
     *qstar = q;
@@ -367,19 +377,27 @@ static int orc_eliminate(orc_state *st, int32_t k, orc_worker *wk) {
   memcpy(st->nb_u, st->nb, (size_t)d * sizeof(orc_nbr)); /* u-ascending */
   /* R3: sampling order */
   qsort(st->nb, (size_t)d, sizeof(orc_nbr), cmp_nbr_wu);
+  /* R18: the sampling slots, `ks` per merged neighbour (one: the plain
+   * method); slot i belongs to neighbour i / ks */
+  const int64_t ks = st->samples > 1 ? st->samples : 1;
+  const int64_t ds = d * ks;
+  if ((rc = orc_scratch(st, ds))) return rc;
+  for (int64_t i = 0; i < ds; ++i) st->x[i] = st->nb[i / ks].w / (double)ks;
   /* R4, R5 */
-  for (int64_t i = 0; i < d; ++i) st->x[i] = st->nb[i].w;
-  orc_suffix_sums(st->x, d, st->S, st->tmp);
+  orc_suffix_sums(st->x, ds, st->S, st->tmp);
   double Dk = st->S[0];
   st->D[k] = Dk;
-  /* R6, R7: one sampled edge per slot p = 1..d-1 (Alg. 2) */
-  ORC_GROW(wk->ops, wk->n, wk->cap, 2 * d, orc_op);
-  for (int64_t s = 0; s + 1 < d; ++s) {
+  /* R6, R7: one draw per slot p = 1..ds-1 (Alg. 2); a loop is dropped */
+  ORC_GROW(wk->ops, wk->n, wk->cap, ds + d, orc_op);
+  int64_t ninsert = 0;
+  for (int64_t s = 0; s + 1 < ds; ++s) {
     int64_t q;
-    rc = orc_choose(st, k, s, d, st->nb, st->S, &q);
+    rc = orc_choose(st, k, s, ds, st->x, st->S, &q);
     if (rc) return rc;
-    double c = (st->S[s + 1] * st->nb[s].w) / Dk;
-    int32_t a = st->nb[s].u, b = st->nb[q].u;
+    int32_t a = st->nb[s / ks].u, b = st->nb[q / ks].u;
+    if (a == b) continue;
+    double c = (st->S[s + 1] * st->x[s]) / Dk;
+    ++ninsert;
     orc_op *op = &wk->ops[wk->n++];
     op->kind = OP_INSERT;
     op->a = a < b ? a : b;     /* target: smaller label */
@@ -407,7 +425,7 @@ static int orc_eliminate(orc_state *st, int32_t k, orc_worker *wk) {
     /* planted mistake: decrements before insertions */
     orc_op *tmp = (orc_op *)malloc((size_t)wk->n * sizeof(orc_op));
     if (!tmp) return ORC_ENOMEM;
-    int64_t ni = d - 1, t = 0;
+    int64_t ni = ninsert, t = 0;
     for (int64_t i = ni; i < wk->n; ++i) tmp[t++] = wk->ops[i];
     for (int64_t i = 0; i < ni; ++i) tmp[t++] = wk->ops[i];
     memcpy(wk->ops, tmp, (size_t)wk->n * sizeof(orc_op));
@@ -474,7 +492,7 @@ int orc_factor(int64_t n, const int64_t *rowptr, const int32_t *col,
                const double *val, const int32_t *perm, uint64_t seed,
                int32_t mode_req, int32_t schedule, uint64_t sched_seed,
                int32_t nworkers, const int32_t *forced, int64_t nforced,
-               int32_t want_trace, int32_t debug_flags,
+               int32_t want_trace, int32_t debug_flags, int32_t samples,
                orc_factor_result **out) {
   *out = NULL;
   orc_factor_result *res = (orc_factor_result *)calloc(1, sizeof(*res));
@@ -503,6 +521,7 @@ int orc_factor(int64_t n, const int64_t *rowptr, const int32_t *col,
   st.ntot = ntot; st.seed = seed; st.forced = forced; st.nforced = nforced;
   st.log_choices = forced != NULL; st.want_trace = want_trace;
   st.debug_flags = debug_flags;
+  st.samples = samples > 1 ? samples : 1;
   int64_t nt1 = ntot > 0 ? ntot : 1;
   st.uptr = (int64_t *)calloc((size_t)nt1 + 1, sizeof(int64_t));
   st.head = (int64_t *)malloc((size_t)nt1 * sizeof(int64_t));

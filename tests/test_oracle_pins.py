@@ -206,7 +206,7 @@ def test_sddm_path_exact(orc):
 # ----------------------------------------------------------------------------
 # T3: unbiasedness E[F D F^T] = L by exact enumeration of sampling outcomes
 # ----------------------------------------------------------------------------
-def enumerate_expectation(orc, A, perm, limit=200000):
+def enumerate_expectation(orc, A, perm, limit=200000, samples=1):
     """Sum P(path) F D F^T over every sequence of sampling choices.  Each run
     of the oracle with a forced prefix completes it with first candidates and
     logs every slot's option count and the probability of the pick taken."""
@@ -214,7 +214,7 @@ def enumerate_expectation(orc, A, perm, limit=200000):
     stack = [[]]
     while stack:
         prefix = stack.pop()
-        f = orc.factor(A, perm=perm, forced=prefix)
+        f = orc.factor(A, perm=perm, forced=prefix, samples=samples)
         assert f.status == orc.OK
         picks = list(f.choice_pick)
         for pos in range(len(prefix), len(picks)):
@@ -604,3 +604,75 @@ def test_large_degree_sum_within_bound(orc):
         f = orc.factor(A, seed=2)
         exact = math.fsum(w)
         assert abs(f.D[0] - exact) <= d * np.finfo(float).eps * exact
+
+
+# ----------------------------------------------------------------------------
+# R18: AC(k), k samples per entry (§V-B)
+# ----------------------------------------------------------------------------
+def ack_case(name):
+    rng = np.random.default_rng(100 + ["k4", "s3", "grid2x3", "p3_sddm", "p3"].index(name))
+    excess = None
+    if name == "p3":
+        n = 3
+        i, j = np.array([0, 1]), np.array([1, 2])
+    elif name == "k4":
+        n = 4
+        i, j = inputs.complete_edges(4)
+    elif name == "s3":
+        n = 4
+        i, j = np.zeros(3, int), np.arange(1, 4)
+    elif name == "grid2x3":
+        n = 6
+        i, j = inputs.grid2d_edges(2, 3)
+    else:
+        n = 3
+        i, j = np.array([0, 1]), np.array([1, 2])
+        excess = np.array([0.4, 0.0, 1.1])
+    A = lap(n, i, j, rng.uniform(0.2, 3.0, len(i)), excess)
+    perm = rng.permutation(n).astype(np.int32)
+    hub = int(np.argmax(np.diff(A.rowptr)))
+    first = int(np.where(perm == 0)[0][0])
+    perm[[hub, first]] = perm[[first, hub]]
+    return A, perm, excess
+
+
+@pytest.mark.parametrize("name,k", [("k4", 2), ("p3", 3), ("s3", 2), ("grid2x3", 2),
+                                    ("p3_sddm", 2)])
+def test_ack_unbiased_exact_enumeration(orc, name, k):
+    """AC(k) draws over k slots of weight w/k per neighbour and drops loops;
+    the expectation over every sampling path is still L (exact enumeration;
+    a wrong slot weight, a kept loop or a wrong D_k would miss it)."""
+    A, perm, excess = ack_case(name)
+    E, ptot, paths = enumerate_expectation(orc, A, perm, samples=k)
+    ref = permuted_dense(A, perm, excess=excess)
+    assert paths > 1
+    assert abs(ptot - 1.0) < 1e-12
+    assert np.max(np.abs(E - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_ack_more_samples_more_fill_same_invariants(orc):
+    """k = 1 is the plain method bit for bit; k = 2 draws about twice as many
+    fill edges; the factor keeps the invariants of §IV (unit lower F with
+    non-positive entries strictly below the diagonal, D >= 0, one zero pivot)."""
+    rng = np.random.default_rng(77)
+    n = 300
+    i, j = inputs.connected_random_edges(n, 3 * n, rng)
+    A = lap(n, i, j, rng.uniform(0.1, 2.0, len(i)))
+    perm = rng.permutation(n).astype(np.int32)
+    f0 = orc.factor(A, perm=perm, seed=9)
+    f1 = orc.factor(A, perm=perm, seed=9, samples=1)
+    assert np.array_equal(f0.colptr, f1.colptr) and np.array_equal(f0.rowind, f1.rowind)
+    assert np.array_equal(f0.val.view(np.uint64), f1.val.view(np.uint64))
+    assert np.array_equal(f0.D.view(np.uint64), f1.D.view(np.uint64))
+    f2 = orc.factor(A, perm=perm, seed=9, samples=2)
+    assert f2.status == orc.OK
+    assert f2.stats["n_fill"] > 1.5 * f0.stats["n_fill"]
+    assert np.all(f2.val < 0.0) and np.all(f2.D >= 0.0)
+    assert np.sum(f2.D == 0.0) == 1
+    for c in range(f2.ntot):
+        rows = f2.rowind[f2.colptr[c]:f2.colptr[c + 1]]
+        assert np.all(rows > c) and np.all(np.diff(rows) > 0)
+    # the preconditioner still solves the system
+    b = inputs.rhs(n, rng)
+    x, st = orc.pcg(A, f2, b, rtol=1e-8)
+    assert st["status"] == 0
