@@ -20,9 +20,11 @@
  *      label n, joined to every i with s_i > 0 by an edge of weight s_i
  *      (§V: ground node of the augmented Laplacian).
  *  R2  merge of parallel edges (Alg. 3/4, duplicate fill edges): gathered
- *      entries are sorted by the key (u, src) with src = -1 for input edges
- *      and the producing pivot's label for fill; a run of equal u is summed
- *      by a left fold in key order; its length is the multiplicity m_u.
+ *      entries are sorted by the key (u, src, w) with src = -1 for input
+ *      edges and the producing pivot's label for fill (w only orders the
+ *      repeated draws of one pair in one AC(k) pivot, R18); a run of equal u
+ *      is summed by a left fold in key order; its length is the multiplicity
+ *      m_u.
  *  R3  sampling order (Alg. 2 sort step): ascending by (w_u, u).
  *  R4  suffix sums of the sorted weights (Alg. 3/4): tiles of 64 sorted
  *      positions starting at position 1; inside a tile Hillis-Steele steps
@@ -240,6 +242,9 @@ static int cmp_ent_usrc(const void *pa, const void *pb) {
   const orc_ent *a = (const orc_ent *)pa, *b = (const orc_ent *)pb;
   if (a->u != b->u) return a->u < b->u ? -1 : 1;
   if (a->src != b->src) return a->src < b->src ? -1 : 1;
+  /* equal (u, src): only AC(k) draws the same pair twice in one pivot;
+   * their weights order them, and equal weights are interchangeable */
+  if (a->w != b->w) return a->w < b->w ? -1 : 1;
   return 0;
 }
 
