@@ -24,8 +24,10 @@ Workloads (--workload):
                precision) and, for comparison, one at a time in FP64
 
 --order nnz replaces the random elimination order of a single-system
-workload by the NNZ-sorted one (ascending row count, random ties; the
-ordering the paper recommends for GPUs).
+workload by the NNZ-sorted one (ascending row count, ties by a seeded hash;
+the ordering the paper recommends for GPUs), --order mis by independent-set
+rounds (low degree first); both are computed on the device by parac_order
+before the timed steps (ordering is not part of the setup time).
 """
 import argparse
 import json
@@ -42,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE), scaled by the same counters on a copy of known size; valid only
 # for the kernel sources and the workload it was taken from
 TRAFFIC_PROFILES = {
-    ("chung_lu_22", "fwd64"): os.path.join(ROOT, "profiles", "k_ready_fwd_traffic_chung_lu_22.md"),
-    ("grid3d_128", "fwd64"): os.path.join(ROOT, "profiles", "k_ready_fwd_traffic_grid3d_128.md"),
+    "chung_lu_22": os.path.join(ROOT, "profiles", "k_ready_traffic_chung_lu_22.md"),
+    "grid3d_128": os.path.join(ROOT, "profiles", "k_ready_traffic_grid3d_128.md"),
 }
 SWEEP_SOURCES = ["ready.hip", "internal.hpp", "device.hpp"]
 
@@ -58,15 +60,16 @@ def sweep_source_hash():
 
 
 def measured_traffic(workload, kernel):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on this workload from the current sweep sources; else None."""
+    """HBM bytes per launch of `kernel` (e.g. "k_ready<double, true>") from
+    the committed counter summary, if it was taken on this workload from the
+    current sweep sources; else None."""
     import re
-    path = TRAFFIC_PROFILES.get((workload, kernel))
+    path = TRAFFIC_PROFILES.get(workload)
     if path is None or not os.path.exists(path):
         return None
     text = open(path).read()
     m1 = re.search(r"sweep-sources-sha256:\s*([0-9a-f]{64})", text)
-    m2 = re.search(r"hbm-bytes-per-launch:\s*([0-9]+)", text)
+    m2 = re.search(r"hbm-bytes-per-launch %s:\s*([0-9]+)" % re.escape(kernel), text)
     if not (m1 and m2) or m1.group(1) != sweep_source_hash():
         return None
     return int(m2.group(1))
@@ -121,13 +124,12 @@ def roofline(info, timing, elem, workload):
     """The dominant single kernel of a step (by time) against the HBM peak,
     with the other kernels of the hot path beside it."""
     N, n_off = info["n"], info["nnz_off"]
-    tag = "64" if elem == 8 else "32"
     T = "double" if elem == 8 else "float"
-    fwd = rl_entry("k_ready<%s, false> (forward sweep F y = P r, one launch)" % T,
-                   fwd_bytes(n_off, N, elem), timing["fwd_ms"],
-                   measured_traffic(workload, "fwd" + tag))
-    bwd = rl_entry("k_ready<%s, true> (backward sweep F^T x = D^+ y, one launch)" % T,
-                   bwd_bytes(n_off, N, elem), timing["bwd_ms"])
+    kf, kb = "k_ready<%s, false, 1>" % T, "k_ready<%s, true, 1>" % T
+    fwd = rl_entry("%s (forward sweep F y = P r, one launch)" % kf,
+                   fwd_bytes(n_off, N, elem), timing["fwd_ms"], measured_traffic(workload, kf))
+    bwd = rl_entry("%s (backward sweep F^T x = D^+ y, one launch)" % kb,
+                   bwd_bytes(n_off, N, elem), timing["bwd_ms"], measured_traffic(workload, kb))
     elim = rl_entry("k_eliminate (one factorisation, one persistent launch)",
                     elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N), timing["elim_ms"])
     per_step = {"fwd": timing["fwd_ms"] * timing["applies"],
@@ -157,7 +159,8 @@ def run_system(args, W, desc, precision, nrhs, mixed_extra=False):
     torch.cuda.synchronize()
 
     def step(timing):
-        f = parac.parac_factor(dA, perm=W.perm, seed=W.seed, keep_fp32=keep32)
+        f = parac.parac_factor(dA, perm=W.perm, seed=W.seed, keep_fp32=keep32,
+                               samples=args.samples)
         log("  factor: %.1f ms" % f.info()["ms_total"])
         sts = parac.parac_pcg(dA, f, b, x, rtol=args.rtol, precision=precision, timing=timing)
         info = f.info()
@@ -206,7 +209,8 @@ def run_system(args, W, desc, precision, nrhs, mixed_extra=False):
         "ms_per_step": round(ms_step, 3),
         "dtype": "f64" if precision == parac.PREC_FP64 else "f64 (apply f32)",
         "config": {"workload": desc, "n": N, "nnz_L": int(W.A.nnz), "rhs": nrhs,
-                   "seed": int(W.seed), "order": args.order, "parallelism": "one GPU"},
+                   "seed": int(W.seed), "order": args.order, "samples_per_entry": args.samples,
+                   "parallelism": "one GPU"},
         "t_setup_s": round(ms_setup / 1e3, 6),
         "t_solve_s": round(ms_solve / 1e3, 6),
         "t_eliminate_s": round(ms_elim / 1e3, 6),
@@ -301,7 +305,7 @@ def run_serve(args):
     lat1 = np.array(lat1)
 
     def serve(arr, what):
-        log("serving %s (continuous batching, FP32 apply, %d slots)" % (what, args.serve_slots))
+        log("serving %s (FP32 apply, %d systems in flight, a stream each)" % (what, args.serve_slots))
         rs = [dict(rq, arrival_s=float(a)) for rq, a in zip(reqs, arr)]
         t0 = time.perf_counter()
         res, _ = parac.parac_serve(rs, precision=parac.PREC_MIXED, max_slots=args.serve_slots)
@@ -322,7 +326,7 @@ def run_serve(args):
         "config": {"workload": "serve_200: %d SDDM systems, n log-uniform 1e3..1e6 (sum %d), "
                                "2D/3D grids, Chung-Lu, random geometric; Poisson arrivals at 0.7 / "
                                "mean one-at-a-time FP64 service time = %.3f/s; continuous "
-                               "batching, %d slots, FP32 apply"
+                               "serving, %d systems in flight on streams of their own, FP32 apply"
                                % (count, sum(ns), rate, args.serve_slots),
                    "systems": count, "sum_n": int(sum(ns)), "parallelism": "one GPU"},
         "all_converged": ok,
@@ -406,12 +410,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chung_lu_22")
-    ap.add_argument("--order", choices=["random", "nnz"], default="random")
+    ap.add_argument("--order", choices=["random", "nnz", "mis"], default="random")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--precision", choices=["default", "fp64", "mixed"], default="default")
+    ap.add_argument("--samples", type=int, default=1,
+                    help="AC(k): k sampling slots per merged neighbour (1: the plain method)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=200)
-    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a copy of 2^27 doubles five times (read 1 GiB, write 1 GiB per "
                          "launch): the reference for scaling HBM counters")
@@ -458,6 +464,13 @@ def main():
                     "avg degree 16, exponent 2.1, weights (0,1], %%s order; FP64 factor + %%s PCG "
                     "to 1e-6" % W.A.n)
             prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
+        elif name == "chung_lu_20":
+            W = inputs.chung_lu_workload(20)
+            desc = ("chung_lu_20: Chung-Lu Laplacian, 2^20 generated (largest component %d), "
+                    "avg degree 16, exponent 2.1, weights (0,1], %%s order; FP64 factor + %%s PCG "
+                    "to 1e-6 (a smaller member of the 2^22 family, for ordering and AC(k) "
+                    "studies)" % W.A.n)
+            prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
         elif name == "chung_lu_24_x32":
             W = inputs.chung_lu_workload(24, dbar=8.0, nrhs=32)
             desc = ("chung_lu_24_x32: Chung-Lu Laplacian, 2^24 generated (largest component %d), "
@@ -466,8 +479,12 @@ def main():
             prec = parac.PREC_FP64 if fp64 else parac.PREC_MIXED
         else:
             raise SystemExit("unknown workload " + name)
-        if args.order == "nnz":
-            W = inputs.with_nnz_order(W)
+        if args.order != "random":
+            import dataclasses
+            kind = parac.ORDER_NNZ if args.order == "nnz" else parac.ORDER_MIS
+            perm, rounds = parac.parac_order(W.A, kind, W.seed)
+            W = dataclasses.replace(W, perm=perm)
+            log("order %s computed on the device (%d rounds)" % (args.order, rounds))
         pdesc = "FP64" if prec == parac.PREC_FP64 else "FP32-apply (FP64 SpMV/dots/residuals)"
         desc = desc % (args.order, pdesc)
         nrhs = 32 if name == "chung_lu_24_x32" else 1

@@ -88,6 +88,11 @@ typedef struct {
   double timeout_s;       /* elimination watchdog (0 = 30 s)                */
   double tail_fraction;   /* share of pivots left to the single-workgroup
                              tail kernel (0 or negative = none; 1 = all)    */
+  int32_t samples;        /* AC(k) (§V-B): k sampling slots of weight w/k
+                             per merged neighbour, a draw between copies of
+                             one neighbour dropped; 0 or 1 = the plain
+                             method, at most 16.  A denser factor for fewer
+                             iterations.                                    */
 } parac_factor_opts;
 
 typedef struct {
@@ -139,9 +144,9 @@ parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
  * the elimination levels (a row depends only on rows of earlier levels).
  * Two sweeps, each a single launch in which every row starts as soon as the
  * rows it reads are solved; with nrhs > 1, chunks of up to 64 columns run as
- * one sweep pair per column in the same two launches (or level by level,
- * the factor read once per chunk, when a level-synchronous block shape is
- * fixed, see parac_block_shape_set).
+ * sweep slots of several columns each in the same two launches (the factor
+ * read once per slot; see parac_block_shape_set for the shape and how it is
+ * chosen).
  * Every column equals, bit for bit, the apply of that column alone.
  * The call returns after the result is complete.  Errors: EINVAL, ETIMEOUT
  * (a sweep's watchdog expired; the factor stays usable). */
@@ -149,26 +154,41 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z,
                          int64_t nrhs, int32_t precision, void *stream);
 
 /* Launch shape of the block apply for chunks of `cols` columns (2..64) in
- * one precision.  Results do not depend on it, only speed.
- *   cpl        0: one dependency-driven sweep pair per column, all columns
- *              in the same two launches (the default);
- *              1, 2 or 4: level-synchronous block launches with that many
- *              columns per lane (the factor read once for all columns)
- *   tail_rows  level-synchronous shapes: levels at most this wide, and all
- *              levels after them, are solved by a single workgroup (the rest
- *              one launch per level) */
+ * one precision.  The two triangular sweeps run one slot per group of
+ * cols_per_sweep columns, all slots in the same two launches; a slot reads
+ * each factor row once for all of its columns and sums every column exactly
+ * as the single-vector apply does.  Results do not depend on the shape, only
+ * speed.
+ *   cols_per_sweep  1, 2 or 4 (FP64); 1, 2, 4 or 8 (MIXED)
+ *   workgroups      cap on the sweep workgroups of one slot (0 = as many as
+ *                   its units need, at most 256; at most 1024)
+ *   source          (get) 0 fixed by parac_block_shape_set, 1 timed on first
+ *                   use in this process, 2 taken from the shape cache file
+ *   ms              (get) time of one block apply with this shape when it was
+ *                   timed, else 0
+ * Unless fixed, the shape is chosen on first use for (cols, precision): each
+ * candidate width is timed on the call's own vectors (a bounded budget of a
+ * few seconds) and the fastest kept in the handle and in the JSON file named
+ * by the environment variable PARAC_SHAPE_CACHE (default
+ * $HOME/.cache/parac_block_shapes.json; empty: no file), keyed by device
+ * architecture, precision, columns and the factor's size, depth and entries
+ * per row, each to the nearest power of two below. */
 typedef struct {
-  int32_t cpl;
-  int64_t tail_rows;
+  int32_t cols_per_sweep;
+  int32_t workgroups;
+  int32_t source;
+  float ms;
 } parac_block_shape;
 
-/* Fix (shape != NULL) or forget (shape == NULL: time again on next use)
- * the shape for (cols, precision).  Errors: EINVAL. */
+/* Fix (shape != NULL) or forget (shape == NULL: the next use takes the cache
+ * file's shape or times the candidates again) the shape for (cols,
+ * precision).  Errors: EINVAL. */
 parac_status parac_block_shape_set(parac_factor_t f, int32_t cols,
                                    int32_t precision,
                                    const parac_block_shape *shape);
 
-/* The shape in use for (cols, precision); EINVAL if none is fixed yet. */
+/* The shape in use for (cols, precision); EINVAL if none is fixed, timed or
+ * cached for this handle yet. */
 parac_status parac_block_shape_get(parac_factor_t f, int32_t cols,
                                    int32_t precision,
                                    parac_block_shape *shape);
@@ -199,9 +219,10 @@ typedef struct {
 /* Preconditioned conjugate gradients with x0 = 0 (§V methodology; the
  * textbook recurrence).  With nrhs > 1 the columns run as independent
  * recurrences (own alpha, beta and stopping test) in one block launch
- * sequence per chunk of 64 columns: matrix and factor are read once per
- * iteration for all columns of a chunk; a converged column is frozen while
- * the others go on.
+ * sequence per chunk of 64 columns: the matrix is read once per iteration
+ * for all columns of a chunk, the factor once per sweep slot of the block
+ * shape (parac_block_shape_set); a converged column is frozen while the
+ * others go on.
  *   A      the matrix the factor was built from (device arrays)
  *   b, x   device pointers, n x nrhs row-major; x is output only
  *   st     host array of nrhs stats (may be NULL)
@@ -268,26 +289,28 @@ typedef struct {
 typedef struct {
   size_t hbm_budget;      /* bytes the stream may hold resident (0 = 80% of
                              free device memory)                            */
-  int32_t max_slots;      /* concurrently admitted systems (0 = 32, at most
-                             256)                                           */
+  int32_t max_slots;      /* systems in flight at once, each on a stream of
+                             its own (0 = 4, the device's hardware queues;
+                             at most 64)                                    */
   int32_t precision;      /* PARAC_PREC_* for the batched PCG               */
   int32_t maxit;          /* per system (0 = 10000)                         */
   int32_t check_every;    /* batched iterations between convergence checks
                              (0 = 4)                                        */
 } parac_serve_opts;
 
-/* Continuous-batching serving loop (not in the paper, which solves one
- * system at a time; each system here is the §III factorisation followed by
- * the §V PCG).  Requests are replayed at their arrival times and admitted in
- * arrival order while a slot is free and the budget holds the request's
- * estimated peak footprint (input, elimination pools, factor, PCG vectors);
- * once set up, the reservation shrinks to the bytes actually resident.  A
- * worker thread uploads and factors admitted systems on its own stream while
- * the PCG iterations of all set-up systems advance together: one launch per
- * PCG phase covers every system in flight.  Each system's numbers depend on
- * its own data only, so its x is bit for bit the one parac_factor +
- * parac_pcg give for it alone (same seed, permutation and options).  Results
- * go to the caller's x as each system converges or reaches maxit.
+/* Continuous serving loop (not in the paper, which solves one system at a
+ * time; each system here is the §III factorisation followed by the §V PCG).
+ * Requests are replayed at their arrival times and admitted in arrival order
+ * while fewer than max_slots systems are in flight and the budget holds the
+ * request's peak footprint (its device copy, the factorisation's peak under
+ * the same sizing parac_factor uses, and the PCG vectors); once set up, the
+ * reservation shrinks to the bytes actually resident.  Every admitted system
+ * runs from upload to result on a worker thread with a HIP stream of its
+ * own, so systems in flight overlap on the device and a small system never
+ * waits for the launches of a large one.  Each system runs parac_factor's
+ * and parac_pcg's own code, so its x is bit for bit the one those calls give
+ * for it alone (same seed, permutation and options).  Results go to the
+ * caller's x as each system finishes.
  *   reqs, out  host arrays of n entries; request arrays are host memory,
  *              borrowed until the call returns
  * Errors: EINVAL for bad options, EDEVICE/ENOMEM if the device fails the
@@ -323,7 +346,8 @@ typedef struct {
  * a caller asks for by name; no GPU entry point calls it.
  *   A        host matrix (on_device must be 0)
  *   o        options (NULL = defaults); perm is a host pointer; workers,
- *            keep_fp32, timeout_s and tail_fraction are ignored
+ *            keep_fp32, timeout_s and tail_fraction are ignored; samples
+ *            above 1 (AC(k)) is rejected with EINVAL
  *   threads  worker threads (0 = the host's hardware threads)
  *   out      filled on success; release with parac_host_factor_free
  * Errors: EINVAL, ENOTLAP, ENOMEM, EINTERNAL (EPOOL is retried inside);
@@ -332,6 +356,37 @@ parac_status parac_factor_host(const parac_csr *A, const parac_factor_opts *o,
                                int32_t threads, parac_host_factor *out);
 void parac_host_factor_free(parac_host_factor *f);
 const char *parac_host_last_error(void);
+
+#define PARAC_ORDER_RANDOM 0 /* uniformly random permutation             */
+#define PARAC_ORDER_NNZ 1    /* ascending stored entries per row        */
+#define PARAC_ORDER_MIS 2    /* independent-set rounds, low degree first */
+
+/* An elimination order for parac_factor (perm[v] = label of vertex v),
+ * computed on the device.  The paper's ordering study (§V, "Ordering for
+ * ParAC") finds that the order sets the depth of the elimination's
+ * dependency DAG, on which both the parallel elimination and the triangular
+ * solves wait, and recommends NNZ-sorted order for GPUs.
+ *   kind   PARAC_ORDER_RANDOM: vertices sorted by h(i);
+ *          PARAC_ORDER_NNZ: by (pri(i), i);
+ *          PARAC_ORDER_MIS: local-minimum rounds: in round r an unplaced
+ *          vertex whose (pri, index) is below that of every neighbour not
+ *          placed in an earlier round joins round r (each round is an
+ *          independent set of the graph); vertices sorted by (round, pri, i)
+ *          where h(i) = the SplitMix64 output for state seed + i and
+ *          pri(i) = min(stored entries of row i, 2^20 - 1) << 24 | h(i) >> 40
+ *   A      the matrix (device arrays if A->on_device, else host arrays); only
+ *          its pattern is read
+ *   perm   [n] output, device pointer iff A->on_device
+ *   rounds optional host pointer: the number of MIS rounds (0 otherwise)
+ * The result depends only on the pattern, kind and seed (integer arithmetic
+ * throughout).  Errors: EINVAL. */
+parac_status parac_order(const parac_csr *A, int32_t kind, uint64_t seed,
+                         int32_t *perm, int32_t *rounds, void *stream);
+
+/* Device memory held by the library (diagnostics): what = 0 the bytes
+ * allocated now, 1 the peak since the last reset, 2 reset the peak to the
+ * current bytes and return it; -1 for another `what`. */
+int64_t parac_device_bytes(int32_t what);
 
 void parac_factor_free(parac_factor_t f);
 const char *parac_status_str(parac_status s);

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libparac.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["setup.hip", "eliminate.hip", "finalize.hip", "solve.hip", "block.hip", "serve.hip", "ready.hip", "api.hip"]
+SOURCES = ["setup.hip", "eliminate.hip", "finalize.hip", "solve.hip", "block.hip", "serve.hip",
+           "ready.hip", "order.hip", "api.hip"]
 # host-only C++ (the CPU elimination): built with g++, no GPU code
 HOST_SOURCES = ["host_parac.cpp"]
 ARCH = os.environ.get("PARAC_ARCH", "gfx950")

@@ -2,6 +2,7 @@
 // handle's accessors.  Host code only orchestrates: every step of the path
 // runs in the library's own kernels.
 #include <math.h>
+#include <unistd.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -36,6 +37,45 @@ void chk(hipError_t e, const char *what) {
   }
 }
 
+// device bytes the library holds (every allocation goes through dev_alloc /
+// dev_free), and the peak since the last reset
+std::mutex g_mem_mu;
+std::map<void *, size_t> g_mem_size;
+int64_t g_mem_live = 0, g_mem_peak = 0;
+
+// A serving worker allocates and frees in its own stream's order: hipMalloc
+// and hipFree wait for the whole device, so a small system being set up
+// would wait for a large one's solve to finish.
+thread_local hipStream_t g_alloc_stream = nullptr;
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+  const hipError_t e = g_alloc_stream ? hipMallocAsync(p, bytes, g_alloc_stream)
+                                      : hipMalloc(p, bytes);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_size[*p] = bytes;
+    g_mem_live += (int64_t)bytes;
+    g_mem_peak = std::max(g_mem_peak, g_mem_live);
+  }
+  return e;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_mem_size.find(p);
+    if (it != g_mem_size.end()) {
+      g_mem_live -= (int64_t)it->second;
+      g_mem_size.erase(it);
+    }
+  }
+  if (g_alloc_stream)
+    (void)hipFreeAsync(p, g_alloc_stream);
+  else
+    (void)hipFree(p);
+}
+
 // device allocations freed at scope exit unless kept
 struct Scratch {
   std::vector<void *> ptrs;
@@ -45,7 +85,7 @@ struct Scratch {
   T *alloc(int64_t n, const char *what) {
     void *p = nullptr;
     size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = dev_alloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       throw Err{PARAC_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) +
@@ -69,7 +109,7 @@ struct Scratch {
     return b;
   }
   void release_all() {
-    for (void *p : ptrs) (void)hipFree(p);
+    for (void *p : ptrs) dev_free(p);
     ptrs.clear();
     sizes.clear();
     total = 0;
@@ -124,26 +164,89 @@ int status_from(Err &e) {
 
 }  // namespace
 
-// first level of the single-workgroup tail for a width threshold: every
-// level from it on has at most `rows` rows and at most kTailEntries entries
-// in each direction
 constexpr double kSweepTimeoutS = 20.0;  // watchdog of one triangular sweep
-
-static int64_t tail_start(parac_factor_t f, int64_t rows) {
-  int64_t L0 = f->depth;
-  while (L0 > 0) {
-    const int64_t L = L0 - 1;
-    if (f->hlptr[L + 1] - f->hlptr[L] > rows) break;
-    if (f->hlqf[L + 1] - f->hlqf[L] > kTailEntries) break;
-    if (f->hlqb[L + 1] - f->hlqb[L] > kTailEntries) break;
-    --L0;
-  }
-  return L0;
-}
 
 // ---------------------------------------------------------------------------
 // factor
 // ---------------------------------------------------------------------------
+// the persistent elimination grid of a system of ntot vertices
+struct ElimSizing {
+  int nteam = 0, workers = 0, wgs = 0;
+};
+static ElimSizing elim_sizing(int64_t ntot, int opt_workers) {
+  const int maxwg = eliminate_max_workgroups();
+  if (maxwg <= 0) throw Err{PARAC_EDEVICE, "occupancy query failed"};
+  ElimSizing z;
+  // one workgroup in kTeamShare is a team for the largest pivots (none when
+  // the graph is too small to have any)
+  z.nteam = ntot > 4 * kTeamMin ? maxwg / kTeamShare : 0;
+  int64_t workers = ((maxwg - z.nteam) * kElimWaves) / kSubQueues * kSubQueues;
+  // no more workers than a sixteenth of the pivots could keep busy
+  workers = std::min<int64_t>(workers,
+                              std::max<int64_t>(kSubQueues, (ntot / 16) / kSubQueues * kSubQueues));
+  if (opt_workers > 0)
+    workers = std::min<int64_t>(workers, std::max(kSubQueues, opt_workers / kSubQueues * kSubQueues));
+  if (workers < kSubQueues) throw Err{PARAC_EDEVICE, "device too small for the persistent grid"};
+  z.workers = (int)workers;
+  z.wgs = z.workers / kElimWaves;
+  return z;
+}
+
+// capacities of the elimination's pools for pool factor pf
+struct PoolSizing {
+  int64_t pool_cap = 0, f_cap = 0, arena_cap = 0;
+  int pg_chunk = 0, f_chunk = 0;
+};
+static PoolSizing pool_sizing(int64_t ntot, int64_t nnz, double pf, int workers) {
+  PoolSizing p;
+  const int64_t base_entries = std::max<int64_t>(nnz, 64);
+  // pages double in size, so up to half of a target's page chain can be
+  // unused: twice the expected record count
+  const int64_t pool_base = (int64_t)(2.0 * pf * (double)base_entries);
+  // factor entries: about 1.6 nnz on grids, about 3 nnz on power-law graphs
+  const int64_t f_base = (int64_t)(pf * (double)base_entries) + ntot;
+  // per-worker reservations: small enough that their slack stays a fraction
+  // of the pools
+  p.pg_chunk = (int)std::min<int64_t>(kPageChunk, std::max<int64_t>(64, pool_base / (8 * workers)));
+  p.f_chunk = (int)std::min<int64_t>(kFChunk, std::max<int64_t>(64, f_base / (8 * workers)));
+  p.pool_cap = std::min<int64_t>(pool_base + (int64_t)workers * p.pg_chunk, (int64_t)INT32_MAX - 1);
+  p.f_cap = f_base + (int64_t)workers * p.f_chunk;
+  // scratch of the large-neighbourhood path: every worker keeps its own
+  // region (grown geometrically), so besides a share of the fill volume
+  // each worker gets room for up to 4096 entries (68 bytes each), fewer on
+  // small graphs (an overflow is retried with a larger pool factor)
+  const int64_t per_worker = std::min<int64_t>(4096, std::max<int64_t>(64, ntot / 4));
+  p.arena_cap = (int64_t)(pf * (double)base_entries) * 16 + (int64_t)workers * 68 * per_worker;
+  return p;
+}
+
+// an upper bound of the device bytes parac_factor holds at its peak for a
+// system of n vertices and nnz stored entries (ntot = n + sddm), at the
+// default pool factor: inputs (when copied from the host), checks, upper
+// adjacency, queues and inboxes, pools, and the finalised factor with its
+// solve layout and work vectors, factor entries bounded by the pool's f_cap
+static int64_t factor_peak_bytes(int64_t n, int64_t nnz, int sddm, bool host_input, bool keep32,
+                                 int opt_workers) {
+  const int64_t ntot = n + sddm;
+  const ElimSizing z = elim_sizing(ntot, opt_workers);
+  const PoolSizing ps = pool_sizing(ntot, nnz, 4.0, z.workers);
+  const int64_t nf = ps.f_cap, nch = nf / 64 + 1;
+  int64_t b = 0;
+  if (host_input) b += 8 * (n + 1) + 12 * nnz + 4 * n;
+  b += 64 + 8 * n + 4 * n + 4 * n + 4 * (n + 1);                                   // A1
+  b += 8 * ntot + 8 * (ntot + 1) + (int64_t)scan_tmp_bytes(ntot + 2) + 12 * (nnz + n + 1);  // A2
+  b += 4 * (ntot + kSubQueues) + 4 * (3 * kSubQueues * kTailStride + 3 * kTailStride) +
+       4 * ntot + 4 * (ntot + z.nteam + 1) + 8 * kTailStride + 4 * ntot + 16 * kInline * ntot +
+       4 * (kPages - 1) * ntot + 28 * ntot + 64;                                   // queues, inboxes
+  b += 16 * ps.pool_cap + 12 * ps.f_cap + ps.arena_cap;                             // pools
+  b += 2 * (8 * (ntot + 1) + 12 * nf + 4 * ntot);                                   // CSC, CSR
+  b += 4 * (ntot + 1) + 8 * (ntot + 2) + 4 * n + 8 * n + 16 * (n + 1) + 24 * nf;    // level copies
+  b += 16 * n + 16 * (ntot + 1) + 60 * ntot + 8 * n + 16 * (n + 1) + 8 * n;        // maps, lists
+  b += 2 * 16 * (n + nch) + 8 * ntot + 16 * ntot + 8 * nch;                         // units, roots, work
+  if (keep32) b += 4 * n + 8 * nf + 8 * ntot + 4 * nch;
+  return b + (1 << 20);
+}
+
 static void ensure_work(parac_factor_t f, int prec, hipStream_t s);
 
 static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o, hipStream_t s) {
@@ -161,6 +264,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     if (!(opt.timeout_s > 0)) opt.timeout_s = 30.0;
   }
   if (opt.mode < 0 || opt.mode > 2) throw Err{PARAC_EINVAL, "bad mode"};
+  if (opt.samples < 0 || opt.samples > 16) throw Err{PARAC_EINVAL, "bad samples per entry"};
+  const int samples = opt.samples > 1 ? opt.samples : 1;
 
   Events ev;
   ev.create();
@@ -172,7 +277,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     bool ok = false;
     ~Guard() {
       if (!ok && f) {
-        for (void *p : f->owned) (void)hipFree(p);
+        for (void *p : f->owned) dev_free(p);
         delete f;
       }
     }
@@ -258,17 +363,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   const int64_t n_edges = read1(uptr + ntot, s);
 
   // persistent grid
-  int maxwg = eliminate_max_workgroups();
-  if (maxwg <= 0) throw Err{PARAC_EDEVICE, "occupancy query failed"};
-  // one workgroup in kTeamShare is a team for the largest pivots (none when
-  // the graph is too small to have any)
-  const int nteam = ntot > 4 * kTeamMin ? maxwg / kTeamShare : 0;
-  int workers = ((maxwg - nteam) * kElimWaves) / kSubQueues * kSubQueues;
-  // no more workers than a quarter of the pivots could keep busy
-  workers = std::min<int64_t>(workers, std::max<int64_t>(kSubQueues, (ntot / 4) / kSubQueues * kSubQueues));
-  if (opt.workers > 0) workers = std::min(workers, std::max(kSubQueues, opt.workers / kSubQueues * kSubQueues));
-  if (workers < kSubQueues) throw Err{PARAC_EDEVICE, "device too small for the persistent grid"};
-  const int wgs = workers / kElimWaves;
+  const ElimSizing ez = elim_sizing(ntot, opt.workers);
+  const int nteam = ez.nteam, workers = ez.workers, wgs = ez.wgs;
 
   // per-attempt state
   const int32_t cap_q = (int32_t)((ntot + kSubQueues - 1) / kSubQueues);
@@ -293,7 +389,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   unsigned long long *tops = tmp.alloc<unsigned long long>(8, "tops");
   int *err = flags;
 
-  double pf = opt.pool_factor;
+  // AC(k) draws about k times the fill: pools scale with it
+  double pf = opt.pool_factor * samples;
   int retries = 0;
   Rec *pool = nullptr;
   int32_t *frow = nullptr;
@@ -303,22 +400,11 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   unsigned long long htops[3] = {0, 0, 0};
   double ms_elim = 0.0;
   for (;;) {
-    const int64_t base_entries = std::max<int64_t>(nnz, 64);
-    // pages double in size, so up to half of a target's page chain can be
-    // unused: twice the expected record count
-    const int64_t pool_base = (int64_t)(2.0 * pf * (double)base_entries);
-    // factor entries: about 1.6 nnz on grids, about 3 nnz on power-law graphs
-    const int64_t f_base = (int64_t)(pf * (double)base_entries) + ntot;
-    // per-worker reservations: small enough that their slack stays a fraction
-    // of the pools
-    const int pg_chunk = (int)std::min<int64_t>(kPageChunk, std::max<int64_t>(64, pool_base / (8 * workers)));
-    const int f_chunk = (int)std::min<int64_t>(kFChunk, std::max<int64_t>(64, f_base / (8 * workers)));
-    pool_cap = std::min<int64_t>(pool_base + (int64_t)workers * pg_chunk, (int64_t)INT32_MAX - 1);
-    f_cap = f_base + (int64_t)workers * f_chunk;
-    // scratch of the large-neighbourhood path: every worker keeps its own
-    // region (grown geometrically), so besides a share of the fill volume
-    // each worker gets room for a few thousand entries (68 bytes each)
-    arena_cap = (int64_t)(pf * (double)base_entries) * 16 + (int64_t)workers * 68 * 4096;
+    const PoolSizing ps = pool_sizing(ntot, nnz, pf, workers);
+    const int pg_chunk = ps.pg_chunk, f_chunk = ps.f_chunk;
+    pool_cap = ps.pool_cap;
+    f_cap = ps.f_cap;
+    arena_cap = ps.arena_cap;
     pool = tmp.alloc<Rec>(pool_cap, "fill pool");
     frow = tmp.alloc<int32_t>(f_cap, "factor rows");
     fval = tmp.alloc<double>(f_cap, "factor values");
@@ -399,7 +485,8 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     ea.bq_head = bqc;
     ea.bq_tail = bqc + kTailStride;
     ea.bq_cap = bq_cap;
-    ea.team_min = nteam > 0 ? kTeamMin : 0;
+    ea.team_min = nteam > 0 && samples == 1 ? kTeamMin : 0;
+    ea.samples = samples;
     ea.team_wg0 = wgs;
     if (ntot > 0) chk(launch_eliminate(ea, wgs + nteam, s), "eliminate");
     chk(hipEventRecord(ev.e[2], s), "event");
@@ -417,8 +504,11 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
       for (void *p : {(void *)pool, (void *)frow, (void *)fval, (void *)arena}) {
         auto it = std::find(tmp.ptrs.begin(), tmp.ptrs.end(), p);
         if (it != tmp.ptrs.end()) {
-          (void)hipFree(p);
+          const size_t k = (size_t)(it - tmp.ptrs.begin());
+          tmp.total -= (int64_t)tmp.sizes[k];
+          tmp.sizes.erase(tmp.sizes.begin() + (std::ptrdiff_t)k);
           tmp.ptrs.erase(it);
+          dev_free(p);
         }
       }
       continue;
@@ -468,6 +558,12 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   unsigned long long hst[5];
   chk(hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s), "read");
   chk(hipStreamSynchronize(s), "sync");
+  // scheduler invariants (besides the kernel's own: a counter never goes
+  // below zero, a queue shard never takes more labels than it holds, so no
+  // vertex is enqueued twice): every vertex was eliminated, i.e. wrote its
+  // column count (-1 until then, read here as the largest unsigned value)
+  if (ntot > 0 && hst[1] > (unsigned long long)ntot)
+    throw Err{PARAC_EINTERNAL, "a vertex was not eliminated"};
   const int64_t depth = ntot > 0 ? (int64_t)hst[3] + 1 : 0;
   F->depth = depth;
   // rows (labels < n) grouped by level
@@ -702,11 +798,11 @@ static void ensure_work(parac_factor_t f, int prec, hipStream_t s) {
   if (*py) return;
   const size_t el = mixed ? 4 : 8;
   const int64_t m = std::max<int64_t>(f->ntot, 1), c = std::max<int64_t>(f->ncs, 1);
-  chk(hipMalloc(py, m * el), "work vector");
+  chk(dev_alloc(py, m * el), "work vector");
   f->owned.push_back(*py);
-  chk(hipMalloc(px, m * el), "work vector");
+  chk(dev_alloc(px, m * el), "work vector");
   f->owned.push_back(*px);
-  chk(hipMalloc(pc, c * el), "chunk sums");
+  chk(dev_alloc(pc, c * el), "chunk sums");
   f->owned.push_back(*pc);
   f->bytes += (int64_t)((2 * m + c) * el);
   reset_work(f, prec, s);
@@ -724,27 +820,6 @@ static void check_sweeps(parac_factor_t f, int prec, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // block apply (several right-hand sides, chunks of at most kBlockCols)
 // ---------------------------------------------------------------------------
-static void ensure_bwork(parac_factor_t f, int prec, int nc) {
-  const int k = prec_slot(prec);
-  if (f->bcols[k] >= nc) return;
-  const size_t el = k ? 4 : 8;
-  for (void **pp : {&f->bwy[k], &f->bwx[k]}) {
-    if (!*pp) continue;
-    f->owned.erase(std::remove(f->owned.begin(), f->owned.end(), *pp), f->owned.end());
-    (void)hipFree(*pp);
-    *pp = nullptr;
-    f->bytes -= (int64_t)((size_t)std::max<int64_t>(f->ntot, 1) * (size_t)f->bcols[k] * el);
-  }
-  f->bcols[k] = 0;
-  const size_t m = (size_t)std::max<int64_t>(f->ntot, 1) * (size_t)nc;
-  chk(hipMalloc(&f->bwy[k], m * el), "block work vector");
-  f->owned.push_back(f->bwy[k]);
-  chk(hipMalloc(&f->bwx[k], m * el), "block work vector");
-  f->owned.push_back(f->bwx[k]);
-  f->bcols[k] = nc;
-  f->bytes += 2 * (int64_t)(m * el);
-}
-
 // column sweeps: every column's work vectors and chunk sums pending, its
 // counters clear (the state each sweep pair starts from and leaves)
 static void reset_cwork(parac_factor_t f, int prec, hipStream_t s) {
@@ -762,26 +837,32 @@ static void reset_cwork(parac_factor_t f, int prec, hipStream_t s) {
   chk(hipMemsetAsync(f->cctr[k], 0, 2 * nc * sizeof(int32_t), s), "memset");
 }
 
-static void ensure_cwork(parac_factor_t f, int prec, int nc, hipStream_t s) {
+// columns of the sweep state for nc columns in slots of up to kMaxSweepCols
+// (the last slot of a block may be partly filled)
+constexpr int kMaxSweepCols = 8;
+static int padded_cols(int nc) { return (nc + kMaxSweepCols - 1) / kMaxSweepCols * kMaxSweepCols; }
+
+static void ensure_cwork(parac_factor_t f, int prec, int nc_, hipStream_t s) {
   const int k = prec_slot(prec);
+  const int nc = padded_cols(nc_);
   if (f->ccols[k] >= nc) return;
   const size_t el = k ? 4 : 8;
   const int64_t m0 = std::max<int64_t>(f->ntot, 1), c0 = std::max<int64_t>(f->ncs, 1);
   for (void **pp : {&f->cy[k], &f->cx[k], &f->ccs[k], (void **)&f->cctr[k]}) {
     if (!*pp) continue;
     f->owned.erase(std::remove(f->owned.begin(), f->owned.end(), *pp), f->owned.end());
-    (void)hipFree(*pp);
+    dev_free(*pp);
     *pp = nullptr;
   }
   f->bytes -= f->ccols[k] * (int64_t)((2 * m0 + c0) * el + 2 * sizeof(int32_t));
   f->ccols[k] = 0;
-  chk(hipMalloc(&f->cy[k], (size_t)(m0 * nc) * el), "column work vector");
+  chk(dev_alloc(&f->cy[k], (size_t)(m0 * nc) * el), "column work vector");
   f->owned.push_back(f->cy[k]);
-  chk(hipMalloc(&f->cx[k], (size_t)(m0 * nc) * el), "column work vector");
+  chk(dev_alloc(&f->cx[k], (size_t)(m0 * nc) * el), "column work vector");
   f->owned.push_back(f->cx[k]);
-  chk(hipMalloc(&f->ccs[k], (size_t)(c0 * nc) * el), "column chunk sums");
+  chk(dev_alloc(&f->ccs[k], (size_t)(c0 * nc) * el), "column chunk sums");
   f->owned.push_back(f->ccs[k]);
-  chk(hipMalloc((void **)&f->cctr[k], (size_t)(2 * nc) * sizeof(int32_t)), "column counters");
+  chk(dev_alloc((void **)&f->cctr[k], (size_t)(2 * nc) * sizeof(int32_t)), "column counters");
   f->owned.push_back(f->cctr[k]);
   f->ccols[k] = nc;
   f->bytes += nc * (int64_t)((2 * m0 + c0) * el + 2 * sizeof(int32_t));
@@ -789,45 +870,178 @@ static void ensure_cwork(parac_factor_t f, int prec, int nc, hipStream_t s) {
 }
 
 struct Batch;
-static void build_cols(Batch &bt, parac_factor_t f, int nc, const double *r, int64_t ldr,
-                       double *z, int64_t ldz, int prec, const int *skip, int skip_stride,
-                       hipStream_t s);
-static void apply_cols(parac_factor_t f, int nc, const double *r, int64_t ldr, double *z,
-                       int64_t ldz, int prec, hipStream_t s);
+static void build_cols(Batch &bt, parac_factor_t f, int nc, const parac_block_shape &shp,
+                       const double *r, int64_t ldr, double *z, int64_t ldz, int prec,
+                       const int *skip, int skip_stride, hipStream_t s);
+static void apply_cols(parac_factor_t f, int nc, const parac_block_shape &shp, const double *r,
+                       int64_t ldr, double *z, int64_t ldz, int prec, hipStream_t s,
+                       float *ms = nullptr);
 
-// a block of nc columns: with cpl = 0 one dependency-driven sweep pair per
-// column, all columns in the same two launches; else level-synchronous block
-// launches of that shape (the factor read once for all columns)
-static void apply_block(parac_factor_t f, const parac_block_shape &shp, int nc, const double *r,
-                        int64_t ldr, double *z, int64_t ldz, int prec, const int *skip,
-                        hipStream_t s) {
-  if (f->n == 0) return;
-  if (shp.cpl == 0) {
-    apply_cols(f, nc, r, ldr, z, ldz, prec, s);
-    return;
-  }
-  ensure_bwork(f, prec, nc);
-  SolveArgs a = solve_args(f, skip);
-  BlockShape sh{shp.cpl, tail_start(f, shp.tail_rows)};
-  const int k = prec_slot(prec);
-  chk(launch_block_apply(a, f->hlptr.data(), sh, nc, r, ldr, f->bwy[k], f->bwx[k], z, ldz, prec,
-                         s),
-      "block apply");
+static bool shape_ok(const parac_block_shape &c, int prec) {
+  return ready_cols_ok(prec, c.cols_per_sweep) && c.workgroups >= 0 &&
+         c.workgroups <= kReadyGroupsMax;
 }
 
-// the shape for (nc, prec): fixed by the caller, else column sweeps
-static parac_block_shape block_shape(parac_factor_t f, int nc, int prec) {
+// ---------------------------------------------------------------------------
+// block-shape autotuner: the block apply of nc columns runs one sweep slot per
+// chunk of cols_per_sweep columns (the factor is read once per chunk); which
+// chunk width is fastest depends on the factor and the precision.  On first
+// use for (columns, precision) the candidates are timed on the caller's
+// vectors (every shape gives the same bits, so the timing runs are ordinary
+// applies) within a bounded budget, and the choice is kept in the handle and
+// in a JSON cache file keyed by device architecture, precision, columns and
+// the factor's shape class, so that later processes skip the timing.
+// ---------------------------------------------------------------------------
+constexpr double kTuneBudgetMs = 4000.0;  // stop timing further candidates past this
+
+static std::mutex g_shape_mu;
+static bool g_shape_loaded = false;
+static std::map<std::string, parac_block_shape> g_shape_cache;
+
+static std::string shape_cache_path() {
+  const char *e = getenv("PARAC_SHAPE_CACHE");
+  if (e) return std::string(e);  // empty: no cache file
+  const char *h = getenv("HOME");
+  if (!h || !*h) return std::string();
+  return std::string(h) + "/.cache/parac_block_shapes.json";
+}
+
+// the cache file: one object, "key": [cols_per_sweep, workgroups, ms]
+static void shape_cache_load() {
+  if (g_shape_loaded) return;
+  g_shape_loaded = true;
+  const std::string path = shape_cache_path();
+  if (path.empty()) return;
+  FILE *fp = fopen(path.c_str(), "r");
+  if (!fp) return;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), fp)) > 0) text.append(buf, got);
+  fclose(fp);
+  size_t i = 0;
+  for (;;) {
+    const size_t k0 = text.find('"', i);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = text.find('"', k0 + 1);
+    const size_t b0 = text.find('[', k1);
+    const size_t b1 = text.find(']', b0);
+    if (k1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+    int cps = 0, wg = 0;
+    double ms = 0.0;
+    if (sscanf(text.c_str() + b0, "[%d , %d , %lf]", &cps, &wg, &ms) == 3) {
+      parac_block_shape sh{};
+      sh.cols_per_sweep = cps;
+      sh.workgroups = wg;
+      sh.source = 2;
+      sh.ms = (float)ms;
+      g_shape_cache[text.substr(k0 + 1, k1 - k0 - 1)] = sh;
+    }
+    i = b1 + 1;
+  }
+}
+
+static void shape_cache_store() {
+  const std::string path = shape_cache_path();
+  if (path.empty()) return;
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  FILE *fp = fopen(tmp.c_str(), "w");
+  if (!fp) return;
+  fprintf(fp, "{\n");
+  size_t k = 0;
+  for (const auto &kv : g_shape_cache)
+    fprintf(fp, "  \"%s\": [%d, %d, %.4f]%s\n", kv.first.c_str(), kv.second.cols_per_sweep,
+            kv.second.workgroups, (double)kv.second.ms,
+            ++k < g_shape_cache.size() ? "," : "");
+  fprintf(fp, "}\n");
+  const bool ok = fclose(fp) == 0;
+  if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
+}
+
+static int log2_bucket(double v) { return v < 1.0 ? 0 : (int)floor(log2(v)); }
+
+// architecture, precision, columns and the factor's shape class: size,
+// depth and entries per row, each to the nearest power of two below
+static std::string shape_key(parac_factor_t f, int nc, int prec) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch = arch.substr(0, c);
+  }
+  char key[256];
+  snprintf(key, sizeof(key), "%s|%s|cols%d|n2^%d|depth2^%d|epr2^%d", arch.c_str(),
+           prec == PARAC_PREC_MIXED ? "fp32" : "fp64", nc, log2_bucket((double)f->ntot),
+           log2_bucket((double)f->depth),
+           log2_bucket((double)f->nnz_off / (double)std::max<int64_t>(f->ntot, 1)));
+  return key;
+}
+
+// candidates in the order they are timed: the widest chunks first (the
+// likeliest winners when the factor dominates the traffic)
+static std::vector<int> tune_candidates(int nc, int prec) {
+  std::vector<int> c;
+  for (int cps : {8, 4, 2, 1})
+    if (ready_cols_ok(prec, cps) && (cps == 1 || cps <= nc)) c.push_back(cps);
+  return c;
+}
+
+// the shape for (nc, prec): fixed by the caller, tuned earlier, cached, or
+// timed now on r -> z, which then holds the apply's result (*applied set)
+static parac_block_shape block_shape(parac_factor_t f, int nc, int prec, const double *r,
+                                     int64_t ldr, double *z, int64_t ldz, hipStream_t s,
+                                     bool *applied = nullptr) {
+  if (applied) *applied = false;
   const auto key = std::make_pair(nc, prec_slot(prec));
   auto it = f->shapes.find(key);
   if (it != f->shapes.end()) return it->second;
-  // column sweeps unless the caller fixed a level-synchronous shape
-  const parac_block_shape sweeps{0, kTailDefault};
-  f->shapes[key] = sweeps;
-  return sweeps;
-}
-
-static bool shape_ok(const parac_block_shape &c) {
-  return (c.cpl == 0 || c.cpl == 1 || c.cpl == 2 || c.cpl == 4) && c.tail_rows >= 0;
+  const std::string ck = shape_key(f, nc, prec);
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    shape_cache_load();
+    auto c = g_shape_cache.find(ck);
+    if (c != g_shape_cache.end() && shape_ok(c->second, prec)) {
+      parac_block_shape sh = c->second;
+      sh.source = 2;
+      f->shapes[key] = sh;
+      return sh;
+    }
+  }
+  parac_block_shape best{};
+  best.cols_per_sweep = 1;
+  best.source = 1;
+  best.ms = 0.f;
+  if (f->n == 0) {
+    f->shapes[key] = best;
+    return best;
+  }
+  double spent = 0.0;
+  bool have = false;
+  for (int cps : tune_candidates(nc, prec)) {
+    parac_block_shape cand{};
+    cand.cols_per_sweep = cps;
+    cand.workgroups = 0;
+    float ms = 0.f;
+    apply_cols(f, nc, cand, r, ldr, z, ldz, prec, s, &ms);
+    spent += ms;
+    if (!have || ms < best.ms) {
+      best = cand;
+      best.ms = ms;
+      have = true;
+    }
+    if (applied) *applied = true;
+    if (spent > kTuneBudgetMs) break;
+  }
+  best.source = 1;
+  f->shapes[key] = best;
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape_cache[ck] = best;
+    shape_cache_store();
+  }
+  return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -879,14 +1093,16 @@ struct SlotView {
 // sweeps, each system's dealt out round-robin so that every system starts
 // at once.  Uploads into bt.mem.
 static void build_apply_tables(Batch &bt, const std::vector<ApplySlot> &as,
-                               const std::vector<parac_factor_t> &fs, hipStream_t s) {
+                               const std::vector<parac_factor_t> &fs, hipStream_t s,
+                               int wgcap = 0) {
+  const int64_t cap = wgcap > 0 ? wgcap : kReadyGroupsDefault;
   const int ns = (int)as.size();
   std::vector<int32_t> g(ns);
   int32_t gmax = 0;
   for (int k = 0; k < ns; ++k) {
     const int64_t nt = std::max(fs[k]->ntask_f, fs[k]->ntask_b);
     const int64_t waves = kReadyThreads / 64;
-    g[k] = (int32_t)std::min<int64_t>((nt + waves - 1) / waves, kReadyGroupsMax);
+    g[k] = (int32_t)std::min<int64_t>((nt + waves - 1) / waves, cap);
     gmax = std::max(gmax, g[k]);
   }
   std::vector<int32_t> map;
@@ -943,6 +1159,9 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     as[k].cs = prec == PARAC_PREC_MIXED ? f->cs32 : f->cs64;
     as[k].ctr = f->ctr;
     as[k].z = ps[k].z;
+    as[k].ncols = 1;
+    as[k].skip_n = 1;
+    as[k].skip_stride = 0;
   }
   PcgSlot *dps;
   int32_t *dbs;
@@ -980,6 +1199,9 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hi
   as[0].cs = prec == PARAC_PREC_MIXED ? f->cs32 : f->cs64;
   as[0].ctr = f->ctr;
   as[0].z = z;
+  as[0].ncols = 1;
+  as[0].skip_n = 1;
+  as[0].skip_stride = 0;
   Batch bt;
   build_apply_tables(bt, as, {f}, s);
   bt.B.nslots = 1;
@@ -988,30 +1210,38 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hi
   check_sweeps(f, prec, s);
 }
 
-// the column sweeps of a block: column j of r (stride ldr) into column j of
-// z, each a slot of its own over the same factor; skip (optional) gives
-// column j's done flag at skip + j * skip_stride
-static void build_cols(Batch &bt, parac_factor_t f, int nc, const double *r, int64_t ldr,
-                       double *z, int64_t ldz, int prec, const int *skip, int skip_stride,
-                       hipStream_t s) {
+// the column sweeps of a block: columns [j c, (j + 1) c) of r (row stride
+// ldr) into the same columns of z, c = shp.cols_per_sweep columns per sweep
+// slot over the same factor; skip (optional) gives column i's done flag at
+// skip + i * skip_stride (a slot is skipped once all of its columns are done)
+static void build_cols(Batch &bt, parac_factor_t f, int nc, const parac_block_shape &shp,
+                       const double *r, int64_t ldr, double *z, int64_t ldz, int prec,
+                       const int *skip, int skip_stride, hipStream_t s) {
   ensure_cwork(f, prec, nc, s);
   const int k = prec_slot(prec);
   const size_t el = k ? 4 : 8;
+  const int cc = shp.cols_per_sweep;
   const int64_t m = std::max<int64_t>(f->ntot, 1), c = std::max<int64_t>(f->ncs, 1);
-  std::vector<ApplySlot> as(nc);
-  for (int j = 0; j < nc; ++j) {
-    as[j].a = solve_args(f, skip ? skip + (int64_t)j * skip_stride : f->zero);
+  const int ns = (nc + cc - 1) / cc;
+  std::vector<ApplySlot> as(ns);
+  for (int j = 0; j < ns; ++j) {
+    const int c0 = j * cc;
+    as[j].a = solve_args(f, skip ? skip + (int64_t)c0 * skip_stride : f->zero);
     as[j].ldr = ldr;
     as[j].ldz = ldz;
-    as[j].r = r + j;
-    as[j].y = (char *)f->cy[k] + (size_t)(j * m) * el;
-    as[j].x = (char *)f->cx[k] + (size_t)(j * m) * el;
-    as[j].cs = (char *)f->ccs[k] + (size_t)(j * c) * el;
+    as[j].r = r + c0;
+    as[j].y = (char *)f->cy[k] + (size_t)(c0 * m) * el;
+    as[j].x = (char *)f->cx[k] + (size_t)(c0 * m) * el;
+    as[j].cs = (char *)f->ccs[k] + (size_t)(c0 * c) * el;
     as[j].ctr = f->cctr[k] + 2 * j;
-    as[j].z = z + j;
+    as[j].z = z + c0;
+    as[j].ncols = std::min(cc, nc - c0);
+    as[j].skip_n = skip ? as[j].ncols : 1;
+    as[j].skip_stride = skip ? skip_stride : 0;
   }
-  build_apply_tables(bt, as, std::vector<parac_factor_t>(nc, f), s);
-  bt.B.nslots = nc;
+  build_apply_tables(bt, as, std::vector<parac_factor_t>(ns, f), s, shp.workgroups);
+  bt.B.nslots = ns;
+  bt.B.cc = cc;
 }
 
 static void check_col_sweeps(parac_factor_t f, int prec, hipStream_t s) {
@@ -1022,13 +1252,21 @@ static void check_col_sweeps(parac_factor_t f, int prec, hipStream_t s) {
   throw Err{PARAC_ETIMEOUT, "triangular sweep watchdog expired"};
 }
 
-static void apply_cols(parac_factor_t f, int nc, const double *r, int64_t ldr, double *z,
-                       int64_t ldz, int prec, hipStream_t s) {
+// one block apply; ms (optional) receives its time on the stream
+static void apply_cols(parac_factor_t f, int nc, const parac_block_shape &shp, const double *r,
+                       int64_t ldr, double *z, int64_t ldz, int prec, hipStream_t s, float *ms) {
   Batch bt;
-  build_cols(bt, f, nc, r, ldr, z, ldz, prec, nullptr, 0, s);
+  build_cols(bt, f, nc, shp, r, ldr, z, ldz, prec, nullptr, 0, s);
+  Events ev;
+  if (ms) {
+    ev.create();
+    chk(hipEventRecord(ev.e[0], s), "event");
+  }
   chk(slots_apply(bt.B, prec, s), "column sweeps");
+  if (ms) chk(hipEventRecord(ev.e[1], s), "event");
   chk(hipStreamSynchronize(s), "sync");
   check_col_sweeps(f, prec, s);
+  if (ms) *ms = (float)ev.ms(0, 1);
 }
 
 // device memory of one single-vector PCG: vectors r, z, p, q (n each),
@@ -1285,17 +1523,14 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
     chk(bpcg_launch_init(n, nc, o.rtol, b + c0, nrhs, x + c0, nrhs, r, p, partial, bst, bist, gfl,
                          s),
         "bpcg_init");
-    const parac_block_shape shp = block_shape(f, nc, o.precision);
-    // column sweeps: one batch for the whole solve, a converged column's
-    // sweeps skipped through its done flag
+    // the block apply's shape (timed on r -> z on first use: part of this
+    // call's time), then one batch of sweep slots for the whole solve, a
+    // slot skipped once all of its columns have converged
+    const parac_block_shape shp = block_shape(f, nc, o.precision, r, nc, z, nc, s);
     Batch cols;
-    if (shp.cpl == 0 && n > 0) build_cols(cols, f, nc, r, nc, z, nc, o.precision, bist + 1, 4, s);
+    if (n > 0) build_cols(cols, f, nc, shp, r, nc, z, nc, o.precision, bist + 1, 4, s);
     auto apply = [&]() {
-      if (shp.cpl == 0) {
-        if (n > 0) chk(slots_apply(cols.B, o.precision, s), "column sweeps");
-      } else {
-        apply_block(f, shp, nc, r, nc, z, nc, o.precision, gfl + 1, s);
-      }
+      if (n > 0) chk(slots_apply(cols.B, o.precision, s), "column sweeps");
     };
     int applies = 0;
     mark(false);
@@ -1328,7 +1563,7 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
                              partial, bst, bist, gfl, s),
         "bpcg_true_res");
     mark(true);  // last: end
-    if (shp.cpl == 0 && n > 0) check_col_sweeps(f, o.precision, s);
+    if (n > 0) check_col_sweeps(f, o.precision, s);
     std::vector<double> hst(8 * nc);
     std::vector<int> hist(4 * nc);
     chk(hipMemcpyAsync(hst.data(), bst, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s),
@@ -1387,33 +1622,34 @@ struct ServeSlot {
   std::string err;
   ~ServeSlot() {
     if (f) {
-      for (void *ptr : f->owned) (void)hipFree(ptr);
+      for (void *ptr : f->owned) dev_free(ptr);
       delete f;
     }
   }
 };
 
-// estimated peak device bytes of one request: input, PCG vectors, and the
-// elimination's pools and factor arrays at their largest (pool_factor 4)
-int64_t serve_estimate(int64_t n, int64_t nnz) {
-  const int64_t ntot = n + 1;
-  return 12 * nnz + 8 * (n + 1) + 6 * 8 * n + 170 * nnz + 340 * ntot + (1 << 20);
+// peak device bytes of one request: its device copy (CSR, b, perm), the
+// factorisation at its peak (the sizing parac_factor uses, pool factor 4; an
+// SDDM request has a ground vertex), and the PCG vectors and tables
+int64_t serve_estimate(int64_t n, int64_t nnz, int prec) {
+  const int64_t request = 8 * (n + 1) + 12 * nnz + 8 * n + 4 * n;
+  const int64_t pcg = 5 * 8 * n + 8 * kSlotMaxBlocks + 4096;
+  return request + factor_peak_bytes(n, nnz, 1, false, prec == PARAC_PREC_MIXED, 0) + pcg;
 }
 
-struct SetupQueue {
-  std::mutex m;
-  std::condition_variable cv_work, cv_done;
-  std::deque<std::unique_ptr<ServeSlot>> todo, done;
-  bool stop = false;
-};
-
-// upload and factor one admitted request (worker thread, its own stream)
-void serve_setup(ServeSlot &sl, const parac_request &rq, int prec, int maxit, double *st_pool,
-                 int *ist_pool, hipStream_t s) {
+// one request from upload to result, on the calling worker's stream: the
+// device copy of the request, parac_factor's factorisation, and parac_pcg's
+// single-system PCG (the same code, so the result is the same bits as those
+// two calls give for the request alone).  `bytes` is called with the bytes
+// the system holds once it is set up.
+template <class OnBytes>
+void serve_one(const parac_request &rq, const parac_serve_opts &o, parac_result &res,
+               hipStream_t s, OnBytes on_bytes) {
   const int64_t n = rq.A.n, nnz = rq.A.nnz;
   if (n < 0 || nnz < 0 || rq.A.on_device ||
       (n > 0 && (!rq.A.rowptr || !rq.A.col || !rq.A.val || !rq.b || !rq.x)))
     throw Err{PARAC_EINVAL, "a request needs host CSR arrays, b and x"};
+  ServeSlot sl;
   Scratch &M = sl.mem;
   int64_t *rp = M.alloc<int64_t>(n + 1, "request rowptr");
   int32_t *c = M.alloc<int32_t>(nnz, "request col");
@@ -1434,47 +1670,50 @@ void serve_setup(ServeSlot &sl, const parac_request &rq, int prec, int maxit, do
   fo.perm = pm;
   fo.mode = PARAC_MODE_AUTO;
   fo.pool_factor = 4.0;
-  fo.keep_fp32 = prec == PARAC_PREC_MIXED;
+  fo.keep_fp32 = o.precision == PARAC_PREC_MIXED;
   fo.timeout_s = 30.0;
   sl.f = factor_impl(&dA, &fo, s);
   if (sl.f->mode == PARAC_MODE_LAPLACIAN) check_consistent(sl.f, b, s);
-  sl.n = n;
-  sl.rowptr = rp;
-  sl.col = c;
-  sl.val = v;
-  sl.b = b;
-  sl.x = M.alloc<double>(n, "x");
-  sl.r = M.alloc<double>(n, "r");
-  sl.z = M.alloc<double>(n, "z");
-  sl.p = M.alloc<double>(n, "p");
-  sl.q = M.alloc<double>(n, "q");
-  ensure_work(sl.f, prec, s);
-  const double rtol = rq.rtol >= 0 ? rq.rtol : 1e-6;
-  const double hst0[8] = {0, 0, 0, 0, 0, 0, rtol, 0};
-  const int hist0[4] = {0, 0, maxit, 0};
-  chk(hipMemcpyAsync(st_pool + 8 * sl.id, hst0, sizeof(hst0), hipMemcpyHostToDevice, s), "upload");
-  chk(hipMemcpyAsync(ist_pool + 4 * sl.id, hist0, sizeof(hist0), hipMemcpyHostToDevice, s),
-      "upload");
+  double *x = M.alloc<double>(n, "x");
+  PcgWork w{};
+  w.r = M.alloc<double>(n, "r");
+  w.z = M.alloc<double>(n, "z");
+  w.p = M.alloc<double>(n, "p");
+  w.q = M.alloc<double>(n, "q");
+  w.partial = M.alloc<double>(slot_blocks(n), "partials");
+  w.dst = M.alloc<double>(8, "pcg scalars");
+  w.ist = M.alloc<int>(4, "pcg flags");
+  w.tables = nullptr;
+  w.events = false;
+  res.bytes_resident = M.total + sl.f->bytes;
+  on_bytes(res.bytes_resident);
+  parac_pcg_opts po{};
+  po.rtol = rq.rtol >= 0 ? rq.rtol : 1e-6;
+  po.maxit = o.maxit;
+  po.precision = o.precision;
+  po.check_every = o.check_every;
+  parac_pcg_stats st{};
+  const int rc = pcg_run(&dA, sl.f, b, x, po, &st, s, w);
+  if (n > 0) chk(hipMemcpyAsync(rq.x, x, n * sizeof(double), hipMemcpyDeviceToHost, s), "result");
   chk(hipStreamSynchronize(s), "sync");
-  sl.bytes = M.total + sl.f->bytes;
-}
-
-SlotView slot_view(ServeSlot &sl, double *st_pool, int *ist_pool) {
-  return SlotView{PcgSlot{sl.n, sl.rowptr, sl.col, sl.val, sl.b, sl.x, sl.r, sl.z, sl.p, sl.q,
-                          st_pool + 8 * sl.id, ist_pool + 4 * sl.id, 0, 0},
-                  sl.f};
+  res.status = rc;
+  res.iterations = st.iterations;
+  res.true_relres = st.true_relres;
 }
 
 }  // namespace
 
+// Continuous serving: requests are admitted in arrival order while fewer than
+// `streams` systems are in flight and the memory budget holds the request's
+// peak footprint; each admitted system runs from upload to result on a
+// worker thread with its own stream, so systems overlap on the device and a
+// small system never waits for a large one's launches.
 static int serve_impl(const parac_request *reqs, int64_t nreq, const parac_serve_opts &o,
                       parac_result *out) {
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
   auto now = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
-  const int prec = o.precision;
-  const int max_slots = o.max_slots;
-  const int K = o.check_every;
+  const int nstreams = std::max(1, o.max_slots);
   int dev = 0;
   chk(hipGetDevice(&dev), "hipGetDevice");
   size_t budget = o.hbm_budget;
@@ -1494,92 +1733,91 @@ static int serve_impl(const parac_request *reqs, int64_t nreq, const parac_serve
     return reqs[a].arrival_s < reqs[b].arrival_s;
   });
 
-  Scratch pools;
-  double *st_pool = pools.alloc<double>(8 * (int64_t)max_slots, "serve scalars");
-  int *ist_pool = pools.alloc<int>(4 * (int64_t)max_slots, "serve flags");
-  double *partial = pools.alloc<double>((int64_t)max_slots * kSlotMaxBlocks, "serve partials");
-  hipStream_t cs = nullptr;
-  chk(hipStreamCreate(&cs), "hipStreamCreate");
-  struct StreamFree {
-    hipStream_t &s;
-    ~StreamFree() {
-      if (s) (void)hipStreamDestroy(s);
-    }
-  } csfree{cs};
+  struct Job {
+    int64_t req;
+    int64_t est;
+  };
+  std::mutex m;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job> todo;
+  bool stop = false;
+  size_t reserved = 0;
+  int inflight = 0;
+  int64_t finished = 0;
 
-  // the setup worker
-  SetupQueue Q;
-  std::thread worker([&]() {
+  auto worker = [&]() {
     (void)hipSetDevice(dev);
-    hipStream_t ss = nullptr;
-    const bool have_stream = hipStreamCreate(&ss) == hipSuccess;
+    hipStream_t ws = nullptr;
+    const bool have_stream = hipStreamCreate(&ws) == hipSuccess;
+    // this thread's device memory comes and goes in its stream's order
+    if (have_stream) g_alloc_stream = ws;
     for (;;) {
-      std::unique_ptr<ServeSlot> sl;
+      Job job;
       {
-        std::unique_lock<std::mutex> lk(Q.m);
-        Q.cv_work.wait(lk, [&] { return Q.stop || !Q.todo.empty(); });
-        if (Q.todo.empty()) break;
-        sl = std::move(Q.todo.front());
-        Q.todo.pop_front();
+        std::unique_lock<std::mutex> lk(m);
+        cv_work.wait(lk, [&] { return stop || !todo.empty(); });
+        if (todo.empty()) break;
+        job = todo.front();
+        todo.pop_front();
       }
+      parac_result &res = out[job.req];
+      int64_t held = job.est;
       try {
-        if (!have_stream) throw Err{PARAC_EDEVICE, "setup stream"};
-        serve_setup(*sl, reqs[sl->req], prec, o.maxit, st_pool, ist_pool, ss);
+        if (!have_stream) throw Err{PARAC_EDEVICE, "serving stream"};
+        serve_one(reqs[job.req], o, res, ws, [&](int64_t bytes) {
+          // once set up, the reservation shrinks to the bytes actually held
+          std::lock_guard<std::mutex> lk(m);
+          reserved = reserved - (size_t)held + (size_t)bytes;
+          held = bytes;
+        });
       } catch (Err &e) {
-        sl->status = e.code;
-        sl->err = e.msg;
-      } catch (std::exception &e) {
-        sl->status = PARAC_EINTERNAL;
-        sl->err = e.what();
+        res.status = e.code;
+      } catch (std::exception &) {
+        res.status = PARAC_EINTERNAL;
       }
+      if (ws) (void)hipStreamSynchronize(ws);
       {
-        std::lock_guard<std::mutex> lk(Q.m);
-        Q.done.push_back(std::move(sl));
+        std::lock_guard<std::mutex> lk(m);
+        res.t_done = now();
+        reserved -= (size_t)held;
+        --inflight;
+        ++finished;
       }
-      Q.cv_done.notify_one();
+      cv_done.notify_one();
     }
-    if (ss) (void)hipStreamDestroy(ss);
-  });
+    g_alloc_stream = nullptr;
+    if (ws) {
+      (void)hipStreamSynchronize(ws);
+      (void)hipStreamDestroy(ws);
+    }
+  };
+  std::vector<std::thread> pool;
   struct Joiner {
-    SetupQueue &Q;
-    std::thread &t;
+    std::mutex &m;
+    std::condition_variable &cv;
+    bool &stop;
+    std::vector<std::thread> &t;
     ~Joiner() {
       {
-        std::lock_guard<std::mutex> lk(Q.m);
-        Q.stop = true;
+        std::lock_guard<std::mutex> lk(m);
+        stop = true;
       }
-      Q.cv_work.notify_all();
-      if (t.joinable()) t.join();
+      cv.notify_all();
+      for (auto &th : t)
+        if (th.joinable()) th.join();
     }
-  } joiner{Q, worker};
+  } joiner{m, cv_work, stop, pool};
+  for (int k = 0; k < nstreams; ++k) pool.emplace_back(worker);
 
-  std::vector<int> free_ids;
-  for (int k = max_slots - 1; k >= 0; --k) free_ids.push_back(k);
-  std::vector<std::unique_ptr<ServeSlot>> active;
-  int64_t next = 0, finished = 0, inflight = 0;
-  size_t reserved = 0;
-  Batch bt;
-  bool dirty = true;
-  std::vector<int> hflags(4 * (size_t)max_slots);
-
-  auto retire = [&](ServeSlot &sl, int status) {
-    parac_result &r = out[sl.req];
-    r.status = status;
-    r.t_done = now();
-    r.bytes_resident = sl.bytes;
-    reserved -= (size_t)(sl.bytes ? sl.bytes : sl.est);
-    free_ids.push_back(sl.id);
-    --inflight;
-    ++finished;
-  };
-
+  int64_t next = 0;
+  std::unique_lock<std::mutex> lk(m);
   while (finished < nreq) {
-    // 1. admission in arrival order
+    // admission in arrival order
     const double t = now();
     while (next < nreq && reqs[order[next]].arrival_s <= t) {
       const int64_t i = order[next];
       const int64_t est = serve_estimate(std::max<int64_t>(reqs[i].A.n, 0),
-                                         std::max<int64_t>(reqs[i].A.nnz, 0));
+                                         std::max<int64_t>(reqs[i].A.nnz, 0), o.precision);
       if ((size_t)est > budget) {
         out[i].status = PARAC_ENOMEM;
         out[i].t_admit = out[i].t_done = t;
@@ -1587,122 +1825,22 @@ static int serve_impl(const parac_request *reqs, int64_t nreq, const parac_serve
         ++finished;
         continue;
       }
-      if (free_ids.empty() || reserved + (size_t)est > budget) break;
-      auto sl = std::make_unique<ServeSlot>();
-      sl->req = i;
-      sl->id = free_ids.back();
-      free_ids.pop_back();
-      sl->est = est;
+      if (inflight >= nstreams || reserved + (size_t)est > budget) break;
       reserved += (size_t)est;
       ++inflight;
       out[i].t_admit = t;
-      {
-        std::lock_guard<std::mutex> lk(Q.m);
-        Q.todo.push_back(std::move(sl));
-      }
-      Q.cv_work.notify_one();
+      todo.push_back(Job{i, est});
+      cv_work.notify_one();
       ++next;
     }
-    // 2. systems the worker has set up: start their PCG, then join the batch
-    std::vector<std::unique_ptr<ServeSlot>> fresh;
-    {
-      std::lock_guard<std::mutex> lk(Q.m);
-      while (!Q.done.empty()) {
-        fresh.push_back(std::move(Q.done.front()));
-        Q.done.pop_front();
-      }
-    }
-    std::vector<std::unique_ptr<ServeSlot>> started;
-    for (auto &sl : fresh) {
-      if (sl->status != PARAC_OK) {
-        retire(*sl, sl->status);
-        continue;
-      }
-      reserved = reserved - (size_t)sl->est + (size_t)sl->bytes;
-      started.push_back(std::move(sl));
-    }
-    if (!started.empty()) {
-      std::vector<SlotView> v;
-      for (auto &sl : started) v.push_back(slot_view(*sl, st_pool, ist_pool));
-      Batch nb;
-      build_batch(nb, v, prec, partial, cs);
-      chk(slots_init(nb.B, cs), "serve init");
-      chk(slots_apply(nb.B, prec, cs), "serve apply");
-      chk(slots_rz(nb.B, 1, cs), "serve rz");
-      chk(hipStreamSynchronize(cs), "sync");
-      for (auto &sl : started) active.push_back(std::move(sl));
-      dirty = true;
-    }
-    if (active.empty()) {
-      // nothing to iterate: wait for the worker or the next arrival
-      std::unique_lock<std::mutex> lk(Q.m);
-      double wait = 1e-3;
-      if (inflight == 0 && next < nreq)
-        wait = std::max(0.0, reqs[order[next]].arrival_s - now());
-      if (Q.done.empty())
-        Q.cv_done.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.05)));
-      continue;
-    }
-    // 3. K batched iterations over every system in flight
-    if (dirty) {
-      std::vector<SlotView> v;
-      for (auto &sl : active) v.push_back(slot_view(*sl, st_pool, ist_pool));
-      build_batch(bt, v, prec, partial, cs);
-      dirty = false;
-    }
-    for (int it = 0; it < K; ++it) {
-      chk(slots_step(bt.B, cs), "serve step");
-      chk(slots_apply(bt.B, prec, cs), "serve apply");
-      chk(slots_rz(bt.B, 0, cs), "serve rz");
-    }
-    chk(hipMemcpyAsync(hflags.data(), ist_pool, hflags.size() * sizeof(int),
-                       hipMemcpyDeviceToHost, cs),
-        "read");
-    chk(hipStreamSynchronize(cs), "sync");
-    // 4. finished systems: true residual, x back to the caller, release
-    // (the batch tables point into every active slot: slots leave `active`
-    // only together with a rebuild of the batch)
-    bool any_done = false;
-    for (auto &sl : active) any_done |= hflags[4 * sl->id + 1] != 0;
-    if (!any_done) continue;
-    std::vector<std::unique_ptr<ServeSlot>> fin, keep;
-    for (auto &sl : active) {
-      if (hflags[4 * sl->id + 1]) fin.push_back(std::move(sl));
-      else keep.push_back(std::move(sl));
-    }
-    active = std::move(keep);
-    dirty = true;
-    {
-      std::vector<SlotView> v;
-      for (auto &sl : fin) v.push_back(slot_view(*sl, st_pool, ist_pool));
-      Batch fb;
-      build_batch(fb, v, prec, partial, cs);
-      chk(slots_true_res(fb.B, cs), "serve residual");
-    }
-    std::vector<double> hst(8 * (size_t)max_slots);
-    chk(hipMemcpyAsync(hst.data(), st_pool, hst.size() * sizeof(double), hipMemcpyDeviceToHost,
-                       cs),
-        "read");
-    chk(hipMemcpyAsync(hflags.data(), ist_pool, hflags.size() * sizeof(int),
-                       hipMemcpyDeviceToHost, cs),
-        "read");
-    for (auto &sl : fin)
-      if (sl->n > 0)
-        chk(hipMemcpyAsync(reqs[sl->req].x, sl->x, sl->n * sizeof(double), hipMemcpyDeviceToHost,
-                           cs),
-            "result copy");
-    chk(hipStreamSynchronize(cs), "sync");
-    for (auto &sl : fin) {
-      const int id = sl->id;
-      const double bn = sqrt(hst[8 * id]);
-      parac_result &r = out[sl->req];
-      r.iterations = hflags[4 * id];
-      r.true_relres = bn > 0 ? sqrt(hst[8 * id + 7]) / bn : 0.0;
-      int stat = hflags[4 * id + 1] == 1 ? PARAC_OK : PARAC_ENOCONV;
-      if (sl->f && read1(sl->f->serr, cs) != 0) stat = PARAC_ETIMEOUT;
-      retire(*sl, stat);
-    }
+    if (finished >= nreq) break;
+    // wait for a completion or the next arrival
+    double wait = 0.05;
+    if (next < nreq && inflight < nstreams)
+      wait = std::min(wait, std::max(0.0, reqs[order[next]].arrival_s - now()));
+    cv_done.wait_for(lk, std::chrono::duration<double>(wait));
   }
+  lk.unlock();
   return PARAC_OK;
 }
 
@@ -1780,8 +1918,10 @@ parac_status parac_apply(parac_factor_t f, const double *r, double *z, int64_t n
     } else {
       for (int64_t c0 = 0; c0 < nrhs; c0 += kBlockCols) {
         const int nc = (int)std::min<int64_t>(kBlockCols, nrhs - c0);
-        const parac_block_shape shp = block_shape(f, nc, precision);
-        apply_block(f, shp, nc, r + c0, nrhs, z + c0, nrhs, precision, nullptr, s);
+        bool applied = false;
+        const parac_block_shape shp =
+            block_shape(f, nc, precision, r + c0, nrhs, z + c0, nrhs, s, &applied);
+        if (!applied) apply_cols(f, nc, shp, r + c0, nrhs, z + c0, nrhs, precision, s);
       }
     }
     chk(hipStreamSynchronize(s), "sync");
@@ -1902,15 +2042,19 @@ parac_status parac_block_shape_set(parac_factor_t f, int32_t cols, int32_t preci
                                    const parac_block_shape *shape) {
   if (!f || cols < 2 || cols > kBlockCols ||
       (precision != PARAC_PREC_FP64 && precision != PARAC_PREC_MIXED) ||
-      (shape && !shape_ok(*shape))) {
+      (shape && !shape_ok(*shape, precision))) {
     g_last_error = "bad block shape arguments";
     return PARAC_EINVAL;
   }
   const auto key = std::make_pair((int)cols, prec_slot(precision));
-  if (shape)
-    f->shapes[key] = *shape;
-  else
+  if (shape) {
+    parac_block_shape sh = *shape;
+    sh.source = 0;
+    sh.ms = 0.f;
+    f->shapes[key] = sh;
+  } else {
     f->shapes.erase(key);
+  }
   return PARAC_OK;
 }
 
@@ -1922,7 +2066,7 @@ parac_status parac_block_shape_get(parac_factor_t f, int32_t cols, int32_t preci
   }
   auto it = f->shapes.find(std::make_pair((int)cols, prec_slot(precision)));
   if (it == f->shapes.end()) {
-    g_last_error = "no block shape fixed for these columns and precision";
+    g_last_error = "no block shape fixed, timed or cached yet for these columns and precision";
     return PARAC_EINVAL;
   }
   *shape = it->second;
@@ -1937,10 +2081,10 @@ parac_status parac_serve(const parac_request *reqs, int64_t n, const parac_serve
   }
   parac_serve_opts opt{};
   if (o) opt = *o;
-  if (opt.max_slots == 0) opt.max_slots = 32;
+  if (opt.max_slots == 0) opt.max_slots = 4;
   if (opt.maxit <= 0) opt.maxit = 10000;
   if (opt.check_every <= 0) opt.check_every = 4;
-  if (opt.max_slots < 1 || opt.max_slots > 256 ||
+  if (opt.max_slots < 1 || opt.max_slots > 64 ||
       (opt.precision != PARAC_PREC_FP64 && opt.precision != PARAC_PREC_MIXED)) {
     g_last_error = "bad serve options";
     return PARAC_EINVAL;
@@ -1955,9 +2099,92 @@ parac_status parac_serve(const parac_request *reqs, int64_t n, const parac_serve
   }
 }
 
+parac_status parac_order(const parac_csr *A, int32_t kind, uint64_t seed, int32_t *perm,
+                         int32_t *rounds, void *stream) {
+  if (!A || A->n < 0 || A->nnz < 0 || (A->n > 0 && (!A->rowptr || !A->col || !perm)) ||
+      (kind != PARAC_ORDER_RANDOM && kind != PARAC_ORDER_NNZ && kind != PARAC_ORDER_MIS)) {
+    g_last_error = "bad order arguments";
+    return PARAC_EINVAL;
+  }
+  if (A->n > INT32_MAX) {
+    g_last_error = "too many vertices for 32-bit labels";
+    return PARAC_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = A->n, nnz = A->nnz;
+    if (rounds) *rounds = 0;
+    if (n == 0) return PARAC_OK;
+    Scratch tmp;
+    const int64_t *rowptr = A->rowptr;
+    const int32_t *col = A->col;
+    int32_t *dperm = perm;
+    if (!A->on_device) {
+      int64_t *r = tmp.alloc<int64_t>(n + 1, "rowptr");
+      chk(hipMemcpyAsync(r, A->rowptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s), "copy");
+      rowptr = r;
+      if (kind == PARAC_ORDER_MIS) {
+        int32_t *c = tmp.alloc<int32_t>(nnz, "col");
+        chk(hipMemcpyAsync(c, A->col, nnz * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy");
+        col = c;
+      }
+      dperm = tmp.alloc<int32_t>(n, "perm");
+    }
+    uint64_t *key = tmp.alloc<uint64_t>(n, "keys");
+    uint64_t *key2 = tmp.alloc<uint64_t>(n, "keys");
+    int32_t *val = tmp.alloc<int32_t>(n, "values");
+    int32_t *val2 = tmp.alloc<int32_t>(n, "values");
+    const int64_t nh = 16 * order_tiles(n);
+    int32_t *hist = tmp.alloc<int32_t>(nh, "histograms");
+    int64_t *off = tmp.alloc<int64_t>(nh + 1, "offsets");
+    const size_t scan_bytes = scan_tmp_bytes(nh + 1);
+    void *scan_tmp = tmp.alloc<char>((int64_t)scan_bytes, "scan");
+    chk(launch_order_keys(n, rowptr, seed, kind, key, val, s), "order keys");
+    int bits = kind == PARAC_ORDER_RANDOM ? 64 : 44;
+    if (kind == PARAC_ORDER_MIS) {
+      int32_t *round = tmp.alloc<int32_t>(n, "rounds");
+      unsigned long long *placed = tmp.alloc<unsigned long long>(1, "placed");
+      chk(launch_fill_u32((uint32_t *)round, 0xffffffffu, n, s), "fill");
+      chk(launch_fill_u64((uint64_t *)placed, 0, 1, s), "fill");
+      unsigned long long done = 0;
+      int r = 0;
+      // at least the unplaced vertex of least (priority, index) joins each
+      // round, so the loop ends
+      while ((int64_t)done < n) {
+        if (r >= (1 << 20)) throw Err{PARAC_EINTERNAL, "too many rounds"};
+        chk(launch_mis_round(n, rowptr, col, key, round, r, placed, s), "mis round");
+        done = read1(placed, s);
+        ++r;
+      }
+      chk(launch_mis_key(n, round, key, s), "mis key");
+      bits = 64;
+      if (rounds) *rounds = r;
+    }
+    chk(radix_sort_pairs(n, bits, key, val, key2, val2, hist, off, scan_tmp, scan_bytes, s), "sort");
+    chk(launch_rank_to_perm(n, val, dperm, s), "perm");
+    if (!A->on_device)
+      chk(hipMemcpyAsync(perm, dperm, n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
+    chk(hipStreamSynchronize(s), "sync");
+    return PARAC_OK;
+  } catch (Err &e) {
+    return status_from(e);
+  }
+}
+
+int64_t parac_device_bytes(int32_t what) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  if (what == 0) return g_mem_live;
+  if (what == 1) return g_mem_peak;
+  if (what == 2) {
+    g_mem_peak = g_mem_live;
+    return g_mem_peak;
+  }
+  return -1;
+}
+
 void parac_factor_free(parac_factor_t f) {
   if (!f) return;
-  for (void *p : f->owned) (void)hipFree(p);
+  for (void *p : f->owned) dev_free(p);
   delete f;
 }
 

@@ -1,224 +1,11 @@
-// block.hip -- several right-hand sides at once: the preconditioner apply
-// and the PCG kernels on row-major blocks of nc <= 64 columns.
-//
-// A row is handled by a group of G = 2^gshift lanes; lane j of the group
-// holds the columns j, j + G, ... (CPL of them).  The factor entries of a row
-// are read once for all columns (every lane of a group reads the same
-// address), the vector entries of one row are contiguous.
-//
-// Every column of the apply is summed exactly like a single-vector apply
-// (chunks of 64 products, each a left fold, subtracted in order), so each
-// column of the block result is bit for bit the single apply of that column,
-// whatever G, CPL or the level at which the single-workgroup tail starts.  The PCG recurrences of
-// the columns are independent (their own alpha, beta and stopping test).
+// block.hip -- the PCG kernels of several right-hand sides at once, on
+// row-major blocks of nc <= 64 columns.  The preconditioner apply of a block
+// runs in the dependency-driven sweeps (ready.hip), a slot per chunk of
+// columns.
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace parac {
-
-// forward row at position pos: y(pos, :) = r(src pos, :) - sum_e F y(c_e, :)
-// (one lane group per row, columns across its lanes, chunks in sequence)
-template <typename T, int CPL>
-__device__ __forceinline__ void brow_fwd(const SolveArgs &a, int64_t pos, int j0, int G, int nc,
-                                         const double *__restrict__ r, int64_t ldr, T *y) {
-  const T *fv = FactorVals<T>::fwd(a);
-  const double *ri = r + (int64_t)a.src[pos] * ldr;
-  T acc[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int j = j0 + c * G;
-    acc[c] = j < nc ? (T)ri[j] : (T)0;
-  }
-  const int64_t e1 = a.lf_ptr[pos + 1];
-  for (int64_t ch = a.lf_ptr[pos]; ch < e1; ch += kChunk) {  // chunks of the row
-    const int64_t end = ch + kChunk < e1 ? ch + kChunk : e1;
-    T cs[CPL];
-    {
-      const T f = fv[ch];
-      const T *yc = y + (int64_t)a.lf_idx[ch] * nc;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int j = j0 + c * G;
-        cs[c] = j < nc ? f * yc[j] : (T)0;
-      }
-    }
-    for (int64_t e = ch + 1; e < end; ++e) {
-      const T f = fv[e];
-      const T *yc = y + (int64_t)a.lf_idx[e] * nc;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int j = j0 + c * G;
-        if (j < nc) cs[c] = cs[c] + f * yc[j];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) acc[c] = acc[c] - cs[c];
-  }
-  T *yi = y + pos * nc;
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int j = j0 + c * G;
-    if (j < nc) yi[j] = acc[c];
-  }
-}
-
-// backward row at position pos: x(pos, :) = D^+ y(pos, :) - sum_e F x(c_e, :);
-// z(src pos, :) = x(pos, :)
-template <typename T, int CPL>
-__device__ __forceinline__ void brow_bwd(const SolveArgs &a, int64_t pos, int j0, int G, int nc,
-                                         const T *__restrict__ y, T *x, double *z, int64_t ldz) {
-  const T *fv = FactorVals<T>::bwd(a);
-  const T di = FactorVals<T>::dinv(a)[pos];
-  const T *yi = y + pos * nc;
-  T acc[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int j = j0 + c * G;
-    acc[c] = j < nc ? di * yi[j] : (T)0;
-  }
-  const int64_t e1 = a.lb_ptr[pos + 1];
-  for (int64_t ch = a.lb_ptr[pos]; ch < e1; ch += kChunk) {  // chunks of the row
-    const int64_t end = ch + kChunk < e1 ? ch + kChunk : e1;
-    T cs[CPL];
-    {
-      const T f = fv[ch];
-      const T *xc = x + (int64_t)a.lb_idx[ch] * nc;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int j = j0 + c * G;
-        cs[c] = j < nc ? f * xc[j] : (T)0;
-      }
-    }
-    for (int64_t e = ch + 1; e < end; ++e) {
-      const T f = fv[e];
-      const T *xc = x + (int64_t)a.lb_idx[e] * nc;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int j = j0 + c * G;
-        if (j < nc) cs[c] = cs[c] + f * xc[j];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) acc[c] = acc[c] - cs[c];
-  }
-  T *xi = x + pos * nc;
-  double *zi = z + (int64_t)a.src[pos] * ldz;
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int j = j0 + c * G;
-    if (j < nc) {
-      xi[j] = acc[c];
-      zi[j] = (double)acc[c];
-    }
-  }
-}
-
-template <typename T, int CPL>
-__global__ __launch_bounds__(256) void k_blevel_fwd(SolveArgs a, int64_t p0, int64_t p1, int nc,
-                                                    int gshift, const double *__restrict__ r,
-                                                    int64_t ldr, T *y) {
-  if (a.skip && *a.skip) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t pos = p0 + (t >> gshift);
-  if (pos >= p1) return;
-  brow_fwd<T, CPL>(a, pos, (int)(t & ((1 << gshift) - 1)), 1 << gshift, nc, r, ldr, y);
-}
-
-template <typename T, int CPL>
-__global__ __launch_bounds__(256) void k_blevel_bwd(SolveArgs a, int64_t p0, int64_t p1, int nc,
-                                                    int gshift, const T *__restrict__ y, T *x,
-                                                    double *z, int64_t ldz) {
-  if (a.skip && *a.skip) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t pos = p0 + (t >> gshift);
-  if (pos >= p1) return;
-  brow_bwd<T, CPL>(a, pos, (int)(t & ((1 << gshift) - 1)), 1 << gshift, nc, y, x, z, ldz);
-}
-
-constexpr int kBTail = 1024;  // threads of the tail workgroup
-
-// levels [L0, depth) by one workgroup; rows of a level in passes of
-// kBTail / G, a workgroup barrier between levels
-template <typename T, int CPL>
-__global__ __launch_bounds__(kBTail) void k_btail_fwd(SolveArgs a, int64_t L0, int nc, int gshift,
-                                                      const double *__restrict__ r, int64_t ldr,
-                                                      T *y) {
-  if (a.skip && *a.skip) return;
-  const int G = 1 << gshift, j0 = threadIdx.x & (G - 1);
-  const int rows = kBTail >> gshift;
-  for (int64_t L = L0; L < a.depth; ++L) {
-    const int64_t p1 = a.lptr[L + 1];
-    for (int64_t pos = a.lptr[L] + (threadIdx.x >> gshift); pos < p1; pos += rows)
-      brow_fwd<T, CPL>(a, pos, j0, G, nc, r, ldr, y);
-    __syncthreads();
-  }
-}
-
-template <typename T, int CPL>
-__global__ __launch_bounds__(kBTail) void k_btail_bwd(SolveArgs a, int64_t L0, int nc, int gshift,
-                                                      const T *__restrict__ y, T *x, double *z,
-                                                      int64_t ldz) {
-  if (a.skip && *a.skip) return;
-  const int G = 1 << gshift, j0 = threadIdx.x & (G - 1);
-  const int rows = kBTail >> gshift;
-  for (int64_t L = a.depth - 1; L >= L0; --L) {
-    const int64_t p1 = a.lptr[L + 1];
-    for (int64_t pos = a.lptr[L] + (threadIdx.x >> gshift); pos < p1; pos += rows)
-      brow_bwd<T, CPL>(a, pos, j0, G, nc, y, x, z, ldz);
-    __syncthreads();
-  }
-}
-
-template <typename T, int CPL>
-static void bapply_t(const SolveArgs &a, const int64_t *hlptr, const BlockShape &sh, int nc,
-                     const double *r, int64_t ldr, T *y, T *x, double *z, int64_t ldz,
-                     hipStream_t s) {
-  int g = 0;
-  while ((1 << g) * CPL < nc) ++g;
-  const int64_t L0 = sh.L0 < a.depth ? sh.L0 : a.depth;
-  for (int64_t L = 0; L < L0; ++L) {
-    const int64_t p0 = hlptr[L], p1 = hlptr[L + 1];
-    const int64_t thr = (p1 - p0) << g;
-    if (thr > 0)
-      hipLaunchKernelGGL((k_blevel_fwd<T, CPL>), dim3((unsigned)((thr + 255) / 256)), dim3(256), 0,
-                         s, a, p0, p1, nc, g, r, ldr, y);
-  }
-  if (L0 < a.depth) {
-    hipLaunchKernelGGL((k_btail_fwd<T, CPL>), dim3(1), dim3(kBTail), 0, s, a, L0, nc, g, r, ldr,
-                       y);
-    hipLaunchKernelGGL((k_btail_bwd<T, CPL>), dim3(1), dim3(kBTail), 0, s, a, L0, nc, g,
-                       (const T *)y, x, z, ldz);
-  }
-  for (int64_t L = L0 - 1; L >= 0; --L) {
-    const int64_t p0 = hlptr[L], p1 = hlptr[L + 1];
-    const int64_t thr = (p1 - p0) << g;
-    if (thr > 0)
-      hipLaunchKernelGGL((k_blevel_bwd<T, CPL>), dim3((unsigned)((thr + 255) / 256)), dim3(256), 0,
-                         s, a, p0, p1, nc, g, (const T *)y, x, z, ldz);
-  }
-}
-
-template <typename T>
-static hipError_t bapply_cpl(const SolveArgs &a, const int64_t *hlptr, const BlockShape &sh,
-                             int nc, const double *r, int64_t ldr, T *y, T *x, double *z,
-                             int64_t ldz, hipStream_t s) {
-  switch (sh.cpl) {
-    case 1: bapply_t<T, 1>(a, hlptr, sh, nc, r, ldr, y, x, z, ldz, s); break;
-    case 2: bapply_t<T, 2>(a, hlptr, sh, nc, r, ldr, y, x, z, ldz, s); break;
-    case 4: bapply_t<T, 4>(a, hlptr, sh, nc, r, ldr, y, x, z, ldz, s); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_block_apply(const SolveArgs &a, const int64_t *hlptr, const BlockShape &sh,
-                              int nc, const double *r, int64_t ldr, void *y, void *x, double *z,
-                              int64_t ldz, int prec, hipStream_t s) {
-  if (nc < 1 || nc > kBlockCols) return hipErrorInvalidValue;
-  if (prec == PARAC_PREC_MIXED)
-    return bapply_cpl<float>(a, hlptr, sh, nc, r, ldr, (float *)y, (float *)x, z, ldz, s);
-  return bapply_cpl<double>(a, hlptr, sh, nc, r, ldr, (double *)y, (double *)x, z, ldz, s);
-}
 
 // ==========================================================================
 // Block PCG.  One lane per column (G = 2^gshift >= nc lanes per row), rows

@@ -455,6 +455,11 @@ constexpr int kCoarse = 512;    // coarse suffix-sum points per wave (LDS)
 // Rank sorts: an entry's rank is the number of entries before it in the
 // order (keys are distinct), counted with readlanes over 64-key blocks; the
 // blocks are loaded four at a time so that their latencies overlap.
+// rank of each entry in (key, w) order; with TIE (AC(k): one pivot may draw
+// the same pair twice, so keys repeat) equal keys are ordered by weight and
+// entries equal in both by position (they are interchangeable); without it
+// keys are unique
+template <bool TIE>
 __device__ __forceinline__ void rank_sort_key(const uint64_t *keyA, const double *wA,
                                               uint64_t *keyB, double *wB, int g) {
   const int l = lane();
@@ -462,19 +467,29 @@ __device__ __forceinline__ void rank_sort_key(const uint64_t *keyA, const double
     const int i = ib + l;
     const uint64_t ki = i < g ? keyA[i] : ~0ull;
     const double wi = i < g ? wA[i] : 0.0;
+    const uint64_t wbi = dbits(wi);
     int rank = 0;
     for (int jb = 0; jb < g; jb += 4 * kWave) {
-      uint64_t kj[4];
+      uint64_t kj[4], wj[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = jb + r * kWave + l;
         kj[r] = j < g ? keyA[j] : ~0ull;
+        wj[r] = TIE && j < g ? dbits(wA[j]) : 0ull;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int b0 = jb + r * kWave;
         const int lim = g - b0 < kWave ? g - b0 : kWave;
-        for (int jj = 0; jj < lim; ++jj) rank += readlane_u64(kj[r], jj) < ki ? 1 : 0;
+        for (int jj = 0; jj < lim; ++jj) {
+          const uint64_t kk = readlane_u64(kj[r], jj);
+          if (TIE) {
+            const uint64_t ww = readlane_u64(wj[r], jj);
+            rank += (kk < ki || (kk == ki && (ww < wbi || (ww == wbi && b0 + jj < i)))) ? 1 : 0;
+          } else {
+            rank += kk < ki ? 1 : 0;
+          }
+        }
       }
     }
     if (i < g) {
@@ -683,6 +698,9 @@ __device__ __forceinline__ bool sample_rounds(const ElimArgs &a, Worker &wk, int
     c[r] = 0.0;
     if (ins[r]) {
       const int32_t ua = su[sl], ub = su[lo[r]];
+      // AC(k): a partner on the same neighbour is a loop, dropped (never
+      // happens with one slot per neighbour: the labels are distinct)
+      ins[r] = ua != ub;
       c[r] = (Sp1[r] * sw[sl]) / Dk;
       tgt[r] = ua < ub ? ua : ub;
       oth[r] = ua < ub ? ub : ua;
@@ -699,7 +717,11 @@ template <class Sync>
 __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
                             int levk, uint64_t deadline, int *h, double *coarse) {
   const int l = lane();
-  const int64_t bytes = (((int64_t)g * 68) + 255) & ~(int64_t)255;
+  // AC(k): k sampling slots per merged neighbour (at most g neighbours):
+  // slot weights, labels and suffix sums after the per-pivot arrays
+  const int ks = a.samples > 1 ? a.samples : 1;
+  const int64_t slot_cap = ks > 1 ? (int64_t)g * ks : 0;
+  const int64_t bytes = (((int64_t)g * 68 + slot_cap * 20 + 8) + 255) & ~(int64_t)255;
   if (bytes > wk.sc_size) {
     // the worker's region is reused across pivots; grow it geometrically
     int64_t want = bytes > 2 * wk.sc_size ? bytes : 2 * wk.sc_size;
@@ -724,6 +746,10 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   int32_t *mu = (int32_t *)(S + g);
   int32_t *mm = mu + g;
   int32_t *su = mm + g;
+  // slot weights [slot_cap] (AC(k)), 8-byte aligned
+  double *xw2 = (double *)(((uintptr_t)(su + g) + 7) & ~(uintptr_t)7);
+  double *S2 = xw2 + slot_cap;         // their suffix sums
+  int32_t *xu2 = (int32_t *)(S2 + slot_cap);  // slot labels
   // 1. gather
 #pragma unroll 4
   for (int i = l; i < g; i += kWave) {
@@ -743,12 +769,26 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     wA[i] = w;
   }
   fence_wave_local();
-  // 2. sort by (u, src)
+  // 2. sort by (u, src) (AC(k): by (u, src, w), keys may repeat)
   uint64_t *keyS = keyB;   // sorted keys and weights end up here
   double *wS = wB;
   if (g <= kRankMax) {
-    rank_sort_key(keyA, wA, keyB, wB, g);
+    if (ks > 1) rank_sort_key<true>(keyA, wA, keyB, wB, g);
+    else rank_sort_key<false>(keyA, wA, keyB, wB, g);
   } else {
+    if (ks > 1) {
+      // least significant first: the weights (eight passes over the bits of
+      // a positive double, whose order is that of its value), then the keys
+      int wsh[8];
+      for (int p2 = 0; p2 < 8; ++p2) wsh[p2] = 8 * p2;
+      const bool w_in_a = wave_radix_sort<uint64_t, uint64_t>((uint64_t *)wA, keyA, (uint64_t *)wB,
+                                                              keyB, g, wsh, 8, h);
+      if (!w_in_a) {  // (an even pass count leaves them in place)
+        set_error(a.err, PARAC_EINTERNAL);
+        return false;
+      }
+      fence_wave_local();
+    }
     // radix passes over the bits a key can use: src + 1 in the low word,
     // u in the high word, both below 2^bits(ntot + 1)
     const int nb = 32 - __clz(a.ntot + 1);
@@ -799,22 +839,39 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     }
   }
   fence_wave_local();
+  // the sampling slots: the merged neighbours in (w, u) order, or (AC(k))
+  // each of them as ks consecutive slots of weight w / ks
+  const double *xw = sw;
+  const int32_t *xu = su;
+  double *SS = S;
+  int ds = d;
+  if (ks > 1) {
+    ds = d * ks;
+    for (int i = l; i < ds; i += kWave) {
+      xw2[i] = sw[i / ks] / (double)ks;
+      xu2[i] = su[i / ks];
+    }
+    fence_wave_local();
+    xw = xw2;
+    xu = xu2;
+    SS = S2;
+  }
   // suffix sums: 64-wide tiles, Hillis-Steele inside, carries right to left
   // (the next tile's values are loaded while the current one is summed);
   // the exact suffix maximum that makes S non-increasing is taken in the
   // same right-to-left pass (a maximum does not depend on its order)
-  const int ntile = (d + kWave - 1) / kWave;
+  const int ntile = (ds + kWave - 1) / kWave;
   double carry = 0.0, runmax = 0.0;
   double vnext = 0.0;
   {
     const int t0 = (ntile - 1) * kWave;
-    vnext = t0 + l < d ? sw[t0 + l] : 0.0;
+    vnext = t0 + l < ds ? xw[t0 + l] : 0.0;
   }
   for (int tt = ntile - 1; tt >= 0; --tt) {
     const int t0 = tt * kWave;
-    const int len = d - t0 < kWave ? d - t0 : kWave;
+    const int len = ds - t0 < kWave ? ds - t0 : kWave;
     double v = vnext;
-    if (tt > 0) vnext = sw[t0 - kWave + l];
+    if (tt > 0) vnext = xw[t0 - kWave + l];
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       double y = shfl_f64(v, l + o < kWave ? l + o : kWave - 1);
@@ -830,20 +887,20 @@ __device__ bool large_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     }
     if (runmax > v) v = runmax;
     runmax = shfl_f64(v, 0);
-    if (l < len) S[t0 + l] = v;
+    if (l < len) SS[t0 + l] = v;
   }
   fence_wave_local();
-  const double Dk = S[0];
+  const double Dk = SS[0];
   // 4. sampled edges
-  const int st = (d + kCoarse - 1) / kCoarse;
-  const int nco = (d + st - 1) / st;  // coarse points m_j = j st, j < nco
+  const int st = (ds + kCoarse - 1) / kCoarse;
+  const int nco = (ds + st - 1) / st;  // coarse points m_j = j st, j < nco
   for (int j = l; j < nco; j += kWave) {
     const int m = j * st;
-    coarse[j] = m + 1 < d ? S[m + 1] : 0.0;
+    coarse[j] = m + 1 < ds ? SS[m + 1] : 0.0;
   }
   fence_wave_local();
-  for (int ib = 0; ib < d - 1; ib += kSampleRounds * kWave)
-    if (!sample_rounds(a, wk, k, d, ib, kWave, S, sw, su, Dk, coarse, st, nco, deadline)) return false;
+  for (int ib = 0; ib < ds - 1; ib += kSampleRounds * kWave)
+    if (!sample_rounds(a, wk, k, ds, ib, kWave, SS, xw, xu, Dk, coarse, st, nco, deadline)) return false;
   // 5. column k of F
   int64_t fbase;
   if (!alloc_column(a, wk, d, fbase)) return false;
@@ -904,7 +961,9 @@ __device__ __forceinline__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, i
     return true;
   }
   const int levk = ld_acq_relaxed(&a.lev[k]);
-  if (z.g <= kWave) return small_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline);
+  // AC(k) pivots sample over k slots per neighbour: the scratch path
+  if (z.g <= kWave && a.samples <= 1)
+    return small_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline);
   return large_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline, h, coarse);
 }
 

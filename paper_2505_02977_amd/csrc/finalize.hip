@@ -256,7 +256,7 @@ __global__ __launch_bounds__(1024) void k_max_stats(int64_t ntot, const int64_t 
     g = gk > g ? gk : g;
     d = dk > d ? dk : d;
     L = Lk > L ? Lk : L;
-    f += dk > 0 ? dk - 1 : 0;
+    f += (unsigned long long)fill_cnt[k];  // fill records addressed to k
     z += colcnt[k] == 0 ? 1 : 0;
   }
   for (int o = 32; o >= 1; o >>= 1) {

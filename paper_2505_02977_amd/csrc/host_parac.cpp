@@ -570,6 +570,10 @@ parac_status parac_factor_host(const parac_csr *A, const parac_factor_opts *o, i
   parac_factor_opts opt{};
   opt.pool_factor = 4.0;
   if (o) opt = *o;
+  if (opt.samples > 1) {
+    g_host_error = "parac_factor_host builds the plain factor only (samples must be 0 or 1)";
+    return PARAC_EINVAL;
+  }
   if (threads <= 0) threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
   try {
     run_elimination(*A, opt, threads, out);

@@ -75,6 +75,7 @@ struct ElimArgs {
   int32_t *bq_head, *bq_tail;  // team claim, append
   int32_t bq_cap;
   int32_t team_min;    // pivots with more gathered entries go to teams (0: none)
+  int32_t samples;     // AC(k): sampling slots per merged neighbour (1: plain)
   int32_t team_wg0;    // workgroups from this index on are teams
 };
 
@@ -99,6 +100,21 @@ hipError_t launch_queue_init(int64_t ntot, const int32_t *dp, int32_t *q, int32_
 hipError_t scan_counts(const int32_t *cnt, int64_t *out, int64_t n, void *tmp, size_t tmp_bytes,
                        hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
+
+// --- order.hip (elimination orders on the device) ---
+int64_t order_tiles(int64_t n);
+hipError_t launch_order_keys(int64_t n, const int64_t *rowptr, uint64_t seed, int kind,
+                             uint64_t *key, int32_t *val, hipStream_t s);
+hipError_t launch_mis_round(int64_t n, const int64_t *rowptr, const int32_t *col,
+                            const uint64_t *pri, int32_t *round, int r,
+                            unsigned long long *placed, hipStream_t s);
+hipError_t launch_mis_key(int64_t n, const int32_t *round, uint64_t *key, hipStream_t s);
+// stable LSD radix sort of (key, val) by the low `bits` bits of key; hist
+// holds 16 * order_tiles(n) counts, off one more offset
+hipError_t radix_sort_pairs(int64_t n, int bits, uint64_t *key, int32_t *val, uint64_t *key2,
+                            int32_t *val2, int32_t *hist, int64_t *off, void *scan_tmp,
+                            size_t scan_bytes, hipStream_t s);
+hipError_t launch_rank_to_perm(int64_t n, const int32_t *val, int32_t *perm, hipStream_t s);
 
 // --- eliminate.hip ---
 hipError_t launch_eliminate(const ElimArgs &a, int wgs, hipStream_t s);
@@ -161,10 +177,11 @@ template <> struct FactorVals<float> {
   static __device__ __forceinline__ const float *bwd(const SolveArgs &a) { return a.lb_val32; }
   static __device__ __forceinline__ const float *dinv(const SolveArgs &a) { return a.Dinv32; }
 };
-// A row sum is taken in chunks of kChunk products.  Row classes by entries
-// (per direction): at most 16, 64, 256, 1024, more; a row of class c < 4 is
+// Rows are cut in chunks of kChunk entries.  Row classes by entries (per
+// direction): at most 16, 64, 256, 1024, more; a row of class c < 4 is
 // solved by a group of 4^c lanes (16 entries per lane), 64 / 4^c rows to a
-// wave; a longer row in blocks of kBlockChunks chunks and a fold.
+// wave; a longer row in blocks of kBlockChunks chunks (one partial sum per
+// block) and a fold that adds the partials.
 constexpr int kChunk = 64;
 constexpr int kRowClasses = 5;
 __host__ __device__ __forceinline__ int row_class(int64_t m) {
@@ -172,13 +189,16 @@ __host__ __device__ __forceinline__ int row_class(int64_t m) {
 }
 // units of a sweep (x = kind): group of 4^kind lanes per row (y = first
 // class-list index, z = rows), block (y = position, z = first chunk,
-// w = chunk-sum offset), fold (y = position, z = chunks, w = chunk-sum
+// w = partial-sum offset), fold (y = position, z = chunks, w = partial-sum
 // offset)
 constexpr int kUnitGroup1 = 0, kUnitGroup4 = 1, kUnitGroup16 = 2, kUnitGroup64 = 3;
 constexpr int kUnitBlock = 4, kUnitFold = 5;
 constexpr int kBlockChunks = 16;                // chunks of one block unit
 constexpr int kReadyThreads = 256;              // four independent waves
-constexpr int kReadyGroupsMax = 1024;           // workgroups of one system's sweep
+constexpr int kReadyGroupsMax = 1024;           // workgroups of one system's sweep, at most
+// by default: as fast as more on the 3D grid and Chung-Lu benchmarks, and a
+// quarter of the waves the device holds, so other systems' kernels still fit
+constexpr int kReadyGroupsDefault = 256;
 // a work-vector entry whose row is not solved yet (signalling NaNs)
 constexpr unsigned long long kPending64 = 0x7FF4DEADBEEF0001ull;
 constexpr unsigned int kPending32 = 0x7FA0BEEFu;
@@ -212,11 +232,6 @@ hipError_t launch_level_copy(int64_t n, const int32_t *order, const int32_t *pos
                              const double *val, const int64_t *lf_ptr, const int64_t *lb_ptr,
                              int32_t *lf_idx, double *lf_val, int32_t *lb_idx, double *lb_val,
                              hipStream_t s);
-// block apply: levels from the first one after which every level has at
-// most tail_rows rows and kTailEntries entries per direction go to the
-// single-workgroup tail (kTailDefault: the default threshold)
-constexpr int kTailDefault = 256;
-constexpr int kTailEntries = 16384;
 hipError_t launch_comp_init(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
                             int32_t *parent, hipStream_t s);
 hipError_t launch_comp_jump(int64_t ntot, const int32_t *src, int32_t *dst, int *changed,
@@ -225,14 +240,7 @@ hipError_t launch_comp_check(int64_t n, int64_t ground, const int32_t *perm, con
                              const double *b, double *sum, double *sabs, int *bad, hipStream_t s);
 
 // --- block.hip (several right-hand sides, row-major blocks of nc columns) ---
-constexpr int kBlockCols = 64;  // columns per block launch
-struct BlockShape {
-  int cpl;     // columns per lane: 1, 2 or 4
-  int64_t L0;  // first level solved by the single-workgroup tail
-};
-hipError_t launch_block_apply(const SolveArgs &a, const int64_t *hlptr, const BlockShape &sh,
-                              int nc, const double *r, int64_t ldr, void *y, void *x, double *z,
-                              int64_t ldz, int prec, hipStream_t s);
+constexpr int kBlockCols = 64;  // columns per block PCG launch sequence
 int bpcg_partials();
 hipError_t bpcg_launch_init(int64_t n, int nc, double rtol, const double *b, int64_t ldb,
                             double *x, int64_t ldx, double *r, double *p, double *partial,
@@ -268,9 +276,12 @@ struct ApplySlot {
   int64_t ldr, ldz;  // element strides of r and z (1, or the columns of a block)
   const double *r;
   void *y, *x;  // position-space work vectors (precision of the apply), all pending
-  void *cs;     // chunk sums of long rows (precision of the apply), all pending
+  void *cs;     // block partial sums of long rows (precision of the apply), all pending
   int32_t *ctr;  // ticket counters of the forward and backward sweeps
   double *z;
+  int32_t ncols;  // valid columns of the slot (at most the launch's columns per slot)
+  // the slot is skipped when all of a.skip[j * skip_stride], j < skip_n, are set
+  int32_t skip_n, skip_stride;
 };
 struct SlotBatch {
   int nslots = 0, nblocks = 0;
@@ -281,6 +292,7 @@ struct SlotBatch {
   // sweeps: one launch per direction; workgroup b serves slot wgmap[b]
   const int32_t *wgmap = nullptr;  // device [nwg]
   int nwg = 0;
+  int cc = 1;  // columns per sweep slot (1, 2, 4; 8 with the FP32 apply)
 };
 int slot_blocks(int64_t n);
 hipError_t slots_init(const SlotBatch &B, hipStream_t s);
@@ -291,6 +303,8 @@ hipError_t slots_true_res(const SlotBatch &B, hipStream_t s);
 hipError_t slots_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid = nullptr);
 // --- ready.hip ---
 hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid = nullptr);
+// columns per sweep slot the apply supports in a precision
+bool ready_cols_ok(int prec, int cc);
 
 }  // namespace parac
 
@@ -331,10 +345,8 @@ struct parac_factor_s {
   void *cy[2] = {nullptr, nullptr}, *cx[2] = {nullptr, nullptr}, *ccs[2] = {nullptr, nullptr};
   int32_t *cctr[2] = {nullptr, nullptr};
   int64_t ccols[2] = {0, 0};
-  // block work vectors (ntot x bcols) per precision, launch shape per
-  // (columns, precision): set by the caller (else column sweeps)
-  void *bwy[2] = {nullptr, nullptr}, *bwx[2] = {nullptr, nullptr};
-  int64_t bcols[2] = {0, 0};
+  // launch shape of the block apply per (columns, precision): fixed by the
+  // caller, or timed on first use (else taken from the shape cache)
   std::map<std::pair<int, int>, parac_block_shape> shapes;
   std::vector<void *> owned;
   int64_t bytes = 0;  // device bytes held by the factor's own arrays

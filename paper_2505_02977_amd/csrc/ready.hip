@@ -15,11 +15,16 @@
 // Every wait is bounded by a wall-clock watchdog that records an error
 // instead of hanging.
 //
-// The arithmetic of a row is that of the level-synchronous form: the sum is
-// taken in chunks of 64 consecutive products (ascending column), each chunk
-// a left fold from its first product, and the row value is the start value
-// minus the chunk sums in chunk order.  Which wave computes which chunk
-// changes nothing in the bits.
+// The arithmetic of a row: start value minus the sum of its products, the
+// sum taken as a balanced binary tree whose shape depends only on the row's
+// length.  Each lane adds its (up to) 16 products pairwise (4 levels, absent
+// entries contributing -0.0, the exact identity of addition), the G lanes of
+// a row combine their partial sums by a butterfly over lane-index bits
+// (commutative pairs, so every lane ends with the same bits), and rows above
+// 1024 entries add their block partials (1024 entries each) as a tree too.
+// A row's dependent chain is about log2(entries) additions, where a left fold
+// would take one per entry.  Which wave computes which part changes nothing
+// in the bits.
 //
 // Units (int4, kind in x).  A row of m entries is taken by a group of G
 // lanes (G = 1 for m <= 16, 4 for m <= 64, 16 for m <= 256, 64 for
@@ -28,15 +33,24 @@
 // products spans four lanes and is folded along them through shuffles.
 //   group G  : 64/G rows of one class of one level (y = first class-list
 //              index, z = number of rows)
-//   block    : chunks [z, z + 16) of a row of more than 1024 entries, by the
-//              64 lanes as one group (y = position, w = offset of the row's
-//              chunk sums in the chunk-sum buffer)
-//   fold     : the chunk sums of such a row folded into its value
-//              (y = position, z = number of chunks, w = offset)
+//   block    : chunks [z, z + 16) of 64 entries of a row of more than 1024
+//              entries, by the 64 lanes as one group: one block partial,
+//              stored at w + z / 16 of the partial buffer (y = position,
+//              w = offset of the row's partials)
+//   fold     : the block partials of such a row added into its value
+//              (y = position, z = number of 64-entry chunks, w = offset)
 // Work vectors y (forward) and x (backward) are indexed by position.  Each
 // sweep leaves the other vector all-sentinel for the next apply: the forward
 // sweep resets x, the backward sweep resets y once it has read it, and a
 // fold resets the chunk sums it consumed.
+//
+// Columns.  A slot solves CC right-hand sides at once (CC = 1, 2, 4 or 8,
+// fixed per launch): entry (p, j) of its work vectors and chunk sums is at
+// p * CC + j, so the CC values of one position share a line.  Every lane
+// reads its entries' indices and factor values once and folds CC
+// independent chains, one per column, each with exactly the association of
+// the single-column sweep: a column's bits do not depend on CC.  Columns of
+// a slot beyond its valid count carry zeros and are never written out.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -83,8 +97,8 @@ __device__ __forceinline__ void reset(T *p) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double shfl_t(double v, int l) { return shfl_f64(v, l); }
-__device__ __forceinline__ float shfl_t(float v, int l) { return __shfl(v, l, kWave); }
+__device__ __forceinline__ double shfl_xor_t(double v, int o) { return __shfl_xor(v, o, kWave); }
+__device__ __forceinline__ float shfl_xor_t(float v, int o) { return __shfl_xor(v, o, kWave); }
 
 __device__ __forceinline__ double readlane_t(double v, int l) {
   const long long b = __double_as_longlong(v);
@@ -95,27 +109,6 @@ __device__ __forceinline__ double readlane_t(double v, int l) {
 __device__ __forceinline__ float readlane_t(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
-
-// DPP lane moves within rows of 16 lanes: row_shr:1 (lane l gets lane l-1;
-// the first lane of a row keeps 0) and quad_perm [3,3,3,3] (every lane gets
-// lane 3 of its group of four)
-template <int CTRL>
-__device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_t(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_i32<CTRL>((int)(unsigned)(b & 0xffffffffll));
-  const int hi = dpp_i32<CTRL>((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_t(float v) {
-  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
-}
-constexpr int kDppRowShr1 = 0x111;
-constexpr int kDppQuad3 = 0xFF;
 
 // short back-off between polls of one address: 64, 128, 256 cycles
 struct PollBackoff {
@@ -145,29 +138,34 @@ struct Watch {
   }
 };
 
-// Wait until every lane's entries v[u], u < cnt, are solved.  The
-// wave polls one address at a time: of its pending entries the one solved
-// last in sweep order (positions follow the levels: the highest position
+// Wait until every lane's entries v[u][j], u < cnt, are solved.  The wave
+// polls one address at a time: of its pending entries the one solved last
+// in sweep order (positions follow the levels: the highest position
 // forward, DESC: the lowest backward), then reloads the others, which are
 // usually solved by then.  A single polled address per wave leaves the
 // memory system to the loads and stores of the rows being solved.
-template <typename T, int M, bool DESC>
-__device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
-                                           int cnt, typename Bits<T>::U (&v)[M],
-                                           Watch &w) {
+template <typename T, int M, int CC, bool DESC>
+__device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M], int cnt,
+                                           typename Bits<T>::U (&v)[M][CC], Watch &w) {
   using B = Bits<T>;
   auto reload = [&]() {
 #pragma unroll
     for (int u = 0; u < M; ++u)
-      if (u < cnt && v[u] == B::kPending) v[u] = load_bits(vec + ci[u]);
+#pragma unroll
+      for (int j = 0; j < CC; ++j)
+        if (u < cnt && v[u][j] == B::kPending) v[u][j] = load_bits(vec + ci[u] * CC + j);
   };
   for (;;) {
+    // key: the element index p * CC + j of a pending entry (negated: DESC)
     int key = INT32_MIN;
 #pragma unroll
-    for (int u = 0; u < M; ++u) {
-      const int k = DESC ? -ci[u] : ci[u];
-      if (u < cnt && v[u] == B::kPending && k > key) key = k;
-    }
+    for (int u = 0; u < M; ++u)
+#pragma unroll
+      for (int j = 0; j < CC; ++j) {
+        const int e = ci[u] * CC + j;
+        const int k = DESC ? -e : e;
+        if (u < cnt && v[u][j] == B::kPending && k > key) key = k;
+      }
     if (!__ballot(key != INT32_MIN)) return;
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) {
@@ -180,7 +178,9 @@ __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
       if (__ballot(w.expired())) {
 #pragma unroll
         for (int u = 0; u < M; ++u)
-          if (v[u] == B::kPending) v[u] = B::kQuietNaN;
+#pragma unroll
+          for (int j = 0; j < CC; ++j)
+            if (v[u][j] == B::kPending) v[u][j] = B::kQuietNaN;
         return;
       }
       bo.pause();
@@ -189,16 +189,61 @@ __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
   }
 }
 
+// balanced sum of a lane's 16 products (pairs, then pairs of pairs, ...)
+template <typename T>
+__device__ __forceinline__ T tree16(const T (&p)[16]) {
+  T a[8], c[4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = p[2 * i] + p[2 * i + 1];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) c[i] = a[2 * i] + a[2 * i + 1];
+  return (c[0] + c[1]) + (c[2] + c[3]);
+}
+
+// DPP lane moves inside rows of 16 lanes: quad_perm [1,0,3,2] (lane ^ 1),
+// quad_perm [2,3,0,1] (lane ^ 2), row_half_mirror (lane i <-> 7 - i within
+// 8) and row_mirror (i <-> 15 - i within 16)
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL>((int)(unsigned)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+
+// sum over the G lanes of a row group (G a power of two, groups aligned to
+// G lanes): a butterfly that pairs lanes 1, 2, 4, 8, 16, 32 apart (the
+// partners at 4 and 8 by mirroring, which pairs the same two partial sums);
+// the two lanes of a pair add the same two values, so every lane of the
+// group ends with the same bits
+template <typename T, int G>
+__device__ __forceinline__ T group_reduce(T v) {
+  if constexpr (G >= 2) v = v + dpp_t<kDppXor1>(v);
+  if constexpr (G >= 4) v = v + dpp_t<kDppXor2>(v);
+  if constexpr (G >= 8) v = v + dpp_t<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v = v + dpp_t<kDppMirror>(v);
+  if constexpr (G >= 32) v = v + shfl_xor_t(v, 16);
+  if constexpr (G >= 64) v = v + shfl_xor_t(v, 32);
+  return v;
+}
+
 // Lane q of a group reads the entries [b + 16q, b + 16q + 16) ∩ [b, e1)
-// (b: the first entry of the group's share of the row); returns the sum of
-// the chunk the lane belongs to (64 products, four lanes) in the chunk's
-// fourth lane, and in every lane when G == 1 (one lane, at most 16
-// products).  Chunks are left folds from their first product: the first
-// lane of a chunk starts the fold, the next three continue it in turn.
-template <typename T, int G, bool DESC>
-__device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool valid,
+// (b: the first entry of the group's share of the row) and sets c[j] to the
+// group's sum of column j over those entries, in every lane of the group.
+template <typename T, int G, bool DESC, int CC>
+__device__ __forceinline__ void group_sum(int64_t b, int64_t e1, int q, bool valid,
                                           const int32_t *__restrict__ idx,
-                                          const T *__restrict__ fv, const T *vec, Watch &w) {
+                                          const T *__restrict__ fv, const T *vec, Watch &w,
+                                          T (&c)[CC]) {
   using B = Bits<T>;
   const int64_t a = b + 16 * (int64_t)q;
   int32_t ci[16];
@@ -206,120 +251,108 @@ __device__ __forceinline__ T group_chunks(int64_t b, int64_t e1, int q, bool val
   // the lane's entries are a prefix of its 16 slots
   const int64_t left = valid ? e1 - a : 0;
   const int cnt = left <= 0 ? 0 : (left < 16 ? (int)left : 16);
-  typename B::U v[16];
+  typename B::U v[16][CC];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     ci[u] = u < cnt ? idx[a + u] : 0;
     f[u] = u < cnt ? fv[a + u] : (T)0;
   }
 #pragma unroll
-  for (int u = 0; u < 16; ++u) v[u] = u < cnt ? load_bits(vec + ci[u]) : (typename B::U)0;
-  wait_ready<T, 16, DESC>(vec, ci, cnt, v, w);
-  // the lane's own products, folded from its first.  An absent entry
-  // contributes -0.0, which leaves every sum unchanged (x + (-0.0) = x
-  // exactly, for every x), so the fold is a plain chain of additions; a lane
-  // without entries passes the running sum on.
-  T p[16];
+  for (int u = 0; u < 16; ++u)
 #pragma unroll
-  for (int u = 0; u < 16; ++u) p[u] = u < cnt ? f[u] * B::val(v[u]) : (T)-0.0;
-  auto fold = [&](T t, bool first) {
-    t = first ? p[0] : t + p[0];
+    for (int j = 0; j < CC; ++j)
+      v[u][j] = u < cnt ? load_bits(vec + ci[u] * CC + j) : (typename B::U)0;
+  wait_ready<T, 16, CC, DESC>(vec, ci, cnt, v, w);
 #pragma unroll
-    for (int u = 1; u < 16; ++u) t = t + p[u];
-    return t;
-  };
-  if constexpr (G == 1) {
-    return fold((T)0, true);
-  } else {
-    // the four lanes of a chunk lie in one DPP row: lane l takes the running
-    // sum of lane l-1
-    const int st = q & 3;
-    T s = (T)0;
+  for (int j = 0; j < CC; ++j) {
+    T p[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const T prev = dpp_t<kDppRowShr1>(s);
-      if (st == k) s = k == 0 ? fold((T)0, true) : fold(prev, false);
-    }
-    return s;
+    for (int u = 0; u < 16; ++u) p[u] = u < cnt ? f[u] * B::val(v[u][j]) : (T)-0.0;
+    c[j] = group_reduce<T, G>(tree16(p));
   }
 }
 
-template <typename T, bool BWD>
+template <typename T, bool BWD, int CC>
 struct Sweep {
-  const ApplySlot &q;  // the system's slot
+  const ApplySlot &q;  // the slot
   const int64_t *ptr;
   const int32_t *idx;
   const T *fv;
   T *in;   // vector read (y forward, x backward)
   T *out;  // vector written: the same vector
+  int nc;  // valid columns of the slot (the others carry zeros)
   __device__ __forceinline__ Sweep(const ApplySlot &q_) : q(q_) {
     ptr = BWD ? q.a.lb_ptr : q.a.lf_ptr;
     idx = BWD ? q.a.lb_idx : q.a.lf_idx;
     fv = BWD ? FactorVals<T>::bwd(q.a) : FactorVals<T>::fwd(q.a);
     in = (T *)(BWD ? q.x : q.y);
     out = in;
+    nc = q.ncols;
   }
-  // start value of a row: (P r) forward, D^+ y backward
-  __device__ __forceinline__ T start(int64_t pos) const {
+  // start values of a row: (P r) forward, D^+ y backward
+  __device__ __forceinline__ void start(int64_t pos, T (&s)[CC]) const {
     if constexpr (BWD) {
-      return FactorVals<T>::dinv(q.a)[pos] * ((const T *)q.y)[pos];
+      const T d = FactorVals<T>::dinv(q.a)[pos];
+#pragma unroll
+      for (int j = 0; j < CC; ++j) s[j] = d * ((const T *)q.y)[pos * CC + j];
     } else {
-      return (T)q.r[(int64_t)q.a.src[pos] * q.ldr];
+      const double *r = q.r + (int64_t)q.a.src[pos] * q.ldr;
+#pragma unroll
+      for (int j = 0; j < CC; ++j) s[j] = j < nc ? (T)r[j] : (T)0;
     }
   }
   // publish row pos; forward resets x[pos], backward resets y[pos] and
   // writes z in the original ordering
-  __device__ __forceinline__ void finish(int64_t pos, T v) const {
-    publish(out + pos, v);
+  __device__ __forceinline__ void finish(int64_t pos, const T (&v)[CC]) const {
+#pragma unroll
+    for (int j = 0; j < CC; ++j) publish(out + pos * CC + j, v[j]);
     if constexpr (BWD) {
-      reset((T *)q.y + pos);
-      q.z[(int64_t)q.a.src[pos] * q.ldz] = (double)v;
+      double *z = q.z + (int64_t)q.a.src[pos] * q.ldz;
+#pragma unroll
+      for (int j = 0; j < CC; ++j) {
+        reset((T *)q.y + pos * CC + j);
+        if (j < nc) z[j] = (double)v[j];
+      }
     } else {
-      reset((T *)q.x + pos);
+#pragma unroll
+      for (int j = 0; j < CC; ++j) reset((T *)q.x + pos * CC + j);
     }
   }
 };
 
-// a group unit: 64/G rows, G lanes each
-template <typename T, bool BWD, int G>
-__device__ __forceinline__ void group_unit(const Sweep<T, BWD> &S, const int4 &u, Watch &w) {
+// a group unit: 64/G rows, G lanes each; the group's first lane publishes
+// each row: start value minus the row's sum
+template <typename T, bool BWD, int G, int CC>
+__device__ __forceinline__ void group_unit(const Sweep<T, BWD, CC> &S, const int4 &u, Watch &w) {
   const int l = lane(), r = l / G, q = l % G;
   const bool valid = r < u.z;
   const int64_t pos = valid ? (BWD ? S.q.a.blist : S.q.a.flist)[u.y + r] : 0;
   const int64_t e0 = valid ? S.ptr[pos] : 0, e1 = valid ? S.ptr[pos + 1] : 0;
-  T acc = valid && q == 0 ? S.start(pos) : (T)0;  // issued before the wait
-  const T c = group_chunks<T, G, BWD>(e0, e1, q, valid, S.idx, S.fv, S.in, w);
-  // the row value: start minus its chunk sums in chunk order (each in the
-  // fourth lane of its chunk); the group's first lane publishes it
-  if constexpr (G == 1) {
-    if (e1 > e0) acc = acc - c;
-  } else if constexpr (G == 4) {
-    const T c0 = dpp_t<kDppQuad3>(c);
-    if (e1 > e0) acc = acc - c0;
-  } else if constexpr (G == 16) {
-    const int base = r * G;
+  T acc[CC];
+  if (valid && q == 0) S.start(pos, acc);  // issued before the wait
+  else
 #pragma unroll
-    for (int k = 0; k < G / 4; ++k) {
-      const T ck = shfl_t(c, base + 4 * k + 3);
-      if (e0 + kChunk * (int64_t)k < e1) acc = acc - ck;
-    }
-  } else {
+    for (int j = 0; j < CC; ++j) acc[j] = (T)0;
+  T c[CC];
+  group_sum<T, G, BWD, CC>(e0, e1, q, valid, S.idx, S.fv, S.in, w, c);
+  if (valid && q == 0) {
+    if (e1 > e0)
 #pragma unroll
-    for (int k = 0; k < G / 4; ++k) {
-      const T ck = readlane_t(c, 4 * k + 3);
-      if (e0 + kChunk * (int64_t)k < e1) acc = acc - ck;
-    }
+      for (int j = 0; j < CC; ++j) acc[j] = acc[j] - c[j];
+    S.finish(pos, acc);
   }
-  if (valid && q == 0) S.finish(pos, acc);
 }
 
-template <typename T, bool BWD>
+template <typename T, bool BWD, int CC>
 __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
                                                          const int32_t *wgmap) {
   const ApplySlot q = AS[wgmap[blockIdx.x]];
-  if (*q.a.skip) return;
+  // a slot whose columns are all done (block PCG) has nothing to solve
+  bool skip = true;
+  for (int j = 0; j < q.skip_n; ++j) skip = skip && q.a.skip[(int64_t)j * q.skip_stride] != 0;
+  if (skip) return;
   const int l = lane();
-  const Sweep<T, BWD> S(q);
+  const Sweep<T, BWD, CC> S(q);
   const int4 *units = BWD ? q.a.task_b : q.a.task_f;
   const int nt = BWD ? q.a.ntask_b : q.a.ntask_f;
   int32_t *ctr = q.ctr + (BWD ? 1 : 0);
@@ -336,57 +369,88 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
     const int4 u = units[t];
     const int kind = first_lane_i32(u.x);
     if (kind == kUnitGroup1) {
-      group_unit<T, BWD, 1>(S, u, w);
+      group_unit<T, BWD, 1, CC>(S, u, w);
     } else if (kind == kUnitGroup4) {
-      group_unit<T, BWD, 4>(S, u, w);
+      group_unit<T, BWD, 4, CC>(S, u, w);
     } else if (kind == kUnitGroup16) {
-      group_unit<T, BWD, 16>(S, u, w);
+      group_unit<T, BWD, 16, CC>(S, u, w);
     } else if (kind == kUnitGroup64) {
-      group_unit<T, BWD, 64>(S, u, w);
+      group_unit<T, BWD, 64, CC>(S, u, w);
     } else if (kind == kUnitBlock) {
-      // chunks [c0, c0 + 16) of a long row: the 64 lanes as one group
+      // entries [64 c0, 64 c0 + 1024) of a long row: the 64 lanes as one
+      // group; the block's partial goes to slot w + c0 / 16
       const int64_t pos = first_lane_i32(u.y);
       const int64_t e0 = S.ptr[pos], e1 = S.ptr[pos + 1];
       const int64_t c0 = u.z;
-      const T c = group_chunks<T, 64, BWD>(e0 + kChunk * c0, e1, l, true, S.idx, S.fv, S.in, w);
-      const int64_t ck = c0 + l / 4;
-      if ((l & 3) == 3 && e0 + kChunk * ck < e1) publish(cs + u.w + ck, c);
+      T c[CC];
+      group_sum<T, 64, BWD, CC>(e0 + kChunk * c0, e1, l, true, S.idx, S.fv, S.in, w, c);
+      if (l == 0)
+#pragma unroll
+        for (int j = 0; j < CC; ++j) publish(cs + (u.w + c0 / kBlockChunks) * CC + j, c[j]);
     } else {  // fold
       const int64_t pos = first_lane_i32(u.y);
-      const int nch = u.z;
-      T acc = S.start(pos);
-      for (int base = 0; base < nch; base += kWave) {
-        const int m = nch - base < kWave ? nch - base : kWave;
+      const int nb = (u.z + kBlockChunks - 1) / kBlockChunks;  // block partials
+      T acc[CC], tot[CC];
+      S.start(pos, acc);
+      // partials 64 at a time, one per lane, each batch added as a tree
+      // (butterfly over all 64 lanes), batches added in order
+      for (int base = 0; base < nb; base += kWave) {
+        const int m = nb - base < kWave ? nb - base : kWave;
         int32_t ci[1] = {u.w + base + l};
         const int cnt = l < m ? 1 : 0;
-        typename Bits<T>::U v[1] = {cnt ? load_bits(cs + ci[0]) : (typename Bits<T>::U)0};
-        wait_ready<T, 1, false>(cs, ci, cnt, v, w);
-        if (cnt) reset(cs + ci[0]);
-        const T c = Bits<T>::val(v[0]);
-        for (int k = 0; k < m; ++k) acc = acc - readlane_t(c, k);
+        typename Bits<T>::U v[1][CC];
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+          v[0][j] = cnt ? load_bits(cs + ci[0] * CC + j) : (typename Bits<T>::U)0;
+        wait_ready<T, 1, CC, false>(cs, ci, cnt, v, w);
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+          if (cnt) reset(cs + ci[0] * CC + j);
+          const T s = group_reduce<T, kWave>(cnt ? Bits<T>::val(v[0][j]) : (T)-0.0);
+          tot[j] = base == 0 ? s : tot[j] + s;
+        }
       }
-      if (l == 0) S.finish(pos, acc);
+      if (l == 0) {
+#pragma unroll
+        for (int j = 0; j < CC; ++j) acc[j] = acc[j] - tot[j];
+        S.finish(pos, acc);
+      }
     }
   }
 }
 
-template <typename T>
+template <typename T, int CC>
 void ready_apply_t(const SlotBatch &B, hipStream_t s, hipEvent_t mid) {
-  hipLaunchKernelGGL((k_ready<T, false>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
+  hipLaunchKernelGGL((k_ready<T, false, CC>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
                      B.wgmap);
   if (mid) (void)hipEventRecord(mid, s);
-  hipLaunchKernelGGL((k_ready<T, true>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
+  hipLaunchKernelGGL((k_ready<T, true, CC>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
                      B.wgmap);
 }
 
 }  // namespace
 
+bool ready_cols_ok(int prec, int cc) {
+  return cc == 1 || cc == 2 || cc == 4 || (prec == PARAC_PREC_MIXED && cc == 8);
+}
+
 hipError_t ready_apply(const SlotBatch &B, int prec, hipStream_t s, hipEvent_t mid) {
   if (B.nwg == 0) return mid ? hipEventRecord(mid, s) : hipSuccess;
-  if (prec == PARAC_PREC_MIXED)
-    ready_apply_t<float>(B, s, mid);
-  else
-    ready_apply_t<double>(B, s, mid);
+  if (!ready_cols_ok(prec, B.cc)) return hipErrorInvalidValue;
+  if (prec == PARAC_PREC_MIXED) {
+    switch (B.cc) {
+      case 1: ready_apply_t<float, 1>(B, s, mid); break;
+      case 2: ready_apply_t<float, 2>(B, s, mid); break;
+      case 4: ready_apply_t<float, 4>(B, s, mid); break;
+      default: ready_apply_t<float, 8>(B, s, mid); break;
+    }
+  } else {
+    switch (B.cc) {
+      case 1: ready_apply_t<double, 1>(B, s, mid); break;
+      case 2: ready_apply_t<double, 2>(B, s, mid); break;
+      default: ready_apply_t<double, 4>(B, s, mid); break;
+    }
+  }
   return hipGetLastError();
 }
 

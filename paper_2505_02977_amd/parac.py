@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libparac.so")
 OK, EINVAL, ENOTLAP, EPOOL, ENOMEM, ETIMEOUT, EDEVICE, EINCONSISTENT, ENOCONV, EINTERNAL = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 MODE_AUTO, MODE_LAPLACIAN, MODE_SDDM = 0, 1, 2
+ORDER_RANDOM, ORDER_NNZ, ORDER_MIS = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -35,7 +36,7 @@ class parac_csr(C.Structure):
 class parac_factor_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("perm", C.c_void_p), ("mode", C.c_int32),
                 ("pool_factor", C.c_double), ("workers", C.c_int32), ("keep_fp32", C.c_int32),
-                ("timeout_s", C.c_double), ("tail_fraction", C.c_double)]
+                ("timeout_s", C.c_double), ("tail_fraction", C.c_double), ("samples", C.c_int32)]
 
 
 class parac_factor_stats(C.Structure):
@@ -60,7 +61,8 @@ class parac_pcg_stats(C.Structure):
 
 
 class parac_block_shape(C.Structure):
-    _fields_ = [("cpl", C.c_int32), ("tail_rows", C.c_int64)]
+    _fields_ = [("cols_per_sweep", C.c_int32), ("workgroups", C.c_int32), ("source", C.c_int32),
+                ("ms", C.c_float)]
 
 
 class parac_request(C.Structure):
@@ -108,6 +110,11 @@ def lib():
                                 C.POINTER(parac_pcg_opts), C.POINTER(parac_pcg_stats), P]
         L.parac_pcg_static.argtypes = [C.POINTER(parac_csr), P, P, P, C.POINTER(parac_pcg_opts),
                                        C.POINTER(parac_pcg_stats), P]
+        L.parac_order.argtypes = [C.POINTER(parac_csr), C.c_int32, C.c_uint64, P,
+                                  C.POINTER(C.c_int32), P]
+        L.parac_order.restype = C.c_int
+        L.parac_device_bytes.argtypes = [C.c_int32]
+        L.parac_device_bytes.restype = C.c_int64
         L.parac_pcg_static_max_rows.argtypes = []
         L.parac_pcg_static_max_rows.restype = C.c_int64
         L.parac_serve.argtypes = [C.POINTER(parac_request), C.c_int64,
@@ -188,14 +195,16 @@ class Factor:
 
 
 def parac_factor(A: DeviceCSR, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, workers=0,
-                 keep_fp32=False, timeout_s=30.0, tail_fraction=0.0, stream=None) -> Factor:
+                 keep_fp32=False, timeout_s=30.0, tail_fraction=0.0, samples=1,
+                 stream=None) -> Factor:
+    """samples = k > 1 builds the AC(k) factor (k sampling slots per entry)."""
     import torch
     pt = None
     if perm is not None:
         pt = torch.as_tensor(np.ascontiguousarray(perm, np.int32), device=A.rowptr.device)
     o = parac_factor_opts(int(seed) & (2**64 - 1), pt.data_ptr() if pt is not None else None,
                           mode, pool_factor, workers, 1 if keep_fp32 else 0, timeout_s,
-                          tail_fraction)
+                          tail_fraction, samples)
     h = C.c_void_p()
     _raise(lib().parac_factor(C.byref(A.c), C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h)
@@ -210,18 +219,29 @@ def parac_apply(f: Factor, r, z, precision=PREC_FP64, stream=None):
     return z
 
 
-def parac_block_shape_set(f: Factor, cols, precision=PREC_FP64, cpl=None, tail_rows=1024):
-    """Fix the block-apply shape for chunks of `cols` columns: cpl 0 = column
-    sweeps, 1/2/4 = level-synchronous launches (cpl=None forgets it, back to
-    column sweeps)."""
-    sh = None if cpl is None else C.byref(parac_block_shape(cpl, tail_rows))
+def parac_block_shape_set(f: Factor, cols, precision=PREC_FP64, cols_per_sweep=None,
+                          workgroups=0):
+    """Fix the block-apply shape for chunks of `cols` columns: sweep slots of
+    `cols_per_sweep` columns (1, 2, 4; 8 with the FP32 apply), at most
+    `workgroups` sweep workgroups per slot (0 = as its units need).
+    cols_per_sweep=None forgets it (the next use takes the cache file's shape
+    or times the candidates)."""
+    sh = None if cols_per_sweep is None else C.byref(
+        parac_block_shape(cols_per_sweep, workgroups, 0, 0.0))
     _raise(lib().parac_block_shape_set(f.h, cols, precision, sh))
 
 
+SHAPE_SOURCES = {0: "fixed", 1: "timed", 2: "cache"}
+
+
 def parac_block_shape_get(f: Factor, cols, precision=PREC_FP64):
+    """The shape in use for (cols, precision): dict with cols_per_sweep,
+    workgroups, source ('fixed', 'timed' or 'cache') and ms (time of one
+    block apply when it was timed)."""
     sh = parac_block_shape()
     _raise(lib().parac_block_shape_get(f.h, cols, precision, C.byref(sh)))
-    return dict(cpl=sh.cpl, tail_rows=sh.tail_rows)
+    return dict(cols_per_sweep=sh.cols_per_sweep, workgroups=sh.workgroups,
+                source=SHAPE_SOURCES.get(sh.source, str(sh.source)), ms=float(sh.ms))
 
 
 def parac_pcg(A: DeviceCSR, f: Factor, b, x, nrhs=None, rtol=1e-6, maxit=10000,
@@ -258,6 +278,34 @@ def parac_pcg_static(A: DeviceCSR, f: Factor, b, x, rtol=1e-6, maxit=10000,
                 true_relres=st.true_relres, applies=st.applies)
 
 
+def parac_order(A, kind, seed=0, stream=None):
+    """An elimination order computed on the device (parac_order): A is a
+    DeviceCSR (the result is computed from its device arrays) or a host CSR
+    with n, rowptr, col.  Returns (perm as an int32 numpy array, MIS rounds)."""
+    rounds = C.c_int32(0)
+    if isinstance(A, DeviceCSR):
+        import torch
+        perm = torch.empty(max(A.n, 1), dtype=torch.int32, device=A.rowptr.device)
+        rc = lib().parac_order(C.byref(A.c), kind, int(seed) & (2**64 - 1),
+                               C.c_void_p(perm.data_ptr()), C.byref(rounds), _stream(stream))
+        _raise(rc)
+        return perm.cpu().numpy()[:A.n], rounds.value
+    n = int(A.n)
+    rowptr = np.ascontiguousarray(A.rowptr, np.int64)
+    col = np.ascontiguousarray(A.col, np.int32)
+    csr = parac_csr(n, int(col.size), rowptr.ctypes.data, col.ctypes.data, None, 0)
+    perm = np.empty(max(n, 1), np.int32)
+    _raise(lib().parac_order(C.byref(csr), kind, int(seed) & (2**64 - 1), perm.ctypes.data,
+                             C.byref(rounds), _stream(stream)))
+    return perm[:n], rounds.value
+
+
+def device_bytes(what=0):
+    """Device bytes the library holds: 0 now, 1 the peak since the last
+    reset, 2 reset the peak to now (parac_device_bytes)."""
+    return int(lib().parac_device_bytes(what))
+
+
 def pcg_static_max_rows():
     """Largest system (rows, ground vertex included) parac_pcg_static takes."""
     return int(lib().parac_pcg_static_max_rows())
@@ -274,7 +322,7 @@ def parac_factor_host(A, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, thr
     pm = None if perm is None else np.ascontiguousarray(perm, np.int32)
     csr = parac_csr(n, int(col.size), rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, 0)
     o = parac_factor_opts(int(seed) & (2**64 - 1), None if pm is None else pm.ctypes.data, mode,
-                          pool_factor, 0, 0, 0.0, 0.0)
+                          pool_factor, 0, 0, 0.0, 0.0, 1)
     out = parac_host_factor()
     rc = lib().parac_factor_host(C.byref(csr), C.byref(o), threads, C.byref(out))
     if rc != OK:

@@ -1,12 +1,15 @@
 """GPU parity of the block (several right-hand sides) path.
 
 The block apply is bit-identical, column by column, to the device's
-single-vector apply of that column, for every launch shape (columns per lane,
-tail threshold) and for the default shape, and agrees with the oracle's apply
-of that column within the rounding bound of the two summation orders; block
-PCG runs an independent recurrence per column, so each column reaches the
-relative residual and agrees with the oracle's single-vector PCG of that
-column."""
+single-vector apply of that column, for every launch shape (columns per sweep
+slot, workgroup cap) and for the tuned shape, and agrees with the oracle's
+apply of that column within the rounding bound of the two summation orders;
+block PCG runs an independent recurrence per column, so each column reaches
+the relative residual and agrees with the oracle's single-vector PCG of that
+column.  The shape autotuner times the candidates on first use, keeps the
+choice in the handle and in the shape cache file, and a later factor of the
+same shape class takes it from the file."""
+import os
 import numpy as np
 import pytest
 
@@ -56,8 +59,19 @@ def single_applies(f, B, precision):
     return out
 
 
-# cpl 0: one dependency-driven sweep pair per column; else level-synchronous
-SHAPES = [(0, 256)] + [(c, t) for c in (1, 2, 4) for t in (0, 64, 1024, 1 << 40)]
+def shapes(precision):
+    """(columns per sweep slot, workgroup cap) of every launch shape."""
+    widths = (1, 2, 4) if precision == 0 else (1, 2, 4, 8)
+    return [(c, w) for c in widths for w in (0, 1, 3)]
+
+
+@pytest.fixture(autouse=True)
+def shape_cache(tmp_path, monkeypatch):
+    """A shape cache file of this test's own (the library reads the path on
+    first use in the process, so every test names the same file)."""
+    path = os.path.join(str(tmp_path), "shapes.json")
+    monkeypatch.setenv("PARAC_SHAPE_CACHE", path)
+    return path
 
 
 @pytest.mark.parametrize("kind", ["grid", "sddm"])
@@ -77,11 +91,13 @@ def test_block_apply_every_shape_bit_identical(orc, kind, precision):
         assert ok, (j, ratio)
     r = torch.tensor(B, device="cuda")
     z = torch.empty_like(r)
-    for cpl, tail in SHAPES:
-        parac.parac_block_shape_set(f, nrhs, precision, cpl=cpl, tail_rows=tail)
+    for cps, wg in shapes(precision):
+        parac.parac_block_shape_set(f, nrhs, precision, cols_per_sweep=cps, workgroups=wg)
         z.fill_(np.nan)
         parac.parac_apply(f, r, z, precision=precision)
-        assert same_bits(z.cpu().numpy(), want), (kind, precision, cpl, tail)
+        assert same_bits(z.cpu().numpy(), want), (kind, precision, cps, wg)
+        sh = parac.parac_block_shape_get(f, nrhs, precision)
+        assert sh["source"] == "fixed" and sh["cols_per_sweep"] == cps
 
 
 @pytest.mark.parametrize("nrhs", [2, 7, 70])
@@ -97,11 +113,13 @@ def test_block_apply_default_shape(orc, nrhs):
     want = single_applies(f, B, 0)
     for j in range(nrhs):
         assert same_bits(got[:, j], want[:, j]), j
-    # chunks of at most 64 columns, each solved by column sweeps unless a
-    # level-synchronous shape is fixed
+    # chunks of at most 64 columns, each with a shape timed on first use (or
+    # taken from the cache file a previous test of this process wrote)
     for cols in sorted({min(64, nrhs - c0) for c0 in range(0, nrhs, 64)}):
         sh = parac.parac_block_shape_get(f, cols)
-        assert sh["cpl"] == 0 and sh["tail_rows"] >= 0
+        assert sh["source"] in ("timed", "cache"), sh
+        assert sh["cols_per_sweep"] in (1, 2, 4) and sh["cols_per_sweep"] <= max(cols, 1)
+        assert sh["ms"] > 0.0
     # the single-vector path agrees as well
     z1 = torch.empty(A.n, dtype=torch.float64, device="cuda")
     parac.parac_apply(f, r[:, 0].contiguous(), z1)
@@ -139,8 +157,8 @@ def test_block_pcg_fp64_per_column(orc, kind):
         if not sddm:
             x, xr = x - x.mean(), xr - xr.mean()
         assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr), j
-    # the level-synchronous block apply gives the same bits
-    parac.parac_block_shape_set(f, nrhs, 0, cpl=2, tail_rows=64)
+    # every fixed shape gives the same bits
+    parac.parac_block_shape_set(f, nrhs, 0, cols_per_sweep=4, workgroups=2)
     x2 = torch.full_like(bt, np.nan)
     sts2 = parac.parac_pcg(dA, f, bt, x2, rtol=1e-6)
     assert [s["iterations"] for s in sts2] == [s["iterations"] for s in sts]
@@ -184,3 +202,66 @@ def test_block_inconsistent_column_rejected(orc):
     assert e.value.status == parac.EINCONSISTENT
     assert orc.check_consistent(A, 1, B[:, 2].copy()) == orc.EINCONSISTENT
     assert orc.check_consistent(A, 1, B[:, 1].copy()) == 0
+
+
+def test_block_shape_tuner_times_then_caches(orc, shape_cache):
+    """First use in a fresh cache: every candidate is timed on the call's own
+    vectors and the fastest kept (source 'timed', its time recorded); the
+    choice is written to the cache file; a new factor of the same shape class
+    takes it from there (source 'cache') without timing; a fixed shape
+    overrides both; forgetting it returns to the file's choice."""
+    import json
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    nrhs = 16
+    A, perm, seed, B, _ = setup_case("sddm", nrhs)
+    dA = parac.DeviceCSR(A)
+    r = torch.tensor(B, device="cuda")
+    f = parac.parac_factor(dA, perm=perm, seed=seed, keep_fp32=True)
+    want = single_applies(f, B, 1)
+    for prec in (0, 1):
+        with pytest.raises(parac.ParacError):
+            parac.parac_block_shape_get(f, nrhs, prec)
+    for prec in (0, 1):
+        z = torch.full_like(r, np.nan)
+        parac.parac_apply(f, r, z, precision=prec)
+        sh = parac.parac_block_shape_get(f, nrhs, prec)
+        assert sh["source"] == "timed" and sh["ms"] > 0.0, sh
+        if prec == 1:
+            assert same_bits(z.cpu().numpy(), want)
+    with open(shape_cache) as fh:
+        cache = json.load(fh)
+    keys = [k for k in cache if "|cols%d|" % nrhs in k]
+    assert any("|fp64|" in k for k in keys) and any("|fp32|" in k for k in keys), cache
+    for k in keys:
+        cps, wg, ms = cache[k]
+        assert cps in (1, 2, 4, 8) and wg >= 0 and ms > 0.0
+    # the same shape class again: from the process's cache, no timing
+    f2 = parac.parac_factor(dA, perm=perm, seed=seed, keep_fp32=True)
+    z = torch.full_like(r, np.nan)
+    parac.parac_apply(f2, r, z, precision=1)
+    sh2 = parac.parac_block_shape_get(f2, nrhs, 1)
+    assert sh2["source"] == "cache", sh2
+    assert sh2["cols_per_sweep"] == parac.parac_block_shape_get(f, nrhs, 1)["cols_per_sweep"]
+    assert same_bits(z.cpu().numpy(), want)
+    # a fixed shape wins; forgetting it goes back to the cached choice
+    parac.parac_block_shape_set(f2, nrhs, 1, cols_per_sweep=1)
+    assert parac.parac_block_shape_get(f2, nrhs, 1)["source"] == "fixed"
+    parac.parac_block_shape_set(f2, nrhs, 1)
+    z.fill_(np.nan)
+    parac.parac_apply(f2, r, z, precision=1)
+    assert parac.parac_block_shape_get(f2, nrhs, 1)["source"] == "cache"
+    assert same_bits(z.cpu().numpy(), want)
+
+
+def test_block_shape_rejects_bad_shapes(orc):
+    need_gpu()
+    from paper_2505_02977_amd import parac
+    A, perm, seed, B, _ = setup_case("grid", 4)
+    f = parac.parac_factor(parac.DeviceCSR(A), perm=perm, seed=seed)
+    for cps, prec in ((3, 0), (8, 0), (16, 1), (0, 1)):
+        with pytest.raises(parac.ParacError) as e:
+            parac.parac_block_shape_set(f, 4, prec, cols_per_sweep=cps)
+        assert e.value.status == parac.EINVAL
+    with pytest.raises(parac.ParacError):
+        parac.parac_block_shape_set(f, 4, 0, cols_per_sweep=2, workgroups=-1)

@@ -225,3 +225,36 @@ def test_nnz_sorted_order_bit_identical(orc, case):
     f = gpu_factor(A, perm, 515)
     assert f.info()["depth"] == ref.stats["depth"]
     compare_factor(f, ref)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_ack_factor_bit_identical(orc, k):
+    """AC(k) (k sampling slots per merged neighbour, loops dropped): the
+    device factor is the oracle's AC(k) factor bit for bit, on a grid, an
+    SDDM system and a power-law graph (large gathered neighbourhoods); k = 1
+    is the plain factor."""
+    need_gpu()
+    from paper_2505_02977_amd import parac
+    rng = np.random.default_rng(500 + k)
+    cases = []
+    i, j = inputs.grid2d_edges(33, 31)
+    cases.append((lap(33 * 31, i, j, rng.uniform(1, 2, len(i))), None))
+    n = 2000
+    i, j = inputs.connected_random_edges(n, 4 * n, rng)
+    ex = np.zeros(n)
+    ex[rng.choice(n, 200, replace=False)] = rng.random(200)
+    cases.append((lap(n, i, j, rng.uniform(0.05, 3.0, len(i)), ex), None))
+    i, j = inputs.chung_lu_edges(1 << 12, 16.0, 2.1, rng)
+    m, i, j, _ = inputs.largest_component(1 << 12, i, j)
+    cases.append((lap(m, i, j, rng.uniform(0.5, 2.0, len(i))), None))
+    for A, _ in cases:
+        perm = rng.permutation(A.n).astype(np.int32)
+        ref = orc.factor(A, perm=perm, seed=321, samples=k)
+        assert ref.status == 0
+        f = gpu_factor(A, perm, 321, samples=k)
+        compare_factor(f, ref)
+        assert f.info()["n_fill"] == ref.stats["n_fill"]
+    # k = 1 is the plain method
+    A = cases[0][0]
+    perm = rng.permutation(A.n).astype(np.int32)
+    compare_factor(gpu_factor(A, perm, 5, samples=1), orc.factor(A, perm=perm, seed=5))

@@ -1,10 +1,12 @@
-"""GPU tests of the serving loop (continuous batching of many systems).
+"""GPU tests of the serving loop (systems in flight on streams of their own).
 
 Every number a system computes depends on its own data only, so its result
 is the same bit for bit alone, in a mix, and through parac_factor +
 parac_pcg; it reaches the relative residual (checked here in FP64) and agrees
 with the oracle's PCG solution.  Admission respects the slot count and the
-memory budget; a request that cannot fit the whole budget is refused."""
+memory budget (the device bytes the library holds during the call stay
+within it); a request that cannot fit the whole budget is refused; small
+systems that arrive behind a large one finish before it."""
 import numpy as np
 import pytest
 
@@ -103,8 +105,12 @@ def test_serve_budget_and_request_errors(orc):
     # a Laplacian request whose b has a nonzero sum
     W = inputs.grid2d_workload(side=20)
     reqs.append(dict(A=W.A, b=W.b + 1.0, perm=W.perm, seed=W.seed, arrival_s=0.0))
-    budget = 60 << 20  # fits every small system, not the big one
+    budget = 150 << 20  # fits every small system, not the big one
+    before = parac.device_bytes(0)
+    parac.device_bytes(2)  # reset the peak
     res, xs = parac.parac_serve(reqs, hbm_budget=budget, max_slots=2)
+    peak = parac.device_bytes(1)
+    assert peak - before <= budget, (peak, before, budget)
     nsmall = len(reqs) - 2
     assert res[nsmall]["status"] == parac.ENOMEM
     assert res[nsmall + 1]["status"] == parac.EINCONSISTENT
@@ -114,3 +120,24 @@ def test_serve_budget_and_request_errors(orc):
     with pytest.raises(parac.ParacError) as e:
         parac.parac_serve(reqs[:1], max_slots=1000)
     assert e.value.status == parac.EINVAL
+
+
+def test_serve_small_systems_pass_a_large_one(orc):
+    """A large system arrives first and small ones just after: with three
+    systems in flight, the small ones run beside the large one and finish
+    before it (no head-of-line blocking), each with its standalone bits."""
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    big = inputs.grid3d_workload(100)  # 1,000,000 vertices
+    reqs = [dict(A=big.A, b=big.b, perm=big.perm, seed=big.seed, rtol=1e-6, arrival_s=0.0)]
+    for k in range(4):
+        W = inputs.sddm_system(k, nmin=1e3, nmax=2e3)
+        reqs.append(dict(A=W.A, b=W.b, perm=W.perm, seed=W.seed, rtol=1e-6,
+                         arrival_s=0.001 * (k + 1)))
+    res, xs = parac.parac_serve(reqs, max_slots=3)
+    assert all(r["status"] == 0 for r in res), res
+    t_big = res[0]["t_done"]
+    assert all(r["t_done"] < t_big for r in res[1:]), [r["t_done"] for r in res]
+    for k in (0, 3):
+        r1, x1 = parac.parac_serve([dict(reqs[k], arrival_s=0.0)], max_slots=1)
+        assert same_bits(x1[0], xs[k]), k

@@ -2,7 +2,7 @@
 
 The preconditioner apply agrees with the oracle's element by element within
 the rounding bound of the two summation orders (the oracle folds each row
-left to right, the device sums long rows in 64-product chunks), in FP64 and
+left to right, the device adds each row as a balanced tree), in FP64 and
 in FP32, and repeated calls give the same bits.  PCG reaches the relative
 residual in FP64 and agrees with the oracle's solution to 1e-8 after removing
 the null-space component; the mixed-precision PCG agrees with the oracle's
