@@ -19,6 +19,8 @@ Workloads (--workload):
   grid2d_64    2D 5-point Laplacian 64x64, weights U[1,2] (small case)
   chung_lu_24_x32  Chung-Lu 2^24, average degree 8, 32 right-hand sides:
                block PCG with the FP32 apply
+  chung_lu_16, chung_lu_18, chung_lu_20
+               smaller members of the 2^22 family (ordering and AC(k) studies)
   serve_200    200 SDDM systems (sizes log-uniform 1e3..1e6, mixed families)
                with Poisson arrivals, served with continuous batching (mixed
                precision) and, for comparison, one at a time in FP64
@@ -464,12 +466,13 @@ def main():
                     "avg degree 16, exponent 2.1, weights (0,1], %%s order; FP64 factor + %%s PCG "
                     "to 1e-6" % W.A.n)
             prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
-        elif name == "chung_lu_20":
-            W = inputs.chung_lu_workload(20)
-            desc = ("chung_lu_20: Chung-Lu Laplacian, 2^20 generated (largest component %d), "
+        elif name in ("chung_lu_16", "chung_lu_18", "chung_lu_20"):
+            lg = int(name.split("_")[-1])
+            W = inputs.chung_lu_workload(lg)
+            desc = ("%s: Chung-Lu Laplacian, 2^%d generated (largest component %d), "
                     "avg degree 16, exponent 2.1, weights (0,1], %%s order; FP64 factor + %%s PCG "
                     "to 1e-6 (a smaller member of the 2^22 family, for ordering and AC(k) "
-                    "studies)" % W.A.n)
+                    "studies)" % (name, lg, W.A.n))
             prec = parac.PREC_MIXED if mixed else parac.PREC_FP64
         elif name == "chung_lu_24_x32":
             W = inputs.chung_lu_workload(24, dbar=8.0, nrhs=32)
