@@ -147,6 +147,34 @@ def roofline(info, timing, elem, workload):
     return out
 
 
+def block_roofline(info, timing, elem, nrhs, shape):
+    """The block apply (both sweeps over nrhs columns in one launch per
+    direction) against the HBM peak: the factor once per direction and the
+    vector terms once per column are what the method has to move; the
+    launch reads the factor once per sweep slot of shape["cols_per_sweep"]
+    columns."""
+    N, n_off = info["n"], info["nnz_off"]
+    T = "double" if elem == 8 else "float"
+    cps = shape["cols_per_sweep"]
+    fac = 2 * n_off * (4 + elem)
+    vec = fwd_bytes(0, N, elem) + bwd_bytes(0, N, elem)
+    slots = (nrhs + cps - 1) // cps
+    app = rl_entry("k_ready<%s, false|true, %d> (both sweeps of one %d-column block apply, %d "
+                   "slots of %d columns)" % (T, cps, nrhs, slots, cps),
+                   fac + nrhs * vec, timing["apply_ms"])
+    app["launch_bytes_factor_per_slot"] = int(slots * fac + nrhs * vec)
+    elim = rl_entry("k_eliminate (one factorisation, one persistent launch)",
+                    elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N), timing["elim_ms"])
+    dom_apply = timing["apply_ms"] * timing["applies"] >= timing["elim_ms"]
+    d, other = (app, elim) if dom_apply else (elim, app)
+    return {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["frac"], "traffic": None, "kernel": d["kernel"],
+            "algorithmic_bytes": d["algorithmic_bytes"], "avg_ms": d["avg_ms"],
+            "limited_by": ("dependency latency: the elimination DAG depth (%d levels) times the "
+                           "per-level publish-to-detect latency, not bandwidth" % info["depth"]),
+            "others": [other]}
+
+
 # --------------------------------------------------------------------------
 # single system (optionally several right-hand sides)
 # --------------------------------------------------------------------------
@@ -224,17 +252,20 @@ def run_system(args, W, desc, precision, nrhs, mixed_extra=False):
         "iterations": iters,
         "true_relres_max": float(rel.max()),
         "apply_ms": round(ms_apply, 4),
-        "fwd_sweep_ms": round(ms_fwd, 4),
+        "fwd_sweep_ms": round(ms_fwd, 4) if nrhs == 1 else None,
         "workers": info["workers"],
     }
     if nrhs == 1:
         pcg_b = pcg_iter_bytes(int(W.A.nnz), n_off, N, elem)
         out["pcg_iteration"] = rl_entry("PCG iteration (SpMV, both sweeps, dots, axpys)", pcg_b,
                                         ms_solve / max(iters, 1))
-    rl = roofline(info, timing, elem, args.workload if args.order == "random" else None)
     if nrhs > 1:
-        rl["note"] = ("block apply: the sweeps' bytes counted as for one column; each of the %d "
-                      "columns runs its own sweep pair in the same launch" % nrhs)
+        shape = parac.parac_block_shape_get(f, min(nrhs, 64), precision)
+        timing["apply_ms"] = ms_apply
+        rl = block_roofline(info, timing, elem, min(nrhs, 64), shape)
+        out["block_shape"] = shape
+    else:
+        rl = roofline(info, timing, elem, args.workload if args.order == "random" else None)
     out["roofline"] = rl
     if mixed_extra:
         # the same factor, preconditioner applied from its FP32 copy (not timed
@@ -439,6 +470,8 @@ def main():
               "(the design notes say how it would); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # long solves report their progress (host convergence checks) on stderr
+    os.environ.setdefault("PARAC_VERBOSE", "1")
     from paper_2505_02977_amd import inputs, parac
     inputs.PROGRESS = log  # the large generators report their stages
     name = args.workload

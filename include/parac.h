@@ -15,6 +15,10 @@
  *   - the factor preconditions conjugate gradients to a relative residual
  *     (§V methodology).
  *
+ * Environment: PARAC_VERBOSE=1 makes long calls report their progress on
+ * stderr (PCG at its host convergence checks, the block-shape tuner per
+ * candidate); PARAC_SHAPE_CACHE names the block-shape cache file.
+ *
  * Conventions for every call:
  *   - all calls return a parac_status (0 = success, negative = error) and
  *     never abort or throw across the ABI; parac_last_error() returns a

@@ -2,6 +2,7 @@
 // handle's accessors.  Host code only orchestrates: every step of the path
 // runs in the library's own kernels.
 #include <math.h>
+#include <stdio.h>
 #include <unistd.h>
 #include <stdlib.h>
 #include <string.h>
@@ -160,6 +161,16 @@ int wall_khz() {
 int status_from(Err &e) {
   g_last_error = e.msg;
   return e.code;
+}
+
+// PARAC_VERBOSE=1: long solves report their progress on stderr at every
+// host convergence check, and the block-shape tuner its candidates
+bool verbose() {
+  static const bool v = [] {
+    const char *e = getenv("PARAC_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
 }
 
 }  // namespace
@@ -1026,6 +1037,11 @@ static parac_block_shape block_shape(parac_factor_t f, int nc, int prec, const d
     float ms = 0.f;
     apply_cols(f, nc, cand, r, ldr, z, ldz, prec, s, &ms);
     spent += ms;
+    if (verbose()) {
+      fprintf(stderr, "parac block shape: %d columns, %d per sweep slot: %.3f ms\n", nc, cps,
+              (double)ms);
+      fflush(stderr);
+    }
     if (!have || ms < best.ms) {
       best = cand;
       best.ms = ms;
@@ -1351,6 +1367,10 @@ static int pcg_run(const parac_csr *A, parac_factor_t f, const double *b, double
     launched += chunk;
     chk(hipMemcpyAsync(hist, ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read");
     chk(hipStreamSynchronize(s), "sync");
+    if (verbose() && launched % 64 == 0) {
+      fprintf(stderr, "parac pcg: %d iterations\n", hist[0]);
+      fflush(stderr);
+    }
     if (hist[1]) break;
   }
   chk(slots_true_res(B, s), "true residual");
@@ -1557,6 +1577,11 @@ static int pcg_block(const parac_csr *A, parac_factor_t f, const double *b, doub
       launched += chunk;
       chk(hipMemcpyAsync(g, gfl, sizeof(g), hipMemcpyDeviceToHost, s), "read");
       chk(hipStreamSynchronize(s), "sync");
+      if (verbose()) {
+        fprintf(stderr, "parac pcg: %d columns, %d iterations, %d columns iterating\n", nc,
+                launched, g[0]);
+        fflush(stderr);
+      }
       if (g[1]) break;
     }
     chk(bpcg_launch_true_res(n, nc, A->rowptr, A->col, A->val, x + c0, nrhs, b + c0, nrhs, q,

@@ -326,7 +326,9 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
     key = merge_key(rc.other, rc.src);
     w = rc.w;
   }
-  // 2. sort by (u, src): bitonic network across the 64 lanes
+  // 2. sort by (u, src) (AC(k): by (u, src, w), keys may repeat; in the
+  // plain method keys are distinct and w never decides): bitonic network
+  // across the 64 lanes
 #pragma unroll
   for (int p = 2; p <= kWave; p <<= 1) {
 #pragma unroll
@@ -334,7 +336,10 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       int pl = (jj == (p >> 1)) ? (l ^ (p - 1)) : (l ^ jj);
       uint64_t ok = shfl_u64(key, pl);
       double ow = shfl_f64(w, pl);
-      bool take = (pl > l) ? (ok < key) : (ok > key);
+      const uint64_t owb = dbits(ow), wbb = dbits(w);
+      const bool lt = ok < key || (ok == key && owb < wbb);
+      const bool gt = ok > key || (ok == key && owb > wbb);
+      bool take = (pl > l) ? lt : gt;
       if (take) {
         key = ok;
         w = ow;
@@ -393,36 +398,49 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       }
     }
   }
-  const double sw = l < d ? bitsd(wb) : 0.0;
+  double sw = l < d ? bitsd(wb) : 0.0;
+  // the sampling slots, one per lane: the merged neighbours, or (AC(k)) each
+  // of them as ks consecutive slots of weight w / ks (ks d <= 64 here)
+  const int ks = a.samples > 1 ? a.samples : 1;
+  const int ds = d * ks;
+  if (ks > 1) {
+    const int src_i = l / ks < kWave ? l / ks : kWave - 1;
+    const double wi = shfl_f64(sw, src_i);
+    const int32_t ui = shfl(su, src_i);
+    sw = l < ds ? wi / (double)ks : 0.0;
+    su = l < ds ? ui : 0x7fffffff;
+  }
   double S = sw;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     double y = shfl_f64(S, l + o < kWave ? l + o : kWave - 1);
-    if (l + o < d) S = S + y;
+    if (l + o < ds) S = S + y;
   }
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     double y = shfl_f64(S, l + o < kWave ? l + o : kWave - 1);
-    if (l + o < d && y > S) S = y;
+    if (l + o < ds && y > S) S = y;
   }
   const double Dk = shfl_f64(S, 0);
-  // 4. one sampled edge per slot s = 0..d-2 (position p = s+1)
-  const bool ins = l < d - 1;
+  // 4. one sampled edge per slot s = 0..ds-2 (position p = s+1)
+  bool ins = l < ds - 1;
   const double Sp1 = shfl_f64(S, l + 1 < kWave ? l + 1 : kWave - 1);
   const double t = draw_unit(a.seed, (uint32_t)k, (uint32_t)l) * Sp1;
-  int lo = l + 1, hi = d - 1;
+  int lo = l + 1, hi = ds - 1;
 #pragma unroll
   for (int it = 0; it < 6; ++it) {
     int mid = (lo + hi) >> 1;
     int idx = mid + 1 < kWave ? mid + 1 : kWave - 1;
     double sn = shfl_f64(S, idx);
-    if (mid + 1 >= d) sn = 0.0;
+    if (mid + 1 >= ds) sn = 0.0;
     if (lo < hi) {
       if (sn <= t) hi = mid;
       else lo = mid + 1;
     }
   }
   const int32_t ub = shfl(su, lo < kWave ? lo : kWave - 1);
+  // AC(k): a partner on the same neighbour is a loop, dropped
+  ins = ins && ub != su;
   const double c = (Sp1 * sw) / Dk;
   const int32_t tgt = su < ub ? su : ub, oth = su < ub ? ub : su;
   {
@@ -961,8 +979,9 @@ __device__ __forceinline__ bool eliminate_pivot(const ElimArgs &a, Worker &wk, i
     return true;
   }
   const int levk = ld_acq_relaxed(&a.lev[k]);
-  // AC(k) pivots sample over k slots per neighbour: the scratch path
-  if (z.g <= kWave && a.samples <= 1)
+  // AC(k) pivots sample over k slots per neighbour: in registers while
+  // all slots fit one wave, else the scratch path
+  if (z.g <= kWave && (a.samples <= 1 || (int64_t)z.g * a.samples <= kWave))
     return small_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline);
   return large_pivot<Sync>(a, wk, k, z.u0, z.nU, z.g, levk, deadline, h, coarse);
 }

@@ -144,6 +144,16 @@ struct Watch {
 // forward, DESC: the lowest backward), then reloads the others, which are
 // usually solved by then.  A single polled address per wave leaves the
 // memory system to the loads and stores of the rows being solved.
+// ci[u] must be a valid index for every u (callers pass one for u >= cnt).
+//
+// With one entry per lane (M = 1, the fold's partial sums) the reload is
+// branch-free: every entry is loaded again and the new bits kept only where
+// the old ones were pending.  The form with the load under a branch was
+// compiled wrongly for the two-column FP32 sweep (hipcc of ROCm 7.2, -O3):
+// the register holding an entry that was already solved was reused for the
+// poll within the loop and not restored, so a column took another entry's
+// value.  The 16-entry form (group units) is compiled correctly; the block
+// apply tests compare every width bit for bit on graphs with long rows.
 template <typename T, int M, int CC, bool DESC>
 __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M], int cnt,
                                            typename Bits<T>::U (&v)[M][CC], Watch &w) {
@@ -153,7 +163,12 @@ __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
     for (int u = 0; u < M; ++u)
 #pragma unroll
       for (int j = 0; j < CC; ++j)
-        if (u < cnt && v[u][j] == B::kPending) v[u][j] = load_bits(vec + ci[u] * CC + j);
+        if constexpr (M == 1) {
+          const typename B::U nv = load_bits(vec + ci[u] * CC + j);
+          v[u][j] = (u < cnt && v[u][j] == B::kPending) ? nv : v[u][j];
+        } else if (u < cnt && v[u][j] == B::kPending) {
+          v[u][j] = load_bits(vec + ci[u] * CC + j);
+        }
   };
   for (;;) {
     // key: the element index p * CC + j of a pending entry (negated: DESC)
@@ -392,12 +407,14 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
       const int nb = (u.z + kBlockChunks - 1) / kBlockChunks;  // block partials
       T acc[CC], tot[CC];
       S.start(pos, acc);
+#pragma unroll
+      for (int j = 0; j < CC; ++j) tot[j] = (T)-0.0;  // -0.0 + s is s, bit for bit
       // partials 64 at a time, one per lane, each batch added as a tree
       // (butterfly over all 64 lanes), batches added in order
       for (int base = 0; base < nb; base += kWave) {
         const int m = nb - base < kWave ? nb - base : kWave;
-        int32_t ci[1] = {u.w + base + l};
         const int cnt = l < m ? 1 : 0;
+        int32_t ci[1] = {cnt ? u.w + base + l : u.w};
         typename Bits<T>::U v[1][CC];
 #pragma unroll
         for (int j = 0; j < CC; ++j)
@@ -406,8 +423,7 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
 #pragma unroll
         for (int j = 0; j < CC; ++j) {
           if (cnt) reset(cs + ci[0] * CC + j);
-          const T s = group_reduce<T, kWave>(cnt ? Bits<T>::val(v[0][j]) : (T)-0.0);
-          tot[j] = base == 0 ? s : tot[j] + s;
+          tot[j] = tot[j] + group_reduce<T, kWave>(cnt ? Bits<T>::val(v[0][j]) : (T)-0.0);
         }
       }
       if (l == 0) {
