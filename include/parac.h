@@ -130,6 +130,19 @@ typedef struct parac_factor_s *parac_factor_t;
 parac_status parac_factor(const parac_csr *A, const parac_factor_opts *o,
                           void *stream, parac_factor_t *out);
 
+/* Test hook, not for production use: parac_factor with some partners of
+ * step 4 of Alg. 2 chosen by the caller instead of drawn, so that a worked
+ * example (the dependency trace of §III, Fig. 1) can be reproduced on the
+ * device.  forced (host, borrowed) holds `count` entries, `stride` per pivot
+ * label k: forced[k * stride + s] >= 0 makes slot s of pivot k take the
+ * partner at offset forced[...] in its candidate range (the neighbours after
+ * the slot's own in sampling order); -1, or an entry beyond `count` or
+ * `stride`, keeps the random draw.  Errors: as parac_factor, plus EINVAL for
+ * stride <= 0, count < 0, or an offset past the end of its candidate range. */
+parac_status parac_debug_factor_forced(const parac_csr *A, const parac_factor_opts *o,
+                                       const int32_t *forced, int32_t stride, int64_t count,
+                                       void *stream, parac_factor_t *out);
+
 /* Sizes and statistics of a factor (host struct, caller-owned). */
 parac_status parac_factor_info(parac_factor_t f, parac_factor_stats *s);
 

@@ -81,7 +81,7 @@ def lib():
         L.orc_classify.argtypes = [C.c_int64, P, P, P, C.c_int32, P, P]
         L.orc_factor.argtypes = [C.c_int64, P, P, P, P, C.c_uint64, C.c_int32, C.c_int32,
                                  C.c_uint64, C.c_int32, P, C.c_int64, C.c_int32, C.c_int32,
-                                 C.c_int32, C.POINTER(C.POINTER(_Res))]
+                                 C.c_int32, C.c_int32, C.POINTER(C.POINTER(_Res))]
         L.orc_factor_free.argtypes = [C.POINTER(_Res)]
         L.orc_apply.argtypes = [C.POINTER(_Res), P, P, P]
         L.orc_apply32.argtypes = [C.POINTER(_Res), P, P, P]
@@ -175,10 +175,16 @@ class Factor:
 def factor(A, perm=None, seed=0, mode=MODE_AUTO, schedule=SCHED_LABEL, sched_seed=0,
            nworkers=1, forced=None, trace=False, debug_flags=0, samples=1):
     """The sequential elimination; samples > 1 is AC(k) with k = samples
-    (R18)."""
+    (R18).  forced: a 1-D sequence of offsets, one per draw in this
+    schedule's order, or a 2-D table forced[k, s] keyed by pivot label and
+    slot (-1: the draw)."""
     n, rp, ci, v = _csr(A)
     pm = None if perm is None else np.ascontiguousarray(perm, np.int32)
     fc = None if forced is None else np.ascontiguousarray(forced, np.int32)
+    stride = 0
+    if fc is not None and fc.ndim == 2:
+        stride = int(fc.shape[1])
+        fc = fc.reshape(-1)
     if fc is not None and fc.size == 0:
         fc = np.zeros(1, np.int32)
         nf = 0
@@ -187,7 +193,8 @@ def factor(A, perm=None, seed=0, mode=MODE_AUTO, schedule=SCHED_LABEL, sched_see
     out = C.POINTER(_Res)()
     lib().orc_factor(n, _p(rp), _p(ci), _p(v), _p(pm), C.c_uint64(int(seed) & (2**64 - 1)),
                      mode, schedule, C.c_uint64(int(sched_seed) & (2**64 - 1)), nworkers,
-                     _p(fc), nf, 1 if trace else 0, debug_flags, int(samples), C.byref(out))
+                     _p(fc), nf, stride, 1 if trace else 0, debug_flags, int(samples),
+                     C.byref(out))
     return Factor(out, pm)
 
 

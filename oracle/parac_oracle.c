@@ -203,7 +203,7 @@ typedef struct {
   double *D;
   /* sampler */
   uint64_t seed;
-  const int32_t *forced; int64_t nforced, iforced;
+  const int32_t *forced; int64_t nforced, iforced; int32_t forced_stride;
   int32_t log_choices;
   int32_t *ch_nopt, *ch_pick; double *ch_prob; int64_t nch, capch;
   /* scratch */
@@ -281,14 +281,24 @@ static void orc_suffix_sums(const double *x, int64_t d, double *S,
     if (S[i + 1] > S[i]) S[i] = S[i + 1];
 }
 
-/* one draw: offset into the candidate range [s+1, d-1] */
+/* one draw: offset into the candidate range [s+1, d-1].  Forced choices
+ * (test hook): either a sequence consumed draw by draw in this schedule's
+ * order, or (forced_stride > 0) a table keyed by pivot label and slot,
+ * forced[k * forced_stride + s], where -1 or an absent entry keeps the draw */
 static int orc_choose(orc_state *st, int32_t k, int64_t s, int64_t d,
                       const double *xw, const double *S, int64_t *qstar) {
-  if (st->forced) {
-    int64_t off = st->iforced < st->nforced ? st->forced[st->iforced] : 0;
+  int64_t off = -1;
+  if (st->forced && st->forced_stride > 0) {
+    int64_t i = (int64_t)k * st->forced_stride + s;
+    if (s < st->forced_stride && i < st->nforced) off = st->forced[i];
+  } else if (st->forced) {
+    off = st->iforced < st->nforced ? st->forced[st->iforced] : 0;
     st->iforced++;
+    if (off < 0) return ORC_EINVAL;
+  }
+  if (off >= 0) {
     int64_t nopt = d - 1 - s;
-    if (off < 0 || off >= nopt) return ORC_EINVAL;
+    if (off >= nopt) return ORC_EINVAL;
     int64_t q = s + 1 + off;
     if (st->log_choices) {
       int64_t need = st->nch + 1;
@@ -497,8 +507,8 @@ int orc_factor(int64_t n, const int64_t *rowptr, const int32_t *col,
                const double *val, const int32_t *perm, uint64_t seed,
                int32_t mode_req, int32_t schedule, uint64_t sched_seed,
                int32_t nworkers, const int32_t *forced, int64_t nforced,
-               int32_t want_trace, int32_t debug_flags, int32_t samples,
-               orc_factor_result **out) {
+               int32_t forced_stride, int32_t want_trace, int32_t debug_flags,
+               int32_t samples, orc_factor_result **out) {
   *out = NULL;
   orc_factor_result *res = (orc_factor_result *)calloc(1, sizeof(*res));
   if (!res) return ORC_ENOMEM;
@@ -524,6 +534,7 @@ int orc_factor(int64_t n, const int64_t *rowptr, const int32_t *col,
   orc_state st;
   memset(&st, 0, sizeof(st));
   st.ntot = ntot; st.seed = seed; st.forced = forced; st.nforced = nforced;
+  st.forced_stride = forced_stride;
   st.log_choices = forced != NULL; st.want_trace = want_trace;
   st.debug_flags = debug_flags;
   st.samples = samples > 1 ? samples : 1;

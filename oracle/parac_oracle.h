@@ -96,14 +96,17 @@ int orc_classify(int64_t n, const int64_t *rowptr, const int32_t *col,
 
 /* The randomized elimination.  perm[v] = elimination label of vertex v
  * (NULL = identity).  forced != NULL switches the sampler to forced choices
- * (offsets into the candidate range; 0 beyond nforced) and logs them.
- * samples > 1 runs AC(k) with k = samples (R18); 0 or 1 the plain method. */
+ * (offsets into the candidate range) and logs them: with forced_stride <= 0
+ * one offset per draw in this schedule's order (0 beyond nforced), with
+ * forced_stride > 0 a table keyed by pivot label k and slot s,
+ * forced[k * forced_stride + s] (-1 or absent: the draw).  samples > 1 runs
+ * AC(k) with k = samples (R18); 0 or 1 the plain method. */
 int orc_factor(int64_t n, const int64_t *rowptr, const int32_t *col,
                const double *val, const int32_t *perm, uint64_t seed,
                int32_t mode_req, int32_t schedule, uint64_t sched_seed,
                int32_t nworkers, const int32_t *forced, int64_t nforced,
-               int32_t want_trace, int32_t debug_flags, int32_t samples,
-               orc_factor_result **out);
+               int32_t forced_stride, int32_t want_trace, int32_t debug_flags,
+               int32_t samples, orc_factor_result **out);
 
 void orc_factor_free(orc_factor_result *f);
 

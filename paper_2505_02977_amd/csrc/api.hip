@@ -260,7 +260,11 @@ static int64_t factor_peak_bytes(int64_t n, int64_t nnz, int sddm, bool host_inp
 
 static void ensure_work(parac_factor_t f, int prec, hipStream_t s);
 
-static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o, hipStream_t s) {
+// forced (host, optional): the test hook's partner offsets, forced_count
+// entries of forced_stride per pivot label
+static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o, hipStream_t s,
+                                  const int32_t *forced = nullptr, int32_t forced_stride = 0,
+                                  int64_t forced_count = 0) {
   if (!A) throw Err{PARAC_EINVAL, "null matrix"};
   const int64_t n = A->n, nnz = A->nnz;
   if (n < 0 || nnz < 0 || n > (int64_t)INT32_MAX - 2 || nnz > (int64_t)INT32_MAX * 4)
@@ -499,6 +503,14 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     ea.team_min = nteam > 0 && samples == 1 ? kTeamMin : 0;
     ea.samples = samples;
     ea.team_wg0 = wgs;
+    if (forced && forced_count > 0) {
+      int32_t *df = tmp.alloc<int32_t>(forced_count, "forced choices");
+      chk(hipMemcpyAsync(df, forced, forced_count * sizeof(int32_t), hipMemcpyHostToDevice, s),
+          "upload");
+      ea.forced = df;
+      ea.forced_stride = forced_stride;
+      ea.forced_count = forced_count;
+    }
     if (ntot > 0) chk(launch_eliminate(ea, wgs + nteam, s), "eliminate");
     chk(hipEventRecord(ev.e[2], s), "event");
     int herr = 0;
@@ -527,6 +539,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     if (herr) {
       throw Err{herr, herr == PARAC_ETIMEOUT ? "elimination watchdog expired"
                       : herr == PARAC_EPOOL  ? "fill pool exhausted after retries"
+                      : herr == PARAC_EINVAL ? "a forced partner offset is out of range"
                                              : "elimination invariant failed"};
     }
     break;
@@ -1883,6 +1896,29 @@ parac_status parac_factor(const parac_csr *A, const parac_factor_opts *o, void *
   *out = nullptr;
   try {
     *out = factor_impl(A, o, (hipStream_t)stream);
+    return PARAC_OK;
+  } catch (Err &e) {
+    return status_from(e);
+  } catch (std::exception &e) {
+    g_last_error = e.what();
+    return PARAC_EINTERNAL;
+  }
+}
+
+parac_status parac_debug_factor_forced(const parac_csr *A, const parac_factor_opts *o,
+                                       const int32_t *forced, int32_t stride, int64_t count,
+                                       void *stream, parac_factor_t *out) {
+  if (!out) {
+    g_last_error = "null output handle";
+    return PARAC_EINVAL;
+  }
+  *out = nullptr;
+  if (stride <= 0 || count < 0 || (count > 0 && !forced)) {
+    g_last_error = "bad forced-choice table";
+    return PARAC_EINVAL;
+  }
+  try {
+    *out = factor_impl(A, o, (hipStream_t)stream, forced, stride, count);
     return PARAC_OK;
   } catch (Err &e) {
     return status_from(e);

@@ -311,6 +311,13 @@ __device__ __forceinline__ bool decrement_batch(const ElimArgs &a, const bool (&
 // ---------------------------------------------------------------------------
 // neighbourhoods of at most 64 gathered entries: one entry per lane
 // ---------------------------------------------------------------------------
+// the test hook's partner offset for slot s of pivot k (-1: draw)
+__device__ __forceinline__ int forced_offset(const ElimArgs &a, int32_t k, int s) {
+  if (s >= a.forced_stride) return -1;
+  const int64_t i = (int64_t)k * a.forced_stride + s;
+  return i < a.forced_count ? a.forced[i] : -1;
+}
+
 template <class Sync>
 __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0, int nU, int g,
                             int levk, uint64_t deadline) {
@@ -329,6 +336,7 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
   // 2. sort by (u, src) (AC(k): by (u, src, w), keys may repeat; in the
   // plain method keys are distinct and w never decides): bitonic network
   // across the 64 lanes
+  const bool tie = a.samples > 1;
 #pragma unroll
   for (int p = 2; p <= kWave; p <<= 1) {
 #pragma unroll
@@ -337,8 +345,8 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       uint64_t ok = shfl_u64(key, pl);
       double ow = shfl_f64(w, pl);
       const uint64_t owb = dbits(ow), wbb = dbits(w);
-      const bool lt = ok < key || (ok == key && owb < wbb);
-      const bool gt = ok > key || (ok == key && owb > wbb);
+      const bool lt = ok < key || (tie && ok == key && owb < wbb);
+      const bool gt = ok > key || (tie && ok == key && owb > wbb);
       bool take = (pl > l) ? lt : gt;
       if (take) {
         key = ok;
@@ -437,6 +445,11 @@ __device__ bool small_pivot(const ElimArgs &a, Worker &wk, int32_t k, int64_t u0
       if (sn <= t) hi = mid;
       else lo = mid + 1;
     }
+  }
+  if (a.forced && ins) {
+    const int fo = forced_offset(a, k, l);
+    if (fo >= 0 && fo >= ds - 1 - l) set_error(a.err, PARAC_EINVAL);
+    else if (fo >= 0) lo = l + 1 + fo;
   }
   const int32_t ub = shfl(su, lo < kWave ? lo : kWave - 1);
   // AC(k): a partner on the same neighbour is a loop, dropped
@@ -706,6 +719,15 @@ __device__ __forceinline__ bool sample_rounds(const ElimArgs &a, Worker &wk, int
       }
     }
     if (!__any(any)) break;
+  }
+  if (a.forced) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = ib + r * stride + l;
+      const int fo = ins[r] ? forced_offset(a, k, sl) : -1;
+      if (fo >= 0 && fo >= d - 1 - sl) set_error(a.err, PARAC_EINVAL);
+      else if (fo >= 0) lo[r] = sl + 1 + fo;
+    }
   }
   int32_t tgt[R], oth[R];
   double c[R];

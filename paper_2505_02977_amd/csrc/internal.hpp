@@ -77,6 +77,11 @@ struct ElimArgs {
   int32_t team_min;    // pivots with more gathered entries go to teams (0: none)
   int32_t samples;     // AC(k): sampling slots per merged neighbour (1: plain)
   int32_t team_wg0;    // workgroups from this index on are teams
+  // test hook (worked examples): forced[k * forced_stride + s], when present
+  // and >= 0, is the partner offset of slot s of pivot k in place of a draw
+  const int32_t *forced;
+  int32_t forced_stride;
+  int64_t forced_count;
 };
 
 // --- launchers (setup.hip) ---

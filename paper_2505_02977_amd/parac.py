@@ -104,6 +104,9 @@ def lib():
         L.parac_factor.argtypes = [C.POINTER(parac_csr), C.POINTER(parac_factor_opts), P,
                                    C.POINTER(P)]
         L.parac_factor_info.argtypes = [P, C.POINTER(parac_factor_stats)]
+        L.parac_debug_factor_forced.argtypes = [C.POINTER(parac_csr), C.POINTER(parac_factor_opts),
+                                                P, C.c_int32, C.c_int64, P, C.POINTER(P)]
+        L.parac_debug_factor_forced.restype = C.c_int
         L.parac_factor_export.argtypes = [P, P, P, P, P, P]
         L.parac_apply.argtypes = [P, P, P, C.c_int64, C.c_int32, P]
         L.parac_pcg.argtypes = [C.POINTER(parac_csr), P, P, P, C.c_int64,
@@ -196,8 +199,10 @@ class Factor:
 
 def parac_factor(A: DeviceCSR, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.0, workers=0,
                  keep_fp32=False, timeout_s=30.0, tail_fraction=0.0, samples=1,
-                 stream=None) -> Factor:
-    """samples = k > 1 builds the AC(k) factor (k sampling slots per entry)."""
+                 stream=None, forced=None) -> Factor:
+    """samples = k > 1 builds the AC(k) factor (k sampling slots per entry).
+    forced (test hook): a 2-D int array, forced[k, s] the partner offset of
+    slot s of pivot label k (-1: drawn), passed to parac_debug_factor_forced."""
     import torch
     pt = None
     if perm is not None:
@@ -206,7 +211,14 @@ def parac_factor(A: DeviceCSR, perm=None, seed=0, mode=MODE_AUTO, pool_factor=4.
                           mode, pool_factor, workers, 1 if keep_fp32 else 0, timeout_s,
                           tail_fraction, samples)
     h = C.c_void_p()
-    _raise(lib().parac_factor(C.byref(A.c), C.byref(o), _stream(stream), C.byref(h)))
+    if forced is None:
+        _raise(lib().parac_factor(C.byref(A.c), C.byref(o), _stream(stream), C.byref(h)))
+    else:
+        fa = np.ascontiguousarray(forced, np.int32)
+        assert fa.ndim == 2
+        _raise(lib().parac_debug_factor_forced(
+            C.byref(A.c), C.byref(o), fa.ctypes.data_as(C.c_void_p), int(fa.shape[1]),
+            int(fa.size), _stream(stream), C.byref(h)))
     return Factor(h)
 
 

@@ -258,3 +258,58 @@ def test_ack_factor_bit_identical(orc, k):
     A = cases[0][0]
     perm = rng.permutation(A.n).astype(np.int32)
     compare_factor(gpu_factor(A, perm, 5, samples=1), orc.factor(A, perm=perm, seed=5))
+
+
+def test_fig1_trace_forced_on_device(orc):
+    """The worked dependency trace of §III (Fig. 1) on the device: the test
+    hook forces pivot 0's three slots to their last candidate, which gives
+    the sampled tree of the figure; factor and levels equal the oracle's bit
+    for bit.  A table of -1 leaves the draws alone, and an offset past its
+    candidate range is EINVAL."""
+    need_gpu()
+    from paper_2505_02977_amd import parac
+    from tests.test_oracle_pins import fig1_matrix
+    g, A = fig1_matrix()
+    tab = -np.ones((g["n"], 4), np.int32)
+    tab[0, :3] = [2, 1, 0]
+    ref = orc.factor(A, forced=tab)
+    assert ref.status == 0
+    f = gpu_factor(A, None, 0, forced=tab)
+    compare_factor(f, ref)
+    colptr, rowind, _, _, lev = f.export()
+    assert list(rowind[colptr[0]:colptr[1]]) == [1, 3, 4, 5]
+    assert all(list(rowind[colptr[k]:colptr[k + 1]]) == [5] for k in (1, 2, 3, 4))
+    assert list(lev) == [0, 1, 0, 1, 1, 2]
+    for seed in (5, 6):
+        f = gpu_factor(A, None, seed, forced=-np.ones((g["n"], 4), np.int32))
+        compare_factor(f, orc.factor(A, seed=seed))
+    bad = tab.copy()
+    bad[0, 2] = 1
+    with pytest.raises(parac.ParacError) as e:
+        gpu_factor(A, None, 0, forced=bad)
+    assert e.value.status == parac.EINVAL
+
+
+@pytest.mark.parametrize("case", ["hub", "bighub", "power_law"])
+def test_forced_choices_every_path(orc, case):
+    """Forced choices keyed by (pivot, slot) act the same way in the one-wave,
+    large-neighbourhood and team pivots: a third of the pivots take offset 0
+    (the next candidate in sampling order) in their first 64 slots, the rest
+    draw; the factor equals the oracle's under the same table."""
+    need_gpu()
+    if case == "power_law":
+        A, perm, _ = power_law_case(orc)
+        seed = 4242
+    else:
+        A = dict((c[0], c[1]) for c in case_graphs())[case]
+        perm = np.random.default_rng(5).permutation(A.n).astype(np.int32)
+        seed = 99
+    rng = np.random.default_rng(A.n)
+    tab = -np.ones((A.n, 64), np.int32)
+    tab[rng.random(A.n) < 1 / 3] = 0
+    ref = orc.factor(A, perm=perm, seed=seed, forced=tab)
+    assert ref.status == 0
+    f = gpu_factor(A, perm, seed, forced=tab)
+    compare_factor(f, ref)
+    plain = orc.factor(A, perm=perm, seed=seed)
+    assert not np.array_equal(plain.val.view(np.uint64), ref.val.view(np.uint64))

@@ -25,7 +25,7 @@ def project(x, sddm):
     return x if sddm else x - x.mean()
 
 
-def check_system(orc, W, sddm, mixed=True, oracle_pcg=True):
+def check_system(orc, W, sddm, mixed=True, oracle_pcg=True, relative=False):
     torch = need_gpu()
     from paper_2505_02977_amd import parac
     t0 = time.time()
@@ -52,7 +52,24 @@ def check_system(orc, W, sddm, mixed=True, oracle_pcg=True):
         out["fp64_vs_oracle"] = float(np.linalg.norm(xp - xrp) / np.linalg.norm(xrp))
         say("%s: FP64 PCG %d iterations, vs oracle %.2e (oracle PCG %.1f s)"
             % (W.name, st["iterations"], out["fp64_vs_oracle"], time.time() - t1))
-        assert out["fp64_vs_oracle"] <= 1e-8
+        if relative:
+            # CG iterates under two rounding orders drift apart by a fraction
+            # of the iteration error itself, so no fixed tolerance follows
+            # from the arithmetic.  Judged against the converged solution
+            # (oracle to 1e-10): the two solutions differ by less than half
+            # the oracle's own error, and the device's error is at most
+            # twice the oracle's.
+            xt, _ = orc.pcg(W.A, ref, b, rtol=1e-10)
+            xtp = project(xt, sddm)
+            nt = np.linalg.norm(xtp)
+            out["oracle_own_error"] = float(np.linalg.norm(xrp - xtp) / nt)
+            out["device_own_error"] = float(np.linalg.norm(xp - xtp) / nt)
+            say("%s: error against the converged solution: oracle %.2e, device %.2e"
+                % (W.name, out["oracle_own_error"], out["device_own_error"]))
+            assert out["fp64_vs_oracle"] <= 0.5 * out["oracle_own_error"]
+            assert out["device_own_error"] <= 2.0 * out["oracle_own_error"]
+        else:
+            assert out["fp64_vs_oracle"] <= 1e-8
     if mixed:
         xm_t = torch.empty_like(bt)
         sm = parac.parac_pcg(dA, f, bt, xm_t, rtol=1e-6, precision=parac.PREC_MIXED)[0]
@@ -80,7 +97,12 @@ def test_grid3d_128_full_size(orc):
     need_gpu()
     say("generating grid3d_128")
     W = inputs.grid3d_workload(128)
-    check_system(orc, W, sddm=False)
+    # weights over four decades: the rounding difference of the two apply
+    # summation orders (device balanced tree, oracle left fold) grows over
+    # the 38 iterations beyond a fixed 1e-8 (2.6e-8 measured, against an
+    # error of 1.4e-7 of either solution), so the agreement is judged
+    # against the solve's own error
+    check_system(orc, W, sddm=False, relative=True)
 
 
 # one system of each family of the serving stream, the smallest of at

@@ -142,6 +142,41 @@ def test_fig1_trace(orc):
     assert all(v not in enq for v in g["not_enqueued"])
 
 
+def fig1_matrix():
+    g = json.load(open(os.path.join(GOLDEN, "fig1_trace.json")))
+    e = np.array(g["edges"])
+    wmap = {(0, 1): 1.0, (0, 3): 2.0, (0, 4): 3.0, (0, 5): 4.0, (2, 5): 1.5}
+    w = np.array([wmap[(min(a, b), max(a, b))] for a, b in e])
+    return g, lap(g["n"], e[:, 0], e[:, 1], w)
+
+
+def test_fig1_keyed_forcing(orc):
+    """The forced-choice table keyed by (pivot label, slot) -- the form the
+    device hook takes -- reproduces the sequential forcing of the worked
+    example under either schedule, a table of -1 is the plain draw, and an
+    offset past its candidate range is an error."""
+    g, A = fig1_matrix()
+    seq = orc.factor(A, forced=[2, 1, 0])
+    assert seq.status == orc.OK
+    tab = -np.ones((g["n"], 4), np.int32)
+    tab[0, :3] = [2, 1, 0]
+    for sched in (orc.SCHED_LABEL, orc.SCHED_ASYNC):
+        keyed = orc.factor(A, forced=tab, schedule=sched, sched_seed=3, nworkers=3)
+        assert keyed.status == orc.OK and same_factor(seq, keyed), sched
+    # the sampled tree of the figure: column 0 holds 1, 3, 4, 5, and each of
+    # 1, 3, 4 (and 2, by its own edge) has 5 as its only entry
+    col = lambda k: list(seq.rowind[seq.colptr[k]:seq.colptr[k + 1]])  # noqa: E731
+    assert col(0) == [1, 3, 4, 5] and all(col(k) == [5] for k in (1, 2, 3, 4))
+    assert list(seq.level) == [0, 1, 0, 1, 1, 2]
+    for seed in (5, 6):
+        plain = orc.factor(A, seed=seed)
+        none = orc.factor(A, seed=seed, forced=-np.ones((g["n"], 4), np.int32))
+        assert same_factor(plain, none)
+    bad = tab.copy()
+    bad[0, 2] = 1  # the last slot has one candidate (offset 0)
+    assert orc.factor(A, forced=bad).status == orc.EINVAL
+
+
 # ----------------------------------------------------------------------------
 # T2: degree-2 pivots are exact (the sampled edge is the Schur complement)
 # ----------------------------------------------------------------------------

@@ -60,7 +60,10 @@ def test_static_pcg_rejects_above_limit():
     i = np.arange(n - 1)
     A = inputs.laplacian_from_edges(n, i, i + 1, np.ones(n - 1))
     dA = parac.DeviceCSR(A)
-    f = parac.parac_factor(dA, seed=5)
+    # random labels: a path labelled in order would be one dependent chain
+    # of n pivots, eliminated one after another
+    perm = np.random.default_rng(5).permutation(n).astype(np.int32)
+    f = parac.parac_factor(dA, perm=perm, seed=5)
     b = torch.zeros(n, dtype=torch.float64, device="cuda")
     x = torch.empty_like(b)
     with pytest.raises(parac.ParacError) as e:
