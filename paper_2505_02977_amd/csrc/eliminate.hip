@@ -189,13 +189,20 @@ __device__ bool insert_records(const ElimArgs &a, Worker &wk, const bool (&ins)[
       return false;
     }
   }
+  // the larger endpoint still counts k among its lower neighbours (k's own
+  // edge to it is removed after the insertions), so its counter is >= 1
+  bool bad = false;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     if (ins[q]) {
       Rec *dst = (j[q] == 0) ? a.inl + (int64_t)tgt[q] * kInline + off[q] : a.pool + pbase[q] + off[q];
       store_rec(dst, oth[q], k, c[q]);
-      fetch_add(&a.dp[oth[q]], 1);
+      bad |= fetch_add(&a.dp[oth[q]], 1) < 1;
     }
+  }
+  if (__any(bad)) {
+    set_error(a.err, PARAC_EINTERNAL);
+    return false;
   }
   return true;
 }

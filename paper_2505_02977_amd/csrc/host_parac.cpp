@@ -304,8 +304,14 @@ struct ThreadCols {
   std::vector<double> val;
 };
 
+// a vertex is enqueued once, when its counter reaches zero; more than ntot
+// enqueues means some vertex came twice
 void enqueue(Shared &S, int32_t u) {
   const int64_t at = S.q_tail.fetch_add(1, std::memory_order_relaxed);
+  if (at >= S.ntot) {
+    S.error.store(PARAC_EINTERNAL, std::memory_order_relaxed);
+    return;
+  }
   S.q[at].store(u, std::memory_order_release);
 }
 
@@ -396,7 +402,8 @@ void worker(Shared &S, int tid, ThreadCols &cols) {
         rec.w = c;
         // the larger endpoint gains a lower neighbour before k's own edge to
         // it is removed below (insert before delete)
-        S.dp[oth].fetch_add(1, std::memory_order_relaxed);
+        if (S.dp[oth].fetch_add(1, std::memory_order_relaxed) < 1)
+          S.error.store(PARAC_EINTERNAL, std::memory_order_relaxed);
         int64_t head = S.inbox[tgt].load(std::memory_order_relaxed);
         do {
           rec.next = head;
@@ -416,6 +423,7 @@ void worker(Shared &S, int tid, ThreadCols &cols) {
     for (const Merged &m : byu) {
       atomic_max(S.level[m.u], lk + 1);
       const int32_t prior = S.dp[m.u].fetch_sub(m.m, std::memory_order_acq_rel);
+      if (prior < m.m) S.error.store(PARAC_EINTERNAL, std::memory_order_relaxed);
       if (prior == m.m) enqueue(S, m.u);
     }
   }
@@ -517,7 +525,9 @@ void run_elimination(const parac_csr &A, const parac_factor_opts &o, int threads
       }
       continue;
     }
-    if (err) throw FailCode{err, "host elimination failed"};
+    if (err)
+      throw FailCode{err, err == PARAC_EINTERNAL ? "a dependency counter invariant failed"
+                                                 : "host elimination failed"};
     if (S.q_tail.load() != ntot) throw FailCode{PARAC_EINTERNAL, "not every vertex was eliminated"};
     break;
   }

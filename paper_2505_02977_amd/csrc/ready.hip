@@ -97,6 +97,61 @@ __device__ __forceinline__ void reset(T *p) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Pairs.  With the FP32 apply and an even number of columns per slot, the
+// two columns 2i, 2i+1 of a position form one 8-byte-aligned pair, read and
+// written by one 64-bit access: a gather moves one address per pair, and a
+// row's two values become visible together.  Elements stay the unit of the
+// pending test; a pair is reloaded when either element is pending (an
+// element once solved keeps its bits for the rest of the sweep).
+template <typename T, int CC>
+__host__ __device__ constexpr int pack_width() {
+  return (sizeof(T) == 4 && CC % 2 == 0) ? 2 : 1;
+}
+
+__device__ __forceinline__ unsigned long long load_pair(const float *p) {
+  return __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// v[j], v[j+1] (PW = 2) or v[j] (PW = 1) from the element p
+template <typename T, int PW, int CC>
+__device__ __forceinline__ void load_elems(const T *p, typename Bits<T>::U (&v)[CC], int j) {
+  if constexpr (PW == 2) {
+    const unsigned long long w = load_pair((const float *)p);
+    v[j] = (unsigned)(w & 0xffffffffull);
+    v[j + 1] = (unsigned)(w >> 32);
+  } else {
+    v[j] = load_bits(p);
+  }
+}
+
+template <typename T, int PW>
+__device__ __forceinline__ void publish_elems(T *p, const T *v) {
+  if constexpr (PW == 2) {
+    using B = Bits<T>;
+    typename B::U u0 = B::of(v[0]), u1 = B::of(v[1]);
+    if (u0 == B::kPending) u0 = B::kQuietNaN;
+    if (u1 == B::kPending) u1 = B::kQuietNaN;
+    __hip_atomic_store((unsigned long long *)p,
+                       (unsigned long long)u0 | ((unsigned long long)u1 << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    publish(p, v[0]);
+  }
+}
+
+template <typename T, int PW>
+__device__ __forceinline__ void reset_elems(T *p) {
+  if constexpr (PW == 2) {
+    using B = Bits<T>;
+    __hip_atomic_store((unsigned long long *)p,
+                       (unsigned long long)B::kPending | ((unsigned long long)B::kPending << 32),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    reset(p);
+  }
+}
+
 __device__ __forceinline__ double shfl_xor_t(double v, int o) { return __shfl_xor(v, o, kWave); }
 __device__ __forceinline__ float shfl_xor_t(float v, int o) { return __shfl_xor(v, o, kWave); }
 
@@ -158,17 +213,23 @@ template <typename T, int M, int CC, bool DESC>
 __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M], int cnt,
                                            typename Bits<T>::U (&v)[M][CC], Watch &w) {
   using B = Bits<T>;
+  constexpr int PW = pack_width<T, CC>();
   auto reload = [&]() {
 #pragma unroll
     for (int u = 0; u < M; ++u)
 #pragma unroll
-      for (int j = 0; j < CC; ++j)
+      for (int j = 0; j < CC; j += PW) {
+        bool pend = v[u][j] == B::kPending;
+        if constexpr (PW == 2) pend = pend || v[u][j + 1] == B::kPending;
         if constexpr (M == 1) {
-          const typename B::U nv = load_bits(vec + ci[u] * CC + j);
-          v[u][j] = (u < cnt && v[u][j] == B::kPending) ? nv : v[u][j];
-        } else if (u < cnt && v[u][j] == B::kPending) {
-          v[u][j] = load_bits(vec + ci[u] * CC + j);
+          typename B::U nv[CC];
+          load_elems<T, PW, CC>(vec + ci[u] * CC + j, nv, j);
+#pragma unroll
+          for (int t = 0; t < PW; ++t) v[u][j + t] = (u < cnt && pend) ? nv[j + t] : v[u][j + t];
+        } else if (u < cnt && pend) {
+          load_elems<T, PW, CC>(vec + ci[u] * CC + j, v[u], j);
         }
+      }
   };
   for (;;) {
     // key: the element index p * CC + j of a pending entry (negated: DESC)
@@ -272,11 +333,18 @@ __device__ __forceinline__ void group_sum(int64_t b, int64_t e1, int q, bool val
     ci[u] = u < cnt ? idx[a + u] : 0;
     f[u] = u < cnt ? fv[a + u] : (T)0;
   }
+  constexpr int PW = pack_width<T, CC>();
 #pragma unroll
   for (int u = 0; u < 16; ++u)
 #pragma unroll
-    for (int j = 0; j < CC; ++j)
-      v[u][j] = u < cnt ? load_bits(vec + ci[u] * CC + j) : (typename B::U)0;
+    for (int j = 0; j < CC; j += PW) {
+      if (u < cnt) {
+        load_elems<T, PW, CC>(vec + ci[u] * CC + j, v[u], j);
+      } else {
+#pragma unroll
+        for (int t = 0; t < PW; ++t) v[u][j + t] = 0;
+      }
+    }
   wait_ready<T, 16, CC, DESC>(vec, ci, cnt, v, w);
 #pragma unroll
   for (int j = 0; j < CC; ++j) {
@@ -319,18 +387,19 @@ struct Sweep {
   // publish row pos; forward resets x[pos], backward resets y[pos] and
   // writes z in the original ordering
   __device__ __forceinline__ void finish(int64_t pos, const T (&v)[CC]) const {
+    constexpr int PW = pack_width<T, CC>();
 #pragma unroll
-    for (int j = 0; j < CC; ++j) publish(out + pos * CC + j, v[j]);
+    for (int j = 0; j < CC; j += PW) publish_elems<T, PW>(out + pos * CC + j, v + j);
     if constexpr (BWD) {
       double *z = q.z + (int64_t)q.a.src[pos] * q.ldz;
 #pragma unroll
-      for (int j = 0; j < CC; ++j) {
-        reset((T *)q.y + pos * CC + j);
+      for (int j = 0; j < CC; j += PW) reset_elems<T, PW>((T *)q.y + pos * CC + j);
+#pragma unroll
+      for (int j = 0; j < CC; ++j)
         if (j < nc) z[j] = (double)v[j];
-      }
     } else {
 #pragma unroll
-      for (int j = 0; j < CC; ++j) reset((T *)q.x + pos * CC + j);
+      for (int j = 0; j < CC; j += PW) reset_elems<T, PW>((T *)q.x + pos * CC + j);
     }
   }
 };
@@ -401,7 +470,8 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
       group_sum<T, 64, BWD, CC>(e0 + kChunk * c0, e1, l, true, S.idx, S.fv, S.in, w, c);
       if (l == 0)
 #pragma unroll
-        for (int j = 0; j < CC; ++j) publish(cs + (u.w + c0 / kBlockChunks) * CC + j, c[j]);
+        for (int j = 0; j < CC; j += pack_width<T, CC>())
+          publish_elems<T, pack_width<T, CC>()>(cs + (u.w + c0 / kBlockChunks) * CC + j, c + j);
     } else {  // fold
       const int64_t pos = first_lane_i32(u.y);
       const int nb = (u.z + kBlockChunks - 1) / kBlockChunks;  // block partials
@@ -415,16 +485,21 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
         const int m = nb - base < kWave ? nb - base : kWave;
         const int cnt = l < m ? 1 : 0;
         int32_t ci[1] = {cnt ? u.w + base + l : u.w};
+        constexpr int PW = pack_width<T, CC>();
         typename Bits<T>::U v[1][CC];
 #pragma unroll
-        for (int j = 0; j < CC; ++j)
-          v[0][j] = cnt ? load_bits(cs + ci[0] * CC + j) : (typename Bits<T>::U)0;
-        wait_ready<T, 1, CC, false>(cs, ci, cnt, v, w);
+        for (int j = 0; j < CC; j += PW) {
+          load_elems<T, PW, CC>(cs + ci[0] * CC + j, v[0], j);
 #pragma unroll
-        for (int j = 0; j < CC; ++j) {
-          if (cnt) reset(cs + ci[0] * CC + j);
-          tot[j] = tot[j] + group_reduce<T, kWave>(cnt ? Bits<T>::val(v[0][j]) : (T)-0.0);
+          for (int t = 0; t < PW; ++t) v[0][j + t] = cnt ? v[0][j + t] : 0;
         }
+        wait_ready<T, 1, CC, false>(cs, ci, cnt, v, w);
+        if (cnt)
+#pragma unroll
+          for (int j = 0; j < CC; j += PW) reset_elems<T, PW>(cs + ci[0] * CC + j);
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+          tot[j] = tot[j] + group_reduce<T, kWave>(cnt ? Bits<T>::val(v[0][j]) : (T)-0.0);
       }
       if (l == 0) {
 #pragma unroll
