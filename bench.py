@@ -46,33 +46,33 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE), scaled by the same counters on a copy of known size; valid only
 # for the kernel sources and the workload it was taken from
 TRAFFIC_PROFILES = {
-    "chung_lu_22": os.path.join(ROOT, "profiles", "k_ready_traffic_chung_lu_22.md"),
-    "grid3d_128": os.path.join(ROOT, "profiles", "k_ready_traffic_grid3d_128.md"),
+    "chung_lu_22": os.path.join(ROOT, "profiles", "hbm_traffic_chung_lu_22.md"),
+    "grid3d_128": os.path.join(ROOT, "profiles", "hbm_traffic_grid3d_128.md"),
 }
-SWEEP_SOURCES = ["ready.hip", "internal.hpp", "device.hpp"]
+KERNEL_SOURCES = ["ready.hip", "eliminate.hip", "internal.hpp", "device.hpp"]
 
 
-def sweep_source_hash():
+def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2505_02977_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` (e.g. "k_ready<double, true>") from
+    """HBM bytes per launch of `kernel` (e.g. "k_ready<double, true, 1>") from
     the committed counter summary, if it was taken on this workload from the
-    current sweep sources; else None."""
+    current kernel sources; else None."""
     import re
     path = TRAFFIC_PROFILES.get(workload)
     if path is None or not os.path.exists(path):
         return None
     text = open(path).read()
-    m1 = re.search(r"sweep-sources-sha256:\s*([0-9a-f]{64})", text)
+    m1 = re.search(r"kernel-sources-sha256:\s*([0-9a-f]{64})", text)
     m2 = re.search(r"hbm-bytes-per-launch %s:\s*([0-9]+)" % re.escape(kernel), text)
-    if not (m1 and m2) or m1.group(1) != sweep_source_hash():
+    if not (m1 and m2) or m1.group(1) != kernel_source_hash():
         return None
     return int(m2.group(1))
 
@@ -133,7 +133,8 @@ def roofline(info, timing, elem, workload):
     bwd = rl_entry("%s (backward sweep F^T x = D^+ y, one launch)" % kb,
                    bwd_bytes(n_off, N, elem), timing["bwd_ms"], measured_traffic(workload, kb))
     elim = rl_entry("k_eliminate (one factorisation, one persistent launch)",
-                    elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N), timing["elim_ms"])
+                    elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N), timing["elim_ms"],
+                    measured_traffic(workload, "k_eliminate"))
     per_step = {"fwd": timing["fwd_ms"] * timing["applies"],
                 "bwd": timing["bwd_ms"] * timing["applies"], "elim": timing["elim_ms"]}
     dom = max(per_step, key=per_step.get)
