@@ -66,8 +66,10 @@
 
 #include <float.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10, from the published description of the generator: ten     */
@@ -597,7 +599,15 @@ int orc_factor(int64_t n, const int64_t *rowptr, const int32_t *col,
   if (schedule == ORC_SCHED_LABEL) {
     orc_worker wk;
     memset(&wk, 0, sizeof(wk));
+    /* optional progress lines on stderr for long runs (no effect on results) */
+    const int progress = getenv("ORC_PROGRESS") != NULL;
+    time_t last = time(NULL);
     for (int64_t k = 0; k < ntot && !rc; ++k) {
+      if (progress && (k & 1023) == 0 && time(NULL) - last >= 10) {
+        last = time(NULL);
+        fprintf(stderr, "oracle: %lld of %lld pivots\n", (long long)k, (long long)ntot);
+        fflush(stderr);
+      }
       if (st.dp[k] != 0 || !st.enq[k]) { rc = ORC_EINTERNAL; break; }
       if ((rc = orc_trace(&st, ORC_EV_CLAIM, k, 0, 0))) break;
       if ((rc = orc_eliminate(&st, (int32_t)k, &wk))) break;

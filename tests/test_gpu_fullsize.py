@@ -5,6 +5,7 @@ the Chung-Lu 2^22 workload is identical to the oracle's, bit for bit (F, D
 and the levels); their PCG solutions agree with the oracle's (FP64) or are
 within the stated bounds of it (FP32 apply).  One system of each family of
 the serving stream at n >= 1e5 is checked the same way."""
+import os
 import time
 
 import numpy as np
@@ -123,3 +124,37 @@ def test_chung_lu_22_full_size(orc):
     say("generating chung_lu_22")
     W = inputs.chung_lu_workload(22)
     check_system(orc, W, sddm=False, oracle_pcg=False)
+
+
+@pytest.mark.skipif(os.environ.get("PARAC_FULLSIZE_SLOW") != "1",
+                    reason="several minutes of oracle work on one core; set PARAC_FULLSIZE_SLOW=1")
+def test_chung_lu_24_x32_factor_full_size(orc):
+    """The block workload's factor (Chung-Lu 2^24 generated, average degree
+    8) equals the oracle's bit for bit, and the FP32 apply of its first and
+    last right-hand sides lies within the rounding bound of the oracle's."""
+    torch = need_gpu()
+    from paper_2505_02977_amd import parac
+    from tests.bounds import within_apply_bound
+    say("generating chung_lu_24_x32")
+    W = inputs.chung_lu_workload(24, dbar=8.0, nrhs=32)
+    t0 = time.time()
+    dA = parac.DeviceCSR(W.A)
+    f = parac.parac_factor(dA, perm=W.perm, seed=W.seed, keep_fp32=True)
+    say("chung_lu_24: device factor %.1f ms, nnz(F) %d, depth %d" % (
+        f.info()["ms_total"], f.info()["nnz_off"], f.info()["depth"]))
+    os.environ["ORC_PROGRESS"] = "1"  # the oracle reports its progress every 10 s
+    ref = orc.factor(W.A, perm=W.perm, seed=W.seed)
+    say("chung_lu_24: oracle factor %.1f s" % (time.time() - t0))
+    assert ref.status == 0
+    compare_factor(f, ref)
+    say("chung_lu_24: factor, D and levels identical to the oracle's")
+    B = np.ascontiguousarray(W.b)
+    for j in (0, 31):
+        r = np.ascontiguousarray(B[:, j])
+        rt = torch.tensor(r, device="cuda")
+        zt = torch.empty_like(rt)
+        parac.parac_apply(f, rt, zt, precision=parac.PREC_MIXED)
+        say("chung_lu_24: column %d applied; the rounding bound takes four sparse solves" % j)
+        ok, ratio = within_apply_bound(zt.cpu().numpy(), orc.apply(ref, r, precision=1), ref, r, 1)
+        say("chung_lu_24: column %d FP32 apply within %.3f of the bound" % (j, ratio))
+        assert ok, (j, ratio)
