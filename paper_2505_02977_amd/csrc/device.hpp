@@ -192,8 +192,9 @@ __device__ __forceinline__ int bitonic_partner(int l, int p, int j, bool first) 
 static __device__ uint64_t g_radix_sink[2];
 constexpr int kRadixGroup = 8;  // chunks of 64 whose loads are issued together
 
-// h[digit] += count of the keys in [lo, hi) (h in LDS, owned by this wave)
-template <typename K>
+// h[digit] += count of the keys in [lo, hi) (h in LDS, owned by this wave);
+// a digit is the BITS bits of the key from bit sh on
+template <typename K, int BITS = 8>
 __device__ __forceinline__ void radix_count(const K *ks, int lo, int hi, int sh, int *h) {
   const int l = lane();
   for (int base = lo; base < hi; base += kRadixGroup * kWave) {
@@ -205,7 +206,8 @@ __device__ __forceinline__ void radix_count(const K *ks, int lo, int hi, int sh,
     }
 #pragma unroll
     for (int q = 0; q < kRadixGroup; ++q)
-      if (base + q * kWave + l < hi) atomicAdd(&h[(int)(((uint64_t)kk[q] >> sh) & 255)], 1);
+      if (base + q * kWave + l < hi)
+        atomicAdd(&h[(int)(((uint64_t)kk[q] >> sh) & ((1u << BITS) - 1))], 1);
   }
 }
 
@@ -213,7 +215,7 @@ __device__ __forceinline__ void radix_count(const K *ks, int lo, int hi, int sh,
 // this wave), 64 elements at a time in index order; the loads of eight
 // chunks are issued together, so waiting for them waits for the previous
 // group's stores once per eight chunks (loads and stores share one counter)
-template <typename K, typename V>
+template <typename K, typename V, int BITS = 8>
 __device__ __forceinline__ void radix_scatter(const K *ks, const V *vs, K *kd, V *vd, int lo,
                                               int hi, int sh, int *h) {
   static_assert(sizeof(K) <= 8 && sizeof(V) <= 8, "sink holds 8-byte values");
@@ -237,10 +239,10 @@ __device__ __forceinline__ void radix_scatter(const K *ks, const V *vs, K *kd, V
       const bool valid = i < hi;
       const K k = kk[q];
       const V v = vv[q];
-      const int d = (int)(((uint64_t)k >> sh) & 255);
+      const int d = (int)(((uint64_t)k >> sh) & ((1u << BITS) - 1));
       uint64_t peers = __ballot(valid);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < BITS; ++b) {
         const uint64_t bm = __ballot(valid && ((d >> b) & 1));
         peers &= ((d >> b) & 1) ? bm : ~bm;
       }

@@ -1130,6 +1130,69 @@ __device__ __forceinline__ bool team_radix_sort(K *ka, V *va, K *kb, V *vb, int 
   return in_a;
 }
 
+// The same stable LSD sort with 11-bit digits, for sorts above the LDS-sort
+// size: fewer passes (a 22-bit label word in two instead of three, a 64-bit
+// weight in six instead of eight), the 2,048-bucket histograms of the eight
+// waves (64 KB) in the LDS of the in-LDS sort, idle at these sizes.  Bucket
+// b of share w starts after every smaller bucket and after bucket b of the
+// shares before w, as above.  shifts[] gives the low bit of each digit.
+constexpr int kWideBits = 11;
+constexpr int kWideBuckets = 1 << kWideBits;
+template <typename K, typename V>
+__device__ __forceinline__ bool team_radix_sort_wide(K *ka, V *va, K *kb, V *vb, int n,
+                                                     const int *shifts, int npass, int *hl,
+                                                     int *wtot) {
+  constexpr int per = kWideBuckets / kTeamThreads;  // buckets a thread owns in the scan
+  static_assert(per * kTeamThreads == kWideBuckets, "buckets split evenly over the team");
+  const int t = threadIdx.x, l = lane(), w = t >> 6;
+  int lo, hi;
+  team_range(n, w, lo, hi);
+  bool in_a = true;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int sh = shifts[pass];
+    K *ks = in_a ? ka : kb;
+    V *vs = in_a ? va : vb;
+    int *hw = hl + w * kWideBuckets;
+    for (int b = l; b < kWideBuckets; b += kWave) hw[b] = 0;
+    fence_wave_local();
+    if (lo < hi) radix_count<K, kWideBits>(ks, lo, hi, sh, hw);
+    __syncthreads();
+    // thread t owns buckets [per t, per t + per): its totals over the shares,
+    // then an exclusive scan of the per-thread totals over the team
+    int c[per][kTeamWaves], tot = 0;
+#pragma unroll
+    for (int e = 0; e < per; ++e)
+#pragma unroll
+      for (int q = 0; q < kTeamWaves; ++q) {
+        c[e][q] = hl[q * kWideBuckets + per * t + e];
+        tot += c[e][q];
+      }
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (l >= o) incl += y;
+    }
+    if (l == kWave - 1) wtot[w] = incl;
+    __syncthreads();
+    int run = incl - tot;
+    for (int q = 0; q < w; ++q) run += wtot[q];
+#pragma unroll
+    for (int e = 0; e < per; ++e)
+#pragma unroll
+      for (int q = 0; q < kTeamWaves; ++q) {
+        hl[q * kWideBuckets + per * t + e] = run;
+        run += c[e][q];
+      }
+    __syncthreads();
+    if (lo < hi)
+      radix_scatter<K, V, kWideBits>(ks, vs, in_a ? kb : ka, in_a ? vb : va, lo, hi, sh, hw);
+    __syncthreads();
+    in_a = !in_a;
+  }
+  return in_a;
+}
+
 // Rank sort by the team for at most kTeamRankMax entries: the keys are staged
 // in LDS (lk), and each thread counts, for each of its entries, the keys
 // below it -- or equal to it at a smaller index, which makes the result the
@@ -1174,12 +1237,15 @@ struct TeamSortLds {
   uint64_t k[2][kTeamLdsSort];
   uint64_t v[2][kTeamLdsSort];
 };
+static_assert(kTeamWaves * kWideBuckets * sizeof(int) <= sizeof(TeamSortLds),
+              "the wide histograms live in the in-LDS sort's buffers");
 // The team's stable sort of the pairs (ka, va) of n entries, with the
 // buffers (kb, vb) beside them, all in global memory; the key bytes are given
-// as for team_radix_sort.  Returns true when the result is in (ka, va),
-// false when it is in (kb, vb).
+// as for team_radix_sort, and `bits` is the number of bits the key uses (per
+// word when half > 0).  Returns true when the result is in (ka, va), false
+// when it is in (kb, vb).
 __device__ __forceinline__ bool team_sort_pairs(uint64_t *ka, uint64_t *va, uint64_t *kb,
-                                                uint64_t *vb, int n, int npass, int half,
+                                                uint64_t *vb, int n, int npass, int half, int bits,
                                                 int (*hist)[256], int *wtot, uint64_t *lk,
                                                 TeamSortLds &ls) {
   const int t = threadIdx.x;
@@ -1187,7 +1253,14 @@ __device__ __forceinline__ bool team_sort_pairs(uint64_t *ka, uint64_t *va, uint
     team_rank_sort(ka, va, kb, vb, n, lk);
     return false;
   }
-  if (n > kTeamLdsSort) return team_radix_sort<uint64_t, uint64_t>(ka, va, kb, vb, n, npass, half, hist, wtot);
+  if (n > kTeamLdsSort) {
+    int shifts[12], np = 0;
+    for (int b = 0; b < bits; b += kWideBits) shifts[np++] = b;
+    if (half > 0)
+      for (int b = 0; b < bits; b += kWideBits) shifts[np++] = 32 + b;
+    return team_radix_sort_wide<uint64_t, uint64_t>(ka, va, kb, vb, n, shifts, np, (int *)&ls,
+                                                    wtot);
+  }
   for (int i = t; i < n; i += kTeamThreads) {
     ls.k[0][i] = ka[i];
     ls.v[0][i] = va[i];
@@ -1282,7 +1355,7 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
     const int nb = 32 - __clz(a.ntot + 1);
     const int half = (nb + 7) / 8;
     const bool in_a = team_sort_pairs(keyA, (uint64_t *)wA, keyB, (uint64_t *)wB, g, 2 * half, half,
-                                      hist, wtot, (uint64_t *)coarse, ls);
+                                      nb, hist, wtot, (uint64_t *)coarse, ls);
     if (!in_a) {  // sorted data in the B buffers: swap names
       uint64_t *tk = keyA;
       keyA = keyB;
@@ -1333,7 +1406,8 @@ __device__ __forceinline__ bool team_pivot(const ElimArgs &a, Worker &wk, int32_
       vx[i] = (uint64_t)(uint32_t)mu[i];
     }
     __syncthreads();
-    const bool in_x = team_sort_pairs(kx, vx, ky, vy, d, 8, 0, hist, wtot, (uint64_t *)coarse, ls);
+    const bool in_x = team_sort_pairs(kx, vx, ky, vy, d, 8, 0, 64, hist, wtot, (uint64_t *)coarse,
+                                      ls);
     const uint64_t *kr = in_x ? kx : ky, *vr = in_x ? vx : vy;
     for (int i = t; i < d; i += kTeamThreads) {
       sw[i] = bitsd(kr[i]);
