@@ -249,8 +249,19 @@ __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
       key = y > key ? y : key;
     }
     const int32_t at = __builtin_amdgcn_readfirstlane(DESC ? -key : key);
+    bool single = false;
+    if constexpr (M == 1) {
+      // a long row's partials: when the polled one is the only entry the
+      // wave still waits for, its bits need no reload
+      bool other = false;
+#pragma unroll
+      for (int j = 0; j < CC; ++j)
+        other = other || (cnt > 0 && v[0][j] == B::kPending && ci[0] * CC + j != at);
+      single = !__ballot(other);
+    }
     PollBackoff bo;
-    while (load_bits(vec + at) == B::kPending) {
+    typename B::U pv;
+    while ((pv = load_bits(vec + at)) == B::kPending) {
       if (__ballot(w.expired())) {
 #pragma unroll
         for (int u = 0; u < M; ++u)
@@ -260,6 +271,14 @@ __device__ __forceinline__ void wait_ready(const T *vec, const int32_t (&ci)[M],
         return;
       }
       bo.pause();
+    }
+    if constexpr (M == 1) {
+      if (single) {
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+          v[0][j] = (cnt > 0 && v[0][j] == B::kPending) ? pv : v[0][j];
+        return;
+      }
     }
     reload();
   }
