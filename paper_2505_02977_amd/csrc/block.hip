@@ -68,7 +68,11 @@ __global__ __launch_bounds__(kBRedT) void k_binit(int64_t n, int nc, int gshift,
   write_partials(acc, sh, gshift, nc, partial);
 }
 
-// q = A p, partial p.q
+// q = A p, partial p.q.  The G lanes of a row load up to G of its entries
+// (index and value) together, share them by shuffles, and issue the gathers
+// of p for eight entries before adding any: the additions keep entry order
+// (a left fold per column), and the gathers no longer wait one by one.
+constexpr int kBSpmvBatch = 8;
 __global__ __launch_bounds__(kBRedT) void k_bspmv_dot(int64_t n, int nc, int gshift,
                                                       const int64_t *__restrict__ rowptr,
                                                       const int32_t *__restrict__ col,
@@ -78,15 +82,36 @@ __global__ __launch_bounds__(kBRedT) void k_bspmv_dot(int64_t n, int nc, int gsh
   __shared__ double sh[kBRedT];
   if (*skip) return;
   RowIter it(gshift);
+  const int G = 1 << gshift;
+  const bool colv = it.j < nc;
   double acc = 0.0;
-  if (it.j < nc)
-    for (int64_t i = it.row; i < n; i += it.stride) {
-      double s = 0.0;
-      const int64_t e1 = rowptr[i + 1];
-      for (int64_t k = rowptr[i]; k < e1; ++k) s = s + val[k] * p[(int64_t)col[k] * nc + it.j];
+  for (int64_t i = it.row; i < n; i += it.stride) {
+    double s = 0.0;
+    const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+    for (int64_t b = e0; b < e1; b += G) {
+      const int64_t kk = b + it.j;
+      const int32_t cl = kk < e1 ? col[kk] : 0;
+      const double vl = kk < e1 ? val[kk] : 0.0;
+      const int m = e1 - b < G ? (int)(e1 - b) : G;
+      for (int t0 = 0; t0 < m; t0 += kBSpmvBatch) {
+        double vv[kBSpmvBatch], pv[kBSpmvBatch];
+#pragma unroll
+        for (int u = 0; u < kBSpmvBatch; ++u) {
+          const int t = t0 + u < G ? t0 + u : G - 1;
+          const int c = __shfl(cl, t, G);
+          vv[u] = __shfl(vl, t, G);
+          pv[u] = (t0 + u < m && colv) ? p[(int64_t)c * nc + it.j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBSpmvBatch; ++u)
+          if (t0 + u < m) s = s + vv[u] * pv[u];
+      }
+    }
+    if (colv) {
       q[i * nc + it.j] = s;
       acc = acc + p[i * nc + it.j] * s;
     }
+  }
   write_partials(acc, sh, gshift, nc, partial);
 }
 

@@ -21,6 +21,7 @@ namespace parac {
 constexpr int kST = 256;   // threads of a PCG workgroup
 constexpr int kSG = 8;     // lanes per SpMV row
 constexpr int kSRPW = kWave / kSG;
+constexpr int kSpmvBatch = 8;  // entries per lane whose loads are issued together
 
 int slot_blocks(int64_t n) {
   const int64_t b = (n + 2047) / 2048;
@@ -92,8 +93,24 @@ __global__ __launch_bounds__(kST) void k_sspmv(const PcgSlot *S, const int32_t *
     const int64_t i = r0 + grp;
     double t = 0.0;
     if (i < s.n) {
+      // eight of the lane's entries at a time: their indices and values,
+      // then their gathers, then the additions in entry order
       const int64_t e = s.rowptr[i + 1];
-      for (int64_t k = s.rowptr[i] + sub; k < e; k += kSG) t = t + s.val[k] * v[s.col[k]];
+      for (int64_t k0 = s.rowptr[i] + sub; k0 < e; k0 += kSG * kSpmvBatch) {
+        int32_t cc[kSpmvBatch];
+        double vv[kSpmvBatch], xv[kSpmvBatch];
+#pragma unroll
+        for (int u = 0; u < kSpmvBatch; ++u) {
+          const int64_t k = k0 + (int64_t)u * kSG;
+          cc[u] = k < e ? s.col[k] : 0;
+          vv[u] = k < e ? s.val[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSpmvBatch; ++u) xv[u] = k0 + (int64_t)u * kSG < e ? v[cc[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kSpmvBatch; ++u)
+          if (k0 + (int64_t)u * kSG < e) t = t + vv[u] * xv[u];
+      }
     }
 #pragma unroll
     for (int o = kSG / 2; o >= 1; o >>= 1) t = t + __shfl_xor(t, o, kWave);
