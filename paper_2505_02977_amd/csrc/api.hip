@@ -262,6 +262,128 @@ static void ensure_work(parac_factor_t f, int prec, hipStream_t s);
 
 // forced (host, optional): the test hook's partner offsets, forced_count
 // entries of forced_stride per pivot label
+
+// Narrow levels of a factor (NarrowDir): the longest run of final levels in
+// which every level has at most kNarrowChunks chunks of 16 entries in either
+// direction, with at most kNarrowRows positions and kNarrowLevels levels in
+// all, and at least kNarrowMinLevels levels.  Builds both directions' tables.
+static void narrow_plan(parac_factor_t F, int64_t n, int64_t depth, Scratch &tmp, hipStream_t s) {
+  F->nlev0 = depth;
+  F->np0 = (int32_t)n;
+  F->nf = NarrowDir{};
+  F->nb = NarrowDir{};
+  if (depth == 0 || n == 0) return;
+  const std::vector<int64_t> &lp = F->hlptr;
+  int64_t lc = depth;  // lowest candidate level
+  while (lc > 0 && n - lp[lc - 1] <= kNarrowRows && depth - (lc - 1) <= kNarrowLevels) --lc;
+  if (depth - lc < kNarrowMinLevels) return;
+  const int64_t pc = lp[lc], m = n - pc;
+  std::vector<int64_t> fp(m + 1), bp(m + 1);
+  chk(hipMemcpyAsync(fp.data(), F->lf_ptr + pc, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s),
+      "read");
+  chk(hipMemcpyAsync(bp.data(), F->lb_ptr + pc, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s),
+      "read");
+  chk(hipStreamSynchronize(s), "sync");
+  if (fp[m] > INT32_MAX || bp[m] > INT32_MAX) return;  // entry indices are 32-bit in the tables
+  auto chunks = [](int64_t len) { return (len + 15) / 16; };
+  int64_t lo = depth;
+  for (int64_t L = depth - 1; L >= lc; --L) {
+    int64_t cf = 0, cb = 0;
+    for (int64_t p = lp[L]; p < lp[L + 1]; ++p) {
+      cf += chunks(fp[p - pc + 1] - fp[p - pc]);
+      cb += chunks(bp[p - pc + 1] - bp[p - pc]);
+    }
+    if (cf > kNarrowChunks || cb > kNarrowChunks) break;
+    lo = L;
+  }
+  const int64_t nlev = depth - lo;
+  if (nlev < kNarrowMinLevels) return;
+  const int64_t p0 = lp[lo];
+  const int32_t P = (int32_t)(n - p0);
+  for (int dir = 0; dir < 2; ++dir) {
+    const std::vector<int64_t> &pp = dir == 0 ? fp : bp;
+    std::vector<int4> hdr;
+    std::vector<int32_t> rows(P, 0), smap, lw;
+    for (int64_t i = 0; i < nlev; ++i) {
+      const int64_t L = dir == 0 ? lo + i : depth - 1 - i;  // the direction's order
+      const int64_t a = lp[L], b = lp[L + 1];
+      const int64_t hc0 = (int64_t)smap.size() / 8;
+      // one wave per row: every row within 32 chunks, groups of 2^lg lanes
+      // (lg >= 1) that fit the workgroup
+      bool one = true;
+      int64_t lanes = 0;
+      std::vector<std::pair<int, int64_t>> grp;  // (lg, position) of rows with entries
+      for (int64_t p = a; p < b && one; ++p) {
+        const int64_t k = chunks(pp[p - pc + 1] - pp[p - pc]);
+        if (k > 32) one = false;
+        if (k == 0) continue;
+        int lg = 1;
+        while ((1 << lg) < 2 * k) ++lg;
+        lanes += 1 << lg;
+        grp.push_back({lg, p});
+      }
+      if (one && lanes > kNarrowThreads) one = false;
+      if (one) {
+        // largest groups first: each lands aligned to its size, inside a wave
+        std::stable_sort(grp.begin(), grp.end(),
+                         [](const std::pair<int, int64_t> &x, const std::pair<int, int64_t> &y) {
+                           return x.first > y.first;
+                         });
+        for (const auto &g : grp) {
+          const int64_t p = g.second, e0 = pp[p - pc], e1 = pp[p - pc + 1];
+          const int G = 1 << g.first;
+          for (int t = 0; t < G; ++t) {
+            lw.push_back(t == 0 ? (int32_t)(((p - p0) << 8) | (g.first << 1) | 1) : g.first << 1);
+            for (int u = 0; u < 8; ++u) {
+              const int64_t e = e0 + 8 * t + u;
+              smap.push_back(e < e1 ? (int32_t)e : -1);
+            }
+          }
+        }
+        hdr.push_back(make_int4((int)hc0, (int)lanes, (int)(a - p0), (int)(b - a) | kNarrowOneWave));
+        continue;
+      }
+      int32_t c = 0;
+      for (int64_t p = a; p < b; ++p) {
+        const int64_t e0 = pp[p - pc], e1 = pp[p - pc + 1];
+        const int32_t k = (int32_t)chunks(e1 - e0);
+        rows[p - p0] = (c << 16) | k;
+        for (int64_t e = e0; e < e0 + 16 * (int64_t)k; ++e) smap.push_back(e < e1 ? (int32_t)e : -1);
+        c += k;
+      }
+      lw.resize(smap.size() / 8, 0);
+      hdr.push_back(make_int4((int)hc0, 2 * c, (int)(a - p0), (int)(b - a)));
+    }
+    // at least one half-chunk of slots: threads without one load slot 0
+    if (smap.empty()) smap.assign(8, -1);
+    lw.resize(smap.size() / 8, 0);
+    NarrowDir &N = dir == 0 ? F->nf : F->nb;
+    int4 *dh = tmp.alloc<int4>(nlev, "narrow levels");
+    int32_t *dr = tmp.alloc<int32_t>(P, "narrow rows");
+    const int64_t ns = (int64_t)smap.size();
+    int32_t *dm = tmp.alloc<int32_t>(ns, "narrow slots");
+    int32_t *dw = tmp.alloc<int32_t>(ns / 8, "narrow lane words");
+    chk(hipMemcpyAsync(dw, lw.data(), (ns / 8) * sizeof(int32_t), hipMemcpyHostToDevice, s),
+        "upload");
+    int16_t *dn = tmp.alloc<int16_t>(ns, "narrow inputs");
+    chk(hipMemcpyAsync(dh, hdr.data(), nlev * sizeof(int4), hipMemcpyHostToDevice, s), "upload");
+    chk(hipMemcpyAsync(dr, rows.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s), "upload");
+    chk(hipMemcpyAsync(dm, smap.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s), "upload");
+    chk(launch_narrow_index(ns, dm, dir == 0 ? F->lf_idx : F->lb_idx, (int32_t)p0, dn, s),
+        "narrow index");
+    chk(hipStreamSynchronize(s), "sync");  // the host tables go out of scope
+    N.hdr = dh;
+    N.rows = dr;
+    N.lw = dw;
+    N.smap = dm;
+    N.nidx = dn;
+    N.nslots = ns;
+    N.nlev = (int32_t)nlev;
+  }
+  F->nlev0 = lo;
+  F->np0 = (int32_t)p0;
+}
+
 static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o, hipStream_t s,
                                   const int32_t *forced = nullptr, int32_t forced_stride = 0,
                                   int64_t forced_count = 0) {
@@ -642,6 +764,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
     chk(hipMemcpyAsync(F->hlqb.data(), lqb, (depth + 1) * sizeof(int64_t),
                        hipMemcpyDeviceToHost, s),
         "read");
+    narrow_plan(F, n, depth, tmp, s);
     // per direction: the positions of each level listed by row class, then
     // the units of the dependency-driven sweep cut from these lists
     const int64_t ncl = (int64_t)kRowClasses * depth;
@@ -681,6 +804,12 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
       const int64_t nu = read1(uoff + n, s), nch = read1(coff + n, s);
       if (nu > INT32_MAX || nch > INT32_MAX)
         throw Err{PARAC_EINVAL, "factor too large for the sweep's 32-bit unit tables"};
+      // the sweeps leave the narrow levels to k_narrow: forward the units of
+      // the levels below, backward those after the narrow levels' units
+      if (dir == 0)
+        F->nwide_f = F->nf.nlev ? (int32_t)read1(uoff + F->hlptr[F->nlev0], s) : (int32_t)nu;
+      else
+        F->nskip_b = F->nb.nlev ? (int32_t)read1(uoff + (n - F->hlptr[F->nlev0]), s) : 0;
       int4 *units = tmp.alloc<int4>(nu, "sweep units");
       chk(launch_unit_write(n, depth, F->lptr, cbase, list, ptr, uoff, coff, units, dir == 1,
                             s),
@@ -751,7 +880,10 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
                   (void *)F->src, (void *)F->flist, (void *)F->blist, (void *)F->zero,
                   (void *)F->task_f, (void *)F->task_b, (void *)F->ctr, (void *)F->serr,
                   (void *)F->lf_ptr, (void *)F->lf_idx, (void *)F->lf_val, (void *)F->lf_val32,
-                  (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32})
+                  (void *)F->lb_ptr, (void *)F->lb_idx, (void *)F->lb_val, (void *)F->lb_val32,
+                  (void *)F->nf.hdr, (void *)F->nf.rows, (void *)F->nf.lw, (void *)F->nf.smap,
+                  (void *)F->nf.nidx, (void *)F->nb.hdr, (void *)F->nb.rows, (void *)F->nb.lw,
+                  (void *)F->nb.smap, (void *)F->nb.nidx})
     if (p) F->bytes += tmp.keep(p, F->owned);
   // the sweeps' work vectors, so that solving with the factor needs no
   // further device allocation
@@ -793,7 +925,23 @@ static SolveArgs solve_args(parac_factor_t f, const int *skip) {
   a.ntask_b = f->ntask_b;
   a.err = f->serr;
   a.timeout_ticks = (uint64_t)(kSweepTimeoutS * 1000.0 * (double)wall_khz());
+  a.nf = f->nf;
+  a.nb = f->nb;
+  const bool narrow = f->nf.nlev > 0;
+  a.np0 = narrow ? f->np0 : (int32_t)f->n;
+  a.nwide_f = narrow ? f->nwide_f : f->ntask_f;
+  a.nskip_b = narrow ? f->nskip_b : 0;
   return a;
+}
+
+// the sweeps take every level (slots of several columns, or work vectors
+// other than the factor's own: no narrow-level kernel for them)
+static void wide_only(SolveArgs &a) {
+  a.nf = NarrowDir{};
+  a.nb = NarrowDir{};
+  a.np0 = (int32_t)a.n;
+  a.nwide_f = a.ntask_f;
+  a.nskip_b = 0;
 }
 
 // label-space work vectors of the two triangular solves
@@ -819,16 +967,20 @@ static void ensure_work(parac_factor_t f, int prec, hipStream_t s) {
   void **py = mixed ? &f->wy32 : &f->wy64;
   void **px = mixed ? &f->wx32 : &f->wx64;
   void **pc = mixed ? &f->cs32 : &f->cs64;
+  void **pv = mixed ? &f->npv32 : &f->npv64;
   if (*py) return;
   const size_t el = mixed ? 4 : 8;
   const int64_t m = std::max<int64_t>(f->ntot, 1), c = std::max<int64_t>(f->ncs, 1);
+  const int64_t nv = std::max<int64_t>(f->nf.nslots + f->nb.nslots, 1);
   chk(dev_alloc(py, m * el), "work vector");
   f->owned.push_back(*py);
   chk(dev_alloc(px, m * el), "work vector");
   f->owned.push_back(*px);
   chk(dev_alloc(pc, c * el), "chunk sums");
   f->owned.push_back(*pc);
-  f->bytes += (int64_t)((2 * m + c) * el);
+  chk(dev_alloc(pv, nv * el), "narrow products");
+  f->owned.push_back(*pv);
+  f->bytes += (int64_t)((2 * m + c + nv) * el);
   reset_work(f, prec, s);
 }
 
@@ -1158,6 +1310,9 @@ static void build_apply_tables(Batch &bt, const std::vector<ApplySlot> &as,
   B.aslots = das;
   B.wgmap = dmap;
   B.nwg = (int)map.size();
+  B.nslots_max = 0;
+  for (const ApplySlot &a : as)
+    if (a.a.nf.nlev > 0) B.nslots_max = std::max(B.nslots_max, a.a.nf.nslots + a.a.nb.nslots);
 }
 
 // lay out the workgroups of a batch and upload its tables; partial must
@@ -1186,6 +1341,7 @@ static void build_batch(Batch &bt, const std::vector<SlotView> &v, int prec, dou
     as[k].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
     as[k].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
     as[k].cs = prec == PARAC_PREC_MIXED ? f->cs32 : f->cs64;
+    as[k].pv = prec == PARAC_PREC_MIXED ? f->npv32 : f->npv64;
     as[k].ctr = f->ctr;
     as[k].z = ps[k].z;
     as[k].ncols = 1;
@@ -1226,6 +1382,7 @@ static void apply_one(parac_factor_t f, const double *r, double *z, int prec, hi
   as[0].y = prec == PARAC_PREC_MIXED ? f->wy32 : f->wy64;
   as[0].x = prec == PARAC_PREC_MIXED ? f->wx32 : f->wx64;
   as[0].cs = prec == PARAC_PREC_MIXED ? f->cs32 : f->cs64;
+  as[0].pv = prec == PARAC_PREC_MIXED ? f->npv32 : f->npv64;
   as[0].ctr = f->ctr;
   as[0].z = z;
   as[0].ncols = 1;
@@ -1256,6 +1413,8 @@ static void build_cols(Batch &bt, parac_factor_t f, int nc, const parac_block_sh
   for (int j = 0; j < ns; ++j) {
     const int c0 = j * cc;
     as[j].a = solve_args(f, skip ? skip + (int64_t)c0 * skip_stride : f->zero);
+    wide_only(as[j].a);
+    as[j].pv = nullptr;
     as[j].ldr = ldr;
     as[j].ldz = ldz;
     as[j].r = r + c0;

@@ -152,6 +152,38 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // The solves work in position space: position p is the p-th row in level
 // order (rows of one level are contiguous), the work vectors are indexed by
 // position, and the level-ordered copies of F store positions as indices.
+// Narrow levels.  The last levels of a factor often hold few rows each; a
+// sweep spends a publish-to-detect hop per level there.  One workgroup per
+// slot solves them instead, with the level's values in LDS and a barrier per
+// level.  Per direction, in the order the direction solves the levels:
+//   hdr[i]  = (first half-chunk, half-chunks, first row - np0, rows)
+//   rows[p] = (first chunk of the level << 16) | chunks, p = position - np0
+// A row of m entries has ceil(m / 16) chunks of 16 entries, each cut in two
+// half-chunks of 8 entry slots (slots past the row's end are padding).
+//   smap[s] = the slot's entry in the level-ordered copy, -1 for padding
+//   nidx[s] = position - np0 of an entry inside the narrow range, else -1
+// A level whose rows all have at most 32 chunks and fit the workgroup's
+// lanes in groups of a power of two (two lanes per chunk, rounded up) is a
+// one-wave-per-row level (bit 30 of hdr.w): each row's half-chunks lie in one
+// aligned lane group, lane word
+//   lw[h] = (row position - np0) << 8 | log2(group lanes) << 1 | first lane
+// and the row is summed inside its wave.  Other levels list each row's
+// half-chunks in position order, and rows[] gives their chunk ranges.
+constexpr int kNarrowOneWave = 1 << 30;
+struct NarrowDir {
+  const int4 *hdr;
+  const int32_t *rows;
+  const int32_t *lw;
+  const int32_t *smap;
+  const int16_t *nidx;
+  int64_t nslots;  // entry slots (8 per half-chunk)
+  int32_t nlev;
+};
+constexpr int kNarrowThreads = 1024;     // one workgroup of 16 waves
+constexpr int kNarrowChunks = 512;       // chunks of one narrow level, at most
+constexpr int kNarrowRows = 8192;        // narrow positions, at most
+constexpr int kNarrowLevels = 2048;      // narrow levels, at most
+constexpr int kNarrowMinLevels = 16;     // fewer: not worth the extra launches
 struct SolveArgs {
   int64_t n;             // solved rows (labels 0..n-1)
   const int64_t *lptr;   // position prefix over levels [depth+1]
@@ -169,6 +201,12 @@ struct SolveArgs {
   int32_t ntask_f, ntask_b;
   int *err;                // error word of the sweeps (watchdog)
   uint64_t timeout_ticks;  // watchdog of one sweep, wall-clock ticks
+  // narrow levels (positions >= np0, solved by one workgroup per slot, see
+  // NarrowDir); the sweeps then take forward units [0, nwide_f) and backward
+  // units [nskip_b, ntask_b).  No narrow levels: np0 = n, nwide_f = ntask_f,
+  // nskip_b = 0, nf.nlev = nb.nlev = 0.
+  int32_t np0, nwide_f, nskip_b;
+  NarrowDir nf, nb;
 };
 // the factor values of an apply precision
 template <typename T> struct FactorVals;
@@ -226,6 +264,8 @@ hipError_t launch_class_count(int64_t n, const int32_t *order, const int32_t *le
 hipError_t launch_class_place(int64_t n, const int32_t *order, const int32_t *lev,
                               const int64_t *ptr, const int64_t *cbase, int32_t *ccursor,
                               int32_t *list, hipStream_t s);
+hipError_t launch_narrow_index(int64_t ns, const int32_t *smap, const int32_t *idx, int32_t np0,
+                               int16_t *nidx, hipStream_t s);
 hipError_t launch_level_offsets(int64_t depth, const int64_t *lptr, const int64_t *lf_ptr,
                                 const int64_t *lb_ptr, int64_t *lqf, int64_t *lqb, hipStream_t s);
 hipError_t launch_position_maps(int64_t n, const int32_t *order, const int32_t *iperm,
@@ -284,6 +324,7 @@ struct ApplySlot {
   void *cs;     // block partial sums of long rows (precision of the apply), all pending
   int32_t *ctr;  // ticket counters of the forward and backward sweeps
   double *z;
+  void *pv;        // narrow entry slots' products (precision of the apply)
   int32_t ncols;  // valid columns of the slot (at most the launch's columns per slot)
   // the slot is skipped when all of a.skip[j * skip_stride], j < skip_n, are set
   int32_t skip_n, skip_stride;
@@ -298,6 +339,7 @@ struct SlotBatch {
   const int32_t *wgmap = nullptr;  // device [nwg]
   int nwg = 0;
   int cc = 1;  // columns per sweep slot (1, 2, 4; 8 with the FP32 apply)
+  int64_t nslots_max = 0;  // narrow entry slots of the batch's largest system (0: none)
 };
 int slot_blocks(int64_t n);
 hipError_t slots_init(const SlotBatch &B, hipStream_t s);
@@ -340,6 +382,11 @@ struct parac_factor_s {
   int4 *task_f = nullptr, *task_b = nullptr;
   int32_t ntask_f = 0, ntask_b = 0;
   int64_t ncs = 0;
+  // narrow levels (levels >= nlev0 when nf.nlev > 0) and the sweeps' cut
+  int64_t nlev0 = 0;
+  int32_t np0 = 0, nwide_f = 0, nskip_b = 0;
+  parac::NarrowDir nf{}, nb{};
+  void *npv64 = nullptr, *npv32 = nullptr;  // products of the narrow slots, per precision
   int32_t *ctr = nullptr;  // sweep ticket counters [2]
   int *serr = nullptr;     // sweep error word
   // solve work vectors (position space) and chunk sums per precision

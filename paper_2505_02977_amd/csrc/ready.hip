@@ -456,8 +456,10 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
   if (skip) return;
   const int l = lane();
   const Sweep<T, BWD, CC> S(q);
-  const int4 *units = BWD ? q.a.task_b : q.a.task_f;
-  const int nt = BWD ? q.a.ntask_b : q.a.ntask_f;
+  // the narrow levels (the last forward, the first backward) are left to
+  // k_narrow
+  const int4 *units = BWD ? q.a.task_b + q.a.nskip_b : q.a.task_f;
+  const int nt = BWD ? q.a.ntask_b - q.a.nskip_b : q.a.nwide_f;
   int32_t *ctr = q.ctr + (BWD ? 1 : 0);
   T *cs = (T *)q.cs;
   Watch w{now_ticks() + q.a.timeout_ticks, q.a.err, false, 0};
@@ -465,10 +467,11 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
     int t = 0;
     if (l == 0) t = fetch_add(ctr, 1);
     t = first_lane_i32(__shfl(t, 0, kWave));
-    if (t >= nt || __ballot(w.dead)) break;
-    // the first unit of a sweep clears the other sweep's counter (that sweep
-    // is finished, and the next one starts after this launch)
+    // the first ticket of a sweep clears the other sweep's counter (that
+    // sweep is finished, and the next one starts after this launch), also
+    // when this sweep has no unit
     if (t == 0 && l == 0) st_relaxed(q.ctr + (BWD ? 0 : 1), 0);
+    if (t >= nt || __ballot(w.dead)) break;
     const int4 u = units[t];
     const int kind = first_lane_i32(u.x);
     if (kind == kUnitGroup1) {
@@ -529,11 +532,257 @@ __global__ __launch_bounds__(kReadyThreads) void k_ready(const ApplySlot *AS,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Narrow levels: one workgroup per slot solves them level by level, with
+// every narrow position's value in LDS and a barrier between levels, in
+// place of a publish-to-detect hop through memory per level.  The forward
+// narrow levels come after every other level, so they start once the
+// forward sweep has ended; the backward ones come first, and the backward
+// sweep starts once they are done.  Launch boundaries order all of it: no
+// kernel here waits on another.
+//
+// The arithmetic is the sweeps' to the bit.  A row's sum is fixed by its
+// entry order alone: products rounded once; per chunk of 16 entries a
+// balanced tree; over the chunks of a row of at most 1,024 entries a
+// balanced tree (padding with -0.0, the exact identity, to the 4, 16 or 64
+// lanes of its group changes nothing); a longer row's blocks of 64 chunks as
+// balanced trees, then added to -0.0 in batches of 64.  Here a thread takes
+// half a chunk (a tree of 8), the two halves of a chunk are added by a lane
+// move, and a wave adds the chunks of a row by the same butterfly.
+// ---------------------------------------------------------------------------
+
+// Products of the narrow entry slots, ahead of the narrow kernels: forward,
+// an entry whose input lies before the narrow range (already solved) gets
+// its product, an inside entry its factor value; backward (every input is
+// inside) the factor value; padding -0.0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_narrow_prep(const ApplySlot *AS) {
+  const ApplySlot &q = AS[blockIdx.y];
+  const NarrowDir &F = q.a.nf, &Bw = q.a.nb;
+  if (F.nlev == 0) return;
+  bool skip = true;
+  for (int j = 0; j < q.skip_n; ++j) skip = skip && q.a.skip[(int64_t)j * q.skip_stride] != 0;
+  if (skip) return;
+  const int32_t *fidx = q.a.lf_idx;
+  const T *ffv = FactorVals<T>::fwd(q.a), *bfv = FactorVals<T>::bwd(q.a);
+  const T *y = (const T *)q.y;
+  T *pv = (T *)q.pv;
+  const int64_t total = F.nslots + Bw.nslots;
+  for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < total;
+       sl += (int64_t)gridDim.x * blockDim.x) {
+    T v = (T)-0.0;
+    if (sl < F.nslots) {
+      const int32_t e = F.smap[sl];
+      if (e >= 0) {
+        const int32_t c = fidx[e];
+        v = c < q.a.np0 ? ffv[e] * y[c] : ffv[e];
+      }
+    } else {
+      const int32_t e = Bw.smap[sl - F.nslots];
+      if (e >= 0) v = bfv[e];
+    }
+    pv[sl] = v;
+  }
+}
+
+// balanced sum of 8 products (the first or second half of tree16)
+template <typename T>
+__device__ __forceinline__ T tree8(const T (&p)[8]) {
+  const T a0 = p[0] + p[1], a1 = p[2] + p[3], a2 = p[4] + p[5], a3 = p[6] + p[7];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// a global-memory view of a pointer: loads through it are global loads,
+// counted by vmcnt alone (a flat load would also hold every LDS wait)
+template <typename T>
+using GlobalPtr = const __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ GlobalPtr<T> global_view(const T *p) {
+  return (GlobalPtr<T>)p;
+}
+
+// a narrow row's value published as Sweep::finish does (single column),
+// through global-memory stores: a flat store would also hold every LDS wait
+template <typename T, bool BWD>
+__device__ __forceinline__ void narrow_finish(const ApplySlot &q, int64_t pos, T v) {
+  using B = Bits<T>;
+  using U = typename B::U;
+  using GU = __attribute__((address_space(1))) U *;
+  U u = B::of(v);
+  if (u == B::kPending) u = B::kQuietNaN;
+  T *out = (T *)(BWD ? q.x : q.y), *other = (T *)(BWD ? q.y : q.x);
+  __hip_atomic_store((GU)(out + pos), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((GU)(other + pos), B::kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (BWD) {
+    using GD = __attribute__((address_space(1))) double *;
+    *(GD)(q.z + (int64_t)q.a.src[pos] * q.ldz) = (double)v;
+  }
+}
+
+// one half-chunk's slots of a level, loaded ahead of its level
+// (the eight 16-bit inputs stay packed in four words until their level:
+// split at the load, they would be waited for there)
+template <typename T>
+struct HalfChunk {
+  int32_t lw;  // lane word (levels of one wave per row)
+  uint32_t ni[4];
+  T pv[8];
+};
+
+// the 64-lane butterfly's sum: rows of 16 lanes by lane moves, then the four
+// row sums in the butterfly's pairs, read as uniform values
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v = group_reduce<T, 16>(v);
+  return (readlane_t(v, 0) + readlane_t(v, 16)) + (readlane_t(v, 32) + readlane_t(v, 48));
+}
+
+template <typename T, bool BWD, int D>
+__global__ __launch_bounds__(kNarrowThreads) void k_narrow(const ApplySlot *AS) {
+  const ApplySlot q = AS[blockIdx.x];
+  const NarrowDir N = BWD ? q.a.nb : q.a.nf;
+  if (N.nlev == 0) return;
+  bool skip = true;
+  for (int j = 0; j < q.skip_n; ++j) skip = skip && q.a.skip[(int64_t)j * q.skip_stride] != 0;
+  if (skip) return;
+  __shared__ T xs[kNarrowRows];          // values of the narrow positions
+  __shared__ int32_t rows[kNarrowRows];  // (first chunk << 16) | chunks
+  __shared__ int4 hdr[kNarrowLevels];
+  __shared__ T cp[kNarrowChunks];        // chunk sums of the current level
+  const Sweep<T, BWD, 1> S(q);
+  const int tid = threadIdx.x, l = tid & (kWave - 1), wv = tid / kWave;
+  const int np0 = q.a.np0, P = (int)(q.a.n - np0);
+  // start values (P r forward, D^+ y backward), row and level tables
+  for (int p = tid; p < P; p += kNarrowThreads) {
+    T s0[1];
+    S.start(np0 + p, s0);
+    xs[p] = s0[0];
+    rows[p] = N.rows[p];
+  }
+  for (int i = tid; i < N.nlev; i += kNarrowThreads) hdr[i] = N.hdr[i];
+  __syncthreads();
+  const GlobalPtr<T> pv = global_view((const T *)q.pv + (BWD ? q.a.nf.nslots : 0));
+  const GlobalPtr<uint32_t> nidx = global_view((const uint32_t *)N.nidx);
+  const GlobalPtr<int32_t> lwp = global_view(N.lw);
+  // Every thread issues the same loads for every level (slot 0 where it has
+  // no half-chunk or the level is past the last), so the number of loads
+  // issued after a buffer's is known where the buffer is used, and a level
+  // waits only for its own buffer.  Nothing in the level loop stores to
+  // global memory: the rows are published after the last level.
+  auto load = [&](int i, HalfChunk<T> &b) {
+    int64_t s0 = 0;
+    if (i < N.nlev) {
+      const int4 h = hdr[i];
+      if (tid < h.y) s0 = ((int64_t)h.x + tid) * 8;
+    }
+    b.lw = lwp[s0 / 8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) b.ni[u] = nidx[s0 / 2 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b.pv[u] = pv[s0 + u];
+  };
+  auto level = [&](int i, const HalfChunk<T> &b) {
+    const int4 h = hdr[i];
+    const bool one = (h.w & kNarrowOneWave) != 0;
+    const int lw = tid < h.y ? b.lw : 0;
+    const int pr1 = lw >> 8;
+    const T x1 = (lw & 1) ? xs[pr1] : (T)0;  // a group's first lane: its row's start
+    T hs = (T)-0.0;
+    if (tid < h.y) {
+      T p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = (int16_t)(b.ni[u / 2] >> (16 * (u % 2)));
+        const T x = xs[c >= 0 ? c : 0];
+        p[u] = c >= 0 ? b.pv[u] * x : b.pv[u];
+      }
+      hs = tree8(p);
+    }
+    if (one) {
+      // the row's group of 2^lg lanes: the butterfly's stages below lg
+      const int lg = (lw >> 1) & 7;
+      T v = hs, t;
+      t = dpp_t<kDppXor1>(v);
+      v = lg > 0 ? v + t : v;
+      t = dpp_t<kDppXor2>(v);
+      v = lg > 1 ? v + t : v;
+      t = dpp_t<kDppHalfMirror>(v);
+      v = lg > 2 ? v + t : v;
+      t = dpp_t<kDppMirror>(v);
+      v = lg > 3 ? v + t : v;
+      t = shfl_xor_t(v, 16);
+      v = lg > 4 ? v + t : v;
+      t = shfl_xor_t(v, 32);
+      v = lg > 5 ? v + t : v;
+      if (lw & 1) xs[pr1] = x1 - v;
+      __syncthreads();
+      return;
+    }
+    const T c = hs + dpp_t<kDppXor1>(hs);  // first half + second half
+    if (tid < h.y && (tid & 1) == 0) cp[tid >> 1] = c;
+    __syncthreads();
+    for (int r = wv; r < (h.w & ~kNarrowOneWave); r += kNarrowThreads / kWave) {
+      const int pr = h.z + r;
+      const int32_t rd = rows[pr];
+      const int c0 = rd >> 16, k = rd & 0xffff;
+      T tot;
+      if (k <= kWave) {
+        tot = wave_sum<T>(l < k ? cp[c0 + l] : (T)-0.0);
+      } else {
+        // blocks of 64 chunks, then the fold of the block sums (one batch)
+        T bl = (T)-0.0;
+        for (int b2 = 0; b2 * kWave < k; ++b2) {
+          const int m = k - b2 * kWave;
+          const T sb = wave_sum<T>(l < m ? cp[c0 + b2 * kWave + l] : (T)-0.0);
+          if (l == b2) bl = sb;
+        }
+        tot = (T)-0.0 + wave_sum<T>(bl);
+      }
+      if (l == 0 && k > 0) xs[pr] = xs[pr] - tot;
+    }
+    __syncthreads();
+  };
+  HalfChunk<T> buf[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) load(d, buf[d]);
+  const int full = N.nlev / D * D;
+  for (int i0 = 0; i0 < full; i0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      level(i0 + d, buf[d]);
+      load(i0 + d + D, buf[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (full + d < N.nlev) level(full + d, buf[d]);
+  // publish every narrow row (forward: y, and x reset; backward: x, y reset
+  // and z)
+  for (int p = tid; p < P; p += kNarrowThreads) narrow_finish<T, BWD>(q, np0 + p, xs[p]);
+}
+
+constexpr int kNarrowAhead = 3;  // levels whose slots are loaded ahead
+
 template <typename T, int CC>
 void ready_apply_t(const SlotBatch &B, hipStream_t s, hipEvent_t mid) {
   hipLaunchKernelGGL((k_ready<T, false, CC>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
                      B.wgmap);
+  const bool narrow = CC == 1 && B.nslots_max > 0;
+  if constexpr (CC == 1) {
+    if (narrow) {
+      const int64_t g = std::min<int64_t>((B.nslots_max + 255) / 256, 1024);
+      hipLaunchKernelGGL((k_narrow_prep<T>), dim3((unsigned)g, (unsigned)B.nslots), dim3(256), 0,
+                         s, B.aslots);
+      hipLaunchKernelGGL((k_narrow<T, false, kNarrowAhead>), dim3(B.nslots),
+                         dim3(kNarrowThreads), 0, s, B.aslots);
+    }
+  }
   if (mid) (void)hipEventRecord(mid, s);
+  if constexpr (CC == 1) {
+    if (narrow)
+      hipLaunchKernelGGL((k_narrow<T, true, kNarrowAhead>), dim3(B.nslots),
+                         dim3(kNarrowThreads), 0, s, B.aslots);
+  }
   hipLaunchKernelGGL((k_ready<T, true, CC>), dim3(B.nwg), dim3(kReadyThreads), 0, s, B.aslots,
                      B.wgmap);
 }

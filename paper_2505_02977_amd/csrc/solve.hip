@@ -256,6 +256,25 @@ hipError_t launch_level_offsets(int64_t depth, const int64_t *lptr, const int64_
   return hipGetLastError();
 }
 
+// narrow entry slots: the input position of an entry inside the narrow
+// range (position - np0), -1 for an input before it and for padding
+__global__ void k_narrow_index(int64_t ns, const int32_t *__restrict__ smap,
+                               const int32_t *__restrict__ idx, int32_t np0, int16_t *nidx) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= ns) return;
+  const int32_t e = smap[sl];
+  const int32_t c = e >= 0 ? idx[e] : -1;
+  nidx[sl] = (int16_t)(c >= np0 ? c - np0 : -1);
+}
+
+hipError_t launch_narrow_index(int64_t ns, const int32_t *smap, const int32_t *idx, int32_t np0,
+                               int16_t *nidx, hipStream_t s) {
+  if (ns == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_narrow_index, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, ns, smap,
+                     idx, np0, nidx);
+  return hipGetLastError();
+}
+
 hipError_t launch_position_maps(int64_t n, const int32_t *order, const int32_t *iperm,
                                 const double *D, int32_t *posof, int32_t *src, double *pdinv,
                                 float *pdinv32, hipStream_t s) {
