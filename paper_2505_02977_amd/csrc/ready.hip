@@ -710,10 +710,12 @@ __global__ __launch_bounds__(kNarrowThreads) void k_narrow(const ApplySlot *AS) 
       v = lg > 2 ? v + t : v;
       t = dpp_t<kDppMirror>(v);
       v = lg > 3 ? v + t : v;
-      t = shfl_xor_t(v, 16);
-      v = lg > 4 ? v + t : v;
-      t = shfl_xor_t(v, 32);
-      v = lg > 5 ? v + t : v;
+      // groups of 32 and 64 lanes: their rows of 16 lanes are uniform now;
+      // the pairs of row sums read as uniform values (same sums as moves)
+      const T ab = readlane_t(v, 0) + readlane_t(v, 16);
+      const T cd = readlane_t(v, 32) + readlane_t(v, 48);
+      v = lg > 4 ? (l < 32 ? ab : cd) : v;
+      v = lg > 5 ? ab + cd : v;
       if (lw & 1) xs[pr1] = x1 - v;
       __syncthreads();
       return;
