@@ -49,7 +49,7 @@ TRAFFIC_PROFILES = {
     "chung_lu_22": os.path.join(ROOT, "profiles", "hbm_traffic_chung_lu_22.md"),
     "grid3d_128": os.path.join(ROOT, "profiles", "hbm_traffic_grid3d_128.md"),
 }
-KERNEL_SOURCES = ["ready.hip", "eliminate.hip", "internal.hpp", "device.hpp"]
+KERNEL_SOURCES = ["ready.hip", "eliminate.hip", "internal.hpp", "device.hpp", "api.hip"]
 
 
 def kernel_source_hash():
@@ -61,20 +61,28 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` (e.g. "k_ready<double, true, 1>") from
-    the committed counter summary, if it was taken on this workload from the
-    current kernel sources; else None."""
+def measured_traffic(workload, kernels):
+    """HBM bytes per launch of a kernel (e.g. "k_ready<double, true, 1>"), or
+    the sum over the launches of a list of kernels, from the committed counter
+    summary, if it was taken on this workload from the current kernel sources;
+    else None."""
     import re
+    if isinstance(kernels, str):
+        kernels = [kernels]
     path = TRAFFIC_PROFILES.get(workload)
     if path is None or not os.path.exists(path):
         return None
     text = open(path).read()
     m1 = re.search(r"kernel-sources-sha256:\s*([0-9a-f]{64})", text)
-    m2 = re.search(r"hbm-bytes-per-launch %s:\s*([0-9]+)" % re.escape(kernel), text)
-    if not (m1 and m2) or m1.group(1) != kernel_source_hash():
+    if not m1 or m1.group(1) != kernel_source_hash():
         return None
-    return int(m2.group(1))
+    total = 0
+    for k in kernels:
+        m2 = re.search(r"hbm-bytes-per-launch %s:\s*([0-9]+)" % re.escape(k), text)
+        if not m2:
+            return None
+        total += int(m2.group(1))
+    return total
 
 
 def log(*a):
@@ -127,10 +135,16 @@ def roofline(info, timing, elem, workload):
     with the other kernels of the hot path beside it."""
     N, n_off = info["n"], info["nnz_off"]
     T = "double" if elem == 8 else "float"
-    kf, kb = "k_ready<%s, false, 1>" % T, "k_ready<%s, true, 1>" % T
-    fwd = rl_entry("%s (forward sweep F y = P r, one launch)" % kf,
+    # a sweep is the dependency-driven launch plus, when the factor has narrow
+    # final levels, the one-workgroup launches that solve them
+    kf = ["k_ready<%s, false, 1>" % T]
+    kb = ["k_ready<%s, true, 1>" % T]
+    if info.get("narrow_levels", 0) > 0:
+        kf += ["k_narrow_prep<%s>" % T, "k_narrow<%s, false, 3>" % T]
+        kb = ["k_narrow<%s, true, 3>" % T] + kb
+    fwd = rl_entry("forward sweep F y = P r (%s: %d launches)" % (" + ".join(kf), len(kf)),
                    fwd_bytes(n_off, N, elem), timing["fwd_ms"], measured_traffic(workload, kf))
-    bwd = rl_entry("%s (backward sweep F^T x = D^+ y, one launch)" % kb,
+    bwd = rl_entry("backward sweep F^T x = D^+ y (%s: %d launches)" % (" + ".join(kb), len(kb)),
                    bwd_bytes(n_off, N, elem), timing["bwd_ms"], measured_traffic(workload, kb))
     elim = rl_entry("k_eliminate (one factorisation, one persistent launch)",
                     elim_bytes(info["n_input_edges"], info["n_fill"], n_off, N), timing["elim_ms"],

@@ -116,6 +116,9 @@ typedef struct {
   double ms_eliminate;    /* the persistent elimination kernel              */
   double ms_finalize;     /* canonical CSC, CSR, levels, D^+, FP32 copy     */
   double ms_total;        /* whole call on the stream                       */
+  int64_t narrow_levels;  /* final levels the triangular solves take in one
+                             workgroup (LDS, a barrier per level) instead of
+                             the dependency-driven sweep; 0 = none          */
 } parac_factor_stats;
 
 typedef struct parac_factor_s *parac_factor_t;

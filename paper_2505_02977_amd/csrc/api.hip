@@ -872,6 +872,7 @@ static parac_factor_t factor_impl(const parac_csr *A, const parac_factor_opts *o
   S.ms_eliminate = ms_elim;
   S.ms_finalize = ev.ms(3, 4);
   S.ms_total = ev.ms(0, 4);
+  S.narrow_levels = F->nf.nlev;
 
   // keep the handle's arrays; everything else is freed with `tmp`
   for (void *p : {(void *)F->perm, (void *)F->iperm, (void *)F->colptr, (void *)F->rowind,

@@ -46,7 +46,7 @@ class parac_factor_stats(C.Structure):
                 ("n_zero_pivots", C.c_int64), ("workers", C.c_int32), ("retries", C.c_int32),
                 ("pool_factor", C.c_double), ("ms_setup", C.c_double),
                 ("ms_eliminate", C.c_double), ("ms_finalize", C.c_double),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("narrow_levels", C.c_int64)]
 
 
 class parac_pcg_opts(C.Structure):
