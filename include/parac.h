@@ -163,10 +163,13 @@ parac_status parac_factor_export(parac_factor_t f, int64_t *colptr,
  * The forward solve F y = P r and the backward solve F^T x = D^+ y follow
  * the elimination levels (a row depends only on rows of earlier levels).
  * Two sweeps, each a single launch in which every row starts as soon as the
- * rows it reads are solved; with nrhs > 1, chunks of up to 64 columns run as
- * sweep slots of several columns each in the same two launches (the factor
- * read once per slot; see parac_block_shape_set for the shape and how it is
- * chosen).
+ * rows it reads are solved.  For one column, the factor's final levels of
+ * few rows (parac_factor_stats.narrow_levels) are left to one workgroup
+ * (values in LDS, a barrier per level), launched between the two sweeps with
+ * a pre-pass; each row's sum keeps the sweeps' association.  With nrhs > 1,
+ * chunks of up to 64 columns run as sweep slots of several columns each in
+ * the same two launches (the factor read once per slot; see
+ * parac_block_shape_set for the shape and how it is chosen).
  * Every column equals, bit for bit, the apply of that column alone.
  * The call returns after the result is complete.  Errors: EINVAL, ETIMEOUT
  * (a sweep's watchdog expired; the factor stays usable). */
