@@ -13,7 +13,9 @@
 // A wave only waits on rows whose units hold smaller tickets, i.e. were
 // claimed by waves that are already running, so the sweep always advances.
 // Every wait is bounded by a wall-clock watchdog that records an error
-// instead of hanging.
+// instead of hanging.  The final levels of few rows, when a factor has a
+// long enough run of them, are not the sweeps' but k_narrow's: one workgroup
+// per slot, launched between the two sweeps (see "Narrow levels" below).
 //
 // The arithmetic of a row: start value minus the sum of its products, the
 // sum taken as a balanced binary tree whose shape depends only on the row's
