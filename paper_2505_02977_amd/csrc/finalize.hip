@@ -9,16 +9,21 @@ namespace parac {
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
 
+// lanes per column in the column copies below, so that a column's reads and
+// writes are contiguous
+constexpr int kColLanes = 16;
+
 __global__ void k_compact_csc(int64_t ntot, const int64_t *__restrict__ colstart,
                               const int32_t *__restrict__ colcnt, const int32_t *__restrict__ frow,
                               const double *__restrict__ fval, const int64_t *__restrict__ colptr,
                               int32_t *rowind, double *val) {
-  // one wave per 64 columns; each lane copies one column
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = t / kColLanes;
+  const int q = (int)(t % kColLanes);
   if (k >= ntot) return;
-  int64_t s = colstart[k], o = colptr[k];
-  int c = colcnt[k];
-  for (int e = 0; e < c; ++e) {
+  const int64_t s = colstart[k], o = colptr[k];
+  const int c = colcnt[k];
+  for (int e = q; e < c; e += kColLanes) {
     rowind[o + e] = frow[s + e];
     val[o + e] = fval[s + e];
   }
@@ -27,8 +32,8 @@ __global__ void k_compact_csc(int64_t ntot, const int64_t *__restrict__ colstart
 hipError_t launch_compact_csc(int64_t ntot, const int64_t *colstart, const int32_t *colcnt,
                               const int32_t *frow, const double *fval, const int64_t *colptr,
                               int32_t *rowind, double *val, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact_csc, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, colstart, colcnt,
-                     frow, fval, colptr, rowind, val);
+  hipLaunchKernelGGL(k_compact_csc, dim3(nblk(ntot * kColLanes, 256)), dim3(256), 0, s, ntot,
+                     colstart, colcnt, frow, fval, colptr, rowind, val);
   return hipGetLastError();
 }
 
@@ -47,9 +52,12 @@ __global__ void k_transpose(int64_t ntot, const int64_t *__restrict__ colptr,
                             const int32_t *__restrict__ rowind, const double *__restrict__ val,
                             const int64_t *__restrict__ rowptr_f, int32_t *cursor,
                             int32_t *colind_f, double *val_f) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the order within a row is arbitrary here; k_sort_rows sorts it
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = t / kColLanes;
+  const int q = (int)(t % kColLanes);
   if (k >= ntot) return;
-  for (int64_t e = colptr[k]; e < colptr[k + 1]; ++e) {
+  for (int64_t e = colptr[k] + q; e < colptr[k + 1]; e += kColLanes) {
     int32_t i = rowind[e];
     int64_t pos = rowptr_f[i] + atomicAdd(&cursor[i], 1);
     colind_f[pos] = (int32_t)k;
@@ -60,8 +68,8 @@ __global__ void k_transpose(int64_t ntot, const int64_t *__restrict__ colptr,
 hipError_t launch_transpose(int64_t ntot, const int64_t *colptr, const int32_t *rowind,
                             const double *val, const int64_t *rowptr_f, int32_t *cursor,
                             int32_t *colind_f, double *val_f, hipStream_t s) {
-  hipLaunchKernelGGL(k_transpose, dim3(nblk(ntot, 256)), dim3(256), 0, s, ntot, colptr, rowind, val,
-                     rowptr_f, cursor, colind_f, val_f);
+  hipLaunchKernelGGL(k_transpose, dim3(nblk(ntot * kColLanes, 256)), dim3(256), 0, s, ntot, colptr,
+                     rowind, val, rowptr_f, cursor, colind_f, val_f);
   return hipGetLastError();
 }
 
