@@ -131,8 +131,10 @@ def rl_entry(name, nbytes, ms, traffic=None):
 
 
 def roofline(info, timing, elem, workload):
-    """The dominant single kernel of a step (by time) against the HBM peak,
-    with the other kernels of the hot path beside it."""
+    """The dominant part of a step (by time) against the HBM peak: the
+    elimination's one launch, or a sweep (its dependency-driven launch, plus
+    the narrow-level launches when the factor has them), with the other parts
+    of the hot path beside it."""
     N, n_off = info["n"], info["nnz_off"]
     T = "double" if elem == 8 else "float"
     # a sweep is the dependency-driven launch plus, when the factor has narrow
